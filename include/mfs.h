@@ -1,0 +1,225 @@
+/*
+ * mfs.h -- C ABI of the MI355X (gfx950) mixed-FEM skinning solver.
+ *
+ * The library computes, for one rig pose, the deformed vertex positions of a
+ * tetrahedral character mesh by the mixed finite element method of "Automatic
+ * Skinning using the Mixed Finite Element Method" (Song et al.): per-element
+ * symmetric stretches S_k are tied to the vertex positions through rotations
+ * R_k fixed by the rig (Section 3, the mixed form and its constraint), vertices
+ * near the skeleton are pinned with a quadratic penalty whose targets follow
+ * their handle (Section 3, the constraint C(x); Section 3.2, "Initial shape
+ * preservation"), and the multipliers and stretches are condensed into a
+ * vertex-only symmetric positive definite system (Section 3, the condensed
+ * per-vertex system and the pseudo-inverse of [R]).  One frame is one pass of
+ * the loop of Algorithm 1: the rig pose sets [R], the system is assembled and
+ * solved.  For quadratic energies (ARAP, co-rotated linear) one solve is the
+ * optimum; for neo-Hookean the frame runs Newton iterations.
+ *
+ * Conventions (all entry points):
+ *   - Every call returns int: 0 = MFS_OK, > 0 = warning, < 0 = error.  The
+ *     text of the last error on the calling thread is mfs_last_error().
+ *   - Inputs are read during the call only; the library never keeps caller
+ *     pointers.  Output buffers are allocated by the caller.
+ *   - Pointers marked "host or device" follow the call's memory-space field:
+ *     MFS_MEM_HOST = ordinary host memory, MFS_MEM_DEVICE = device memory of
+ *     the context's GPU.
+ *   - Opaque handles are owned by the library and released by *_destroy.
+ *   - A context and everything made from it are used by one host thread at a
+ *     time.  All GPU work is enqueued on the context's stream; calls that
+ *     return results to the host synchronise that stream.
+ *   - Arrays are row-major; vertex positions are n x 3 doubles, rotations
+ *     are 3 x 3 row-major (9 doubles) mapping rest to posed space.
+ */
+#ifndef MFS_H
+#define MFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define MFS_OK 0
+#define MFS_W_NOT_CONVERGED 1   /* best iterate written; see mfs_solve_stats */
+#define MFS_E_INVALID (-1)      /* bad argument: index out of range, non-finite value,
+                                   nu outside (-1, 0.5), E <= 0, non-rotation handle */
+#define MFS_E_DEGENERATE (-2)   /* rest tet with |det Dm| <= 1e-12 * (mean edge)^3 */
+#define MFS_E_SINGULAR (-3)     /* pins cannot remove rigid motion (< 3 non-collinear) */
+#define MFS_E_OOM (-4)          /* device allocation failed */
+#define MFS_E_HIP (-5)          /* HIP runtime error */
+#define MFS_E_BUSY (-6)         /* serving queue full / workspace budget exhausted */
+#define MFS_E_UNSUPPORTED (-7)  /* option combination not implemented */
+
+/* ---- enumerations ---------------------------------------------------- */
+enum mfs_material {        /* per-element stretch energy Psi(S) */
+  MFS_ARAP = 0,            /* mu ||S - I||^2 */
+  MFS_COROT = 1,           /* mu ||S - I||^2 + lambda/2 tr(S - I)^2 */
+  MFS_NEOHOOKEAN = 2       /* mu/2 (tr(S S) - 3) - mu ln J + lambda/2 (ln J)^2, J = det S */
+};
+enum mfs_precision {
+  MFS_FP64 = 0,            /* every kernel in FP64 */
+  MFS_FP32_REFINED = 1     /* FP32 Hessian values and PCG; FP64 positions, stretches,
+                              gradient (residual), energies and updates */
+};
+enum mfs_memory { MFS_MEM_HOST = 0, MFS_MEM_DEVICE = 1 };
+enum mfs_warm_start {
+  MFS_WARM_REST = 0,       /* x0 = rest positions (Algorithm 1, x <- X) */
+  MFS_WARM_PREVIOUS = 1    /* x0 = this character's last solved positions */
+};
+
+typedef struct mfs_context mfs_context;
+typedef struct mfs_character mfs_character;
+
+/* ---- descriptors ----------------------------------------------------- */
+typedef struct mfs_mesh_desc {
+  int64_t n_vertices;              /* n >= 4 */
+  const double* rest_positions;    /* n x 3 rest positions X */
+  int64_t n_tets;                  /* m >= 1 */
+  const int32_t* tets;             /* m x 4 vertex indices (any orientation) */
+  const int32_t* material_model;   /* m, enum mfs_material */
+  const double* youngs;            /* m, Young's modulus E > 0 */
+  const double* poisson;           /* m, Poisson ratio in (-1, 0.5) */
+  int32_t n_handles;               /* rig handles, 1..256 */
+  const int32_t* tet_cluster;      /* m, handle whose rotation the tet takes */
+  int64_t n_pins;                  /* >= 3 */
+  const int32_t* pin_vertex;       /* n_pins vertex indices (repeats allowed) */
+  const int32_t* pin_handle;       /* n_pins handle indices */
+  double pin_stiffness;            /* k_s > 0 */
+  int32_t memory_space;            /* enum mfs_memory of the arrays above */
+} mfs_mesh_desc;
+
+typedef struct mfs_solve_opts {
+  int32_t precision;        /* enum mfs_precision */
+  int32_t max_newton;       /* iteration cap (the first, mixed step counts) */
+  int32_t fixed_newton;     /* 1: run exactly max_newton iterations */
+  double step_tol;          /* stop when max_v ||alpha dx_v|| <= step_tol * bbox diagonal
+                               in a Newton-phase iteration */
+  double cg_tol;            /* PCG stop: ||r|| <= cg_tol ||b|| */
+  int32_t cg_max;           /* PCG iteration cap per solve */
+  int32_t warm_start;       /* enum mfs_warm_start */
+  int32_t output_memory;    /* enum mfs_memory of x_out */
+  int32_t reserved;
+} mfs_solve_opts;
+
+typedef struct mfs_solve_stats {
+  int32_t status;           /* return code of the solve */
+  int32_t iterations;       /* Newton iterations run, mixed steps included */
+  int32_t mixed_iterations; /* steps taken while s != J x */
+  int32_t cg_iterations;    /* PCG iterations summed over the frame */
+  int32_t halvings;         /* line-search halvings summed over the frame */
+  int32_t clamped;          /* neo-Hookean elements with clamped Hessian, last iteration */
+  int32_t fp64_routed;      /* tets whose polar decomposition ran in FP64 (FP32 path) */
+  int32_t cg_not_converged; /* solves that hit cg_max */
+  double energy;            /* E(x) at the returned positions */
+  double grad_norm;         /* ||grad E|| at the last Newton-phase assembly */
+  double last_step;         /* max_v ||alpha dx_v|| of the last iteration */
+  double cg_rel_residual;   /* ||r|| / ||b|| of the last PCG solve */
+} mfs_solve_stats;
+
+/* ---- library and context --------------------------------------------- */
+
+/* Fill *opts with the defaults: FP64, max_newton 50, fixed_newton 0,
+ * step_tol 1e-10, cg_tol 1e-10, cg_max 20000, warm start REST, host output. */
+void mfs_default_opts(mfs_solve_opts* opts);
+
+/* Text for a status code (static storage). */
+const char* mfs_status_string(int status);
+
+/* Text of the last error reported on the calling thread ("" if none). */
+const char* mfs_last_error(void);
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * (e.g. the caller's current stream) or NULL for a stream owned by the
+ * context.  Every kernel and copy of this context is enqueued on it. */
+int mfs_context_create(int device, void* hip_stream, mfs_context** out);
+int mfs_context_destroy(mfs_context* ctx);
+
+/* ---- characters (resident per-mesh state) ----------------------------- */
+
+/* Copy a character to the device and precompute its rest data: the shape
+ * gradients Dm^-1 and volumes W_k (Section 3: F = B x and the element
+ * volumes of the discrete mixed energy), Lame parameters from (E, nu), the
+ * 3x3-block sparsity pattern of the condensed matrix and its
+ * element-to-block assembly map, and a bandwidth-reducing vertex order.
+ * Errors: MFS_E_INVALID, MFS_E_DEGENERATE, MFS_E_SINGULAR, MFS_E_OOM,
+ * MFS_E_HIP.  On error *out is NULL. */
+int mfs_character_create(mfs_context* ctx, const mfs_mesh_desc* desc, mfs_character** out);
+int mfs_character_destroy(mfs_character* ch);
+
+/* Device bytes the character keeps resident between frames (mesh data,
+ * assembly map, positions and stretches) and the bytes of its solve
+ * workspace (element state, matrix values, PCG vectors, reductions), for
+ * admission by memory footprint.  Either output may be NULL. */
+int mfs_character_footprint(const mfs_character* ch, size_t* resident_bytes,
+                            size_t* workspace_bytes);
+
+/* ---- rig helpers ------------------------------------------------------ */
+
+/* Rotation clusters (Section 3.1): each tet takes the handle of the bone
+ * segment nearest its barycenter; ties go to the lowest segment index, and a
+ * zero-length segment is a point handle.  X: n x 3, tets: m x 4, seg_a/seg_b:
+ * nseg x 3, seg_handle: nseg, out: m (all host or device per memory_space).
+ * Runs on the GPU of ctx; returns after out is written. */
+int mfs_cluster_by_segments(mfs_context* ctx, const double* X, int64_t n,
+                            const int32_t* tets, int64_t m, int32_t nseg,
+                            const double* seg_a, const double* seg_b,
+                            const int32_t* seg_handle, int32_t* out, int32_t memory_space);
+
+/* ---- solving ------------------------------------------------------------ */
+
+/* Solve one frame (Algorithm 1, one pose).  handle_R: n_handles x 9 and
+ * handle_t: n_handles x 3 on the host give each handle's rest->posed rigid
+ * transform; a tet in cluster h takes rotation R_h, and a pin on handle h
+ * targets R_h X_p + t_h.  x_out: n x 3 in the caller's vertex order, host or
+ * device per opts->output_memory.  stats may be NULL.  A rotation with
+ * ||R^T R - I|| > 1e-9 or det R <= 0 is MFS_E_INVALID.  Returns MFS_OK, or
+ * MFS_W_NOT_CONVERGED with the best iterate written when the line search
+ * fails or the iteration cap is hit before the step tolerance. */
+int mfs_solve_frame(mfs_character* ch, const double* handle_R, const double* handle_t,
+                    const mfs_solve_opts* opts, double* x_out, mfs_solve_stats* stats);
+
+/* Solve one frame for each of `count` characters of one context together:
+ * every kernel launch covers the tiles of all characters still iterating,
+ * with per-character scalars, convergence flags and reductions, so each
+ * character's result is the same as when it is solved alone.  R[i], t[i],
+ * x_out[i] as in mfs_solve_frame; stats: count entries or NULL.  Returns the
+ * most severe status over the batch. */
+int mfs_solve_batch(mfs_context* ctx, int32_t count, mfs_character* const* chars,
+                    const double* const* handle_R, const double* const* handle_t,
+                    const mfs_solve_opts* opts, double* const* x_out,
+                    mfs_solve_stats* stats);
+
+/* ---- evaluation entry points (parity checks) --------------------------- */
+
+/* At positions x (n x 3, caller order, host or device per memory_space) and
+ * the given pose, with s = J x (the condensed stretch, sym(R_k^T F_k)):
+ *   energy_out (1 double, host): E(x) = sum_k W_k Psi(S_k) + k_s/2 sum_p
+ *       ||x_p - (R_h X_p + t_h)||^2 (+inf if a neo-Hookean S_k is not
+ *       positive definite);
+ *   grad_out (n x 3, same memory space as x, or NULL): grad E(x);
+ *   stretch_out (m x 6, same space, or NULL): s_k = (S00,S11,S22,S12,S02,S01)
+ *       in the caller's tet order;
+ * and, if v and Kv_out are non-NULL, Kv_out = K v with K the assembled
+ * condensed matrix (Hessian of E, neo-Hookean clamp applied) in FP64. */
+int mfs_evaluate(mfs_character* ch, const double* handle_R, const double* handle_t,
+                 const double* x, const double* v, int32_t memory_space,
+                 double* energy_out, double* grad_out, double* stretch_out, double* Kv_out);
+
+/* Polar decomposition F = U P (U proper rotation, P symmetric) of `count`
+ * 3x3 matrices by Higham's scaled Newton iteration, as the solver's warm
+ * start uses it.  F, U: count x 9; P: count x 6 (S00,S11,S22,S12,S02,S01);
+ * sigma_min: count (smallest eigenvalue of P); precision MFS_FP32_REFINED
+ * runs FP32 and reroutes matrices with sigma_min < 1e-3 to FP64; routed:
+ * count bytes (1 = ran in FP64), or NULL.  Matrices with det F <= 0 get
+ * U = I, P = I, sigma_min = 0.  All buffers host or device per
+ * memory_space. */
+int mfs_polar(mfs_context* ctx, const double* F, int64_t count, int32_t precision,
+              double* U, double* P, double* sigma_min, uint8_t* routed, int32_t memory_space);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFS_H */

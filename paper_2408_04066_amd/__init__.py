@@ -1,0 +1,288 @@
+"""Python binding of ``libmfs`` (mixed-FEM skinning solve on MI355X, gfx950).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels behind the C ABI declared in ``include/mfs.h``.  PyTorch is used, when
+present, only for device buffers and the current HIP stream.  The library is
+loaded on first use; a missing build raises ``MfsUnavailable`` (there is no
+fallback implementation).
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["MfsError", "MfsUnavailable", "Context", "Character", "SolveOpts", "SolveStats",
+           "solve_batch", "lib", "EXPORTED", "ARAP", "COROT", "NEOHOOKEAN", "FP64", "FP32_REFINED",
+           "MEM_HOST", "MEM_DEVICE", "WARM_REST", "WARM_PREVIOUS"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmfs.so")
+
+OK, W_NOT_CONVERGED = 0, 1
+ARAP, COROT, NEOHOOKEAN = 0, 1, 2
+FP64, FP32_REFINED = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
+WARM_REST, WARM_PREVIOUS = 0, 1
+
+# Every function the header declares.
+EXPORTED = ("mfs_default_opts", "mfs_status_string", "mfs_last_error", "mfs_context_create",
+            "mfs_context_destroy", "mfs_character_create", "mfs_character_destroy",
+            "mfs_character_footprint", "mfs_cluster_by_segments", "mfs_solve_frame",
+            "mfs_solve_batch", "mfs_evaluate", "mfs_polar")
+
+
+class MfsUnavailable(ImportError):
+    pass
+
+
+class MfsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mfs error {code}: {msg}")
+        self.code = code
+
+
+c_i32, c_i64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("n_vertices", c_i64), ("rest_positions", c_vp), ("n_tets", c_i64), ("tets", c_vp),
+                ("material_model", c_vp), ("youngs", c_vp), ("poisson", c_vp),
+                ("n_handles", c_i32), ("tet_cluster", c_vp), ("n_pins", c_i64),
+                ("pin_vertex", c_vp), ("pin_handle", c_vp), ("pin_stiffness", c_dbl),
+                ("memory_space", c_i32)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("precision", c_i32), ("max_newton", c_i32), ("fixed_newton", c_i32),
+                ("step_tol", c_dbl), ("cg_tol", c_dbl), ("cg_max", c_i32), ("warm_start", c_i32),
+                ("output_memory", c_i32), ("reserved", c_i32)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("status", c_i32), ("iterations", c_i32), ("mixed_iterations", c_i32),
+                ("cg_iterations", c_i32), ("halvings", c_i32), ("clamped", c_i32),
+                ("fp64_routed", c_i32), ("cg_not_converged", c_i32), ("energy", c_dbl),
+                ("grad_norm", c_dbl), ("last_step", c_dbl), ("cg_rel_residual", c_dbl)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (loads it on first call)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise MfsUnavailable(f"{LIB_PATH} is not built; run `python -m paper_2408_04066_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    sig = {
+        "mfs_default_opts": (None, [P(SolveOpts)]),
+        "mfs_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "mfs_last_error": (ctypes.c_char_p, []),
+        "mfs_context_create": (ctypes.c_int, [ctypes.c_int, c_vp, P(c_vp)]),
+        "mfs_context_destroy": (ctypes.c_int, [c_vp]),
+        "mfs_character_create": (ctypes.c_int, [c_vp, P(MeshDesc), P(c_vp)]),
+        "mfs_character_destroy": (ctypes.c_int, [c_vp]),
+        "mfs_character_footprint": (ctypes.c_int, [c_vp, P(ctypes.c_size_t), P(ctypes.c_size_t)]),
+        "mfs_cluster_by_segments": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_i32, c_vp, c_vp,
+                                                   c_vp, c_vp, c_i32]),
+        "mfs_solve_frame": (ctypes.c_int, [c_vp, c_vp, c_vp, P(SolveOpts), c_vp, P(SolveStats)]),
+        "mfs_solve_batch": (ctypes.c_int, [c_vp, c_i32, c_vp, c_vp, c_vp, P(SolveOpts), c_vp,
+                                           P(SolveStats)]),
+        "mfs_evaluate": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),
+        "mfs_polar": (ctypes.c_int, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, c_vp, c_i32]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc, allow_warning=True):
+    if rc < 0 or (rc > 0 and not allow_warning):
+        raise MfsError(rc, lib().mfs_last_error().decode())
+    return rc
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(np.asarray(a), dtype=dtype)
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()   # torch tensor on the device
+
+
+def default_opts(**kw):
+    o = SolveOpts()
+    lib().mfs_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown solve option {k}")
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    """One GPU and one HIP stream.  ``stream``: "current" (torch's current
+    stream), None (a stream owned by the context) or a raw hipStream_t."""
+
+    def __init__(self, device=0, stream="current"):
+        raw = None
+        if stream == "current":
+            import torch
+            raw = torch.cuda.current_stream(device).cuda_stream
+        elif stream is not None:
+            raw = int(stream)
+        h = c_vp()
+        _check(lib().mfs_context_create(device, raw, ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().mfs_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def cluster_by_segments(self, X, T, seg_a, seg_b, seg_handle):
+        X = _host(X, np.float64)
+        T = _host(T, np.int32)
+        sa, sb = _host(seg_a, np.float64), _host(seg_b, np.float64)
+        sh = _host(seg_handle, np.int32)
+        out = np.empty(T.shape[0], dtype=np.int32)
+        _check(lib().mfs_cluster_by_segments(self.handle, _ptr(X), X.shape[0], _ptr(T), T.shape[0],
+                                             len(sh), _ptr(sa), _ptr(sb), _ptr(sh), _ptr(out), MEM_HOST))
+        return out
+
+    def polar(self, F, precision=FP64):
+        F = _host(F, np.float64).reshape(-1, 9)
+        c = F.shape[0]
+        U = np.empty((c, 9))
+        P = np.empty((c, 6))
+        s = np.empty(c)
+        routed = np.empty(c, dtype=np.uint8)
+        _check(lib().mfs_polar(self.handle, _ptr(F), c, precision, _ptr(U), _ptr(P), _ptr(s),
+                               _ptr(routed), MEM_HOST))
+        return U.reshape(c, 3, 3), P, s, routed
+
+
+class Character:
+    """A character resident on the context's GPU.
+
+    ``prob`` holds the arrays of a problem: ``X`` (n, 3), ``T`` (m, 4),
+    ``model``, ``youngs``, ``poisson`` (m,), ``n_handles``, ``pin_vertex``,
+    ``pin_handle``, ``pin_stiffness`` and either ``cluster`` (m,) or the bone
+    segments ``seg_a``, ``seg_b``, ``seg_handle`` (clusters are then computed
+    by the library's nearest-segment kernel).
+    """
+
+    def __init__(self, ctx, prob, cluster=None):
+        self.ctx = ctx
+        X = _host(prob["X"], np.float64)
+        T = _host(prob["T"], np.int32)
+        if cluster is None:
+            cluster = prob.get("cluster")
+        if cluster is None:
+            cluster = ctx.cluster_by_segments(X, T, prob["seg_a"], prob["seg_b"], prob["seg_handle"])
+        self.cluster = _host(cluster, np.int32)
+        keep = [X, T, _host(prob["model"], np.int32), _host(prob["youngs"], np.float64),
+                _host(prob["poisson"], np.float64), self.cluster,
+                _host(prob["pin_vertex"], np.int32), _host(prob["pin_handle"], np.int32)]
+        d = MeshDesc()
+        d.n_vertices, d.rest_positions = X.shape[0], _ptr(keep[0])
+        d.n_tets, d.tets = T.shape[0], _ptr(keep[1])
+        d.material_model, d.youngs, d.poisson = _ptr(keep[2]), _ptr(keep[3]), _ptr(keep[4])
+        d.n_handles = int(prob["n_handles"])
+        d.tet_cluster = _ptr(keep[5])
+        d.n_pins, d.pin_vertex, d.pin_handle = len(keep[6]), _ptr(keep[6]), _ptr(keep[7])
+        d.pin_stiffness = float(prob["pin_stiffness"])
+        d.memory_space = MEM_HOST
+        h = c_vp()
+        _check(lib().mfs_character_create(ctx.handle, ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+        self.n, self.m, self.n_handles = X.shape[0], T.shape[0], d.n_handles
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mfs_character_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def footprint(self):
+        r, w = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().mfs_character_footprint(self.handle, ctypes.byref(r), ctypes.byref(w)))
+        return r.value, w.value
+
+    def _pose(self, R, t):
+        R = _host(R, np.float64).reshape(self.n_handles, 9)
+        t = _host(t, np.float64).reshape(self.n_handles, 3)
+        return R, t
+
+    def solve(self, R, t, out=None, **opts):
+        """Solve one frame.  Returns (x, stats, rc); x is (n, 3) float64 in
+        ``out`` (a numpy array, or a CUDA torch tensor for device output) or
+        a new numpy array."""
+        R, t = self._pose(R, t)
+        if out is None:
+            out = np.empty((self.n, 3))
+        o = default_opts(**opts)
+        o.output_memory = MEM_HOST if isinstance(out, np.ndarray) else MEM_DEVICE
+        st = SolveStats()
+        rc = _check(lib().mfs_solve_frame(self.handle, _ptr(R), _ptr(t), ctypes.byref(o), _ptr(out),
+                                          ctypes.byref(st)))
+        return out, st.as_dict(), rc
+
+    def evaluate(self, R, t, x, v=None, want_grad=True, want_stretch=True):
+        """Energy, gradient, stretches and K v at positions x (host arrays)."""
+        R, t = self._pose(R, t)
+        x = _host(x, np.float64).reshape(self.n, 3)
+        E = ctypes.c_double()
+        g = np.empty((self.n, 3)) if want_grad else None
+        s = np.empty((self.m, 6)) if want_stretch else None
+        vv = _host(v, np.float64).reshape(self.n, 3) if v is not None else None
+        kv = np.empty((self.n, 3)) if v is not None else None
+        _check(lib().mfs_evaluate(self.handle, _ptr(R), _ptr(t), _ptr(x), _ptr(vv), MEM_HOST,
+                                  ctypes.byref(E), _ptr(g), _ptr(s), _ptr(kv)))
+        return {"energy": E.value, "grad": g, "stretch": s, "Kv": kv}
+
+
+def solve_batch(ctx, chars, poses, outs=None, **opts):
+    """Solve one frame for each character in one batched run.  ``poses`` is
+    a list of (R, t); returns (list of x, list of stats dicts, rc)."""
+    k = len(chars)
+    Rs, ts = [], []
+    for ch, (R, t) in zip(chars, poses):
+        R, t = ch._pose(R, t)
+        Rs.append(R)
+        ts.append(t)
+    if outs is None:
+        outs = [np.empty((ch.n, 3)) for ch in chars]
+    o = default_opts(**opts)
+    o.output_memory = MEM_HOST if isinstance(outs[0], np.ndarray) else MEM_DEVICE
+    arr = lambda vals: (c_vp * k)(*vals)
+    st = (SolveStats * k)()
+    rc = _check(lib().mfs_solve_batch(ctx.handle, k, arr([c.handle.value for c in chars]),
+                                      arr([_ptr(R) for R in Rs]), arr([_ptr(t) for t in ts]),
+                                      ctypes.byref(o), arr([_ptr(x) for x in outs]), st))
+    return outs, [s.as_dict() for s in st], rc

@@ -1,0 +1,170 @@
+// Shared device-side structures of the mixed-FEM skinning library (gfx950).
+//
+// Every kernel works on "tiles" of one system (one character's frame solve):
+// a workgroup of 256 threads takes one tile, loads its system descriptor with
+// scalar loads, and works on a contiguous range of vertices, tets or
+// matrix-block slots of that system.  A batch is just a longer tile list over
+// several descriptors, so one launch covers every character still iterating
+// and each character keeps its own scalars and reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mfs {
+
+constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
+constexpr int kTile = 256;       // vertices / tets / slots per tile
+constexpr int kMaxHandles = 256;
+constexpr int kNumTrials = 5;    // line-search step lengths evaluated per energy pass
+
+// Per-tile partial-result planes (index into SysDesc::part).
+enum PartSlot : int {
+  P_PQ = 0,      // p . K p
+  P_RZ0 = 1,     // r . z, even iterations
+  P_RZ1 = 2,     // r . z, odd iterations
+  P_RR = 3,      // r . r
+  P_BB = 4,      // b . b
+  P_SLOPE = 5,   // b . dx
+  P_DXMAX = 6,   // max_v |dx_v|
+  P_HMAX = 7,    // largest halving count of the mixed line search
+  P_INF0 = 8,    // infeasible element count per trial (kNumTrials planes)
+  P_E0 = 8 + kNumTrials,        // element energy per trial
+  P_PIN0 = 8 + 2 * kNumTrials,  // pin energy per trial
+  P_CLAMP = 8 + 3 * kNumTrials, // clamped neo-Hookean elements
+  P_ROUTED = 9 + 3 * kNumTrials, // warm-start polar decompositions re-run in FP64
+  P_COUNT = 10 + 3 * kNumTrials
+};
+
+// Per-system integer flags (SysDesc::flags).
+enum FlagSlot : int {
+  F_CG_DONE = 0,   // PCG converged
+  F_CG_ITERS = 1,  // PCG iterations at convergence
+  F_COUNT = 4
+};
+
+// Per-system control block, written by the host driver each iteration.
+struct Ctrl {
+  int32_t phase;     // 0: mixed phase (s != J x), 1: Newton phase (s = J x)
+  int32_t update_s;  // mixed phase: apply the stretch update this iteration
+  double alpha;      // accepted step length (0 = no update)
+  double trials[kNumTrials];  // step lengths evaluated by the energy pass
+};
+
+struct Tile {
+  int32_t sys;     // system (descriptor) index
+  int32_t begin;   // first vertex / tet / slot
+  int32_t end;     // one past the last
+  int32_t local;   // tile index within its system (partial-result column)
+};
+
+struct SysDesc {
+  int32_t n, m, nnzb, nh;
+  int32_t ntv, ntt, nts, ptile;   // tiles per system: vertex, tet, slot; partial stride
+  double ks;                      // pin stiffness
+  // resident (reordered) mesh data
+  const int4* tets;        // m
+  const double* G;         // 9 planes of m: G[(3r+c)*m + k] = (Dm_k^-1)[r][c]
+  const double* wmu;       // m: W_k mu_k
+  const double* wlam;      // m: W_k lambda_k
+  const int32_t* info;     // m: cluster | model << 16
+  const double* X;         // 3n rest positions
+  const int32_t* rowptr;   // n + 1
+  const int32_t* colidx;   // nnzb
+  const int32_t* slot_ptr; // nnzb + 1
+  const int32_t* contrib;  // 16 m: (tet << 4) | (a << 2) | b, grouped by slot
+  const int32_t* diag;     // n: slot of block (r, r)
+  const int32_t* vpin_ptr; // n + 1
+  const int32_t* vpin_h;   // pins grouped by vertex: their handles
+  // per-frame rig
+  const double* Rh;        // nh x 9
+  const double* th;        // nh x 3
+  // state (double)
+  double* x;     // 3n positions
+  double* s;     // 6 planes of m: mixed stretches
+  double* est;   // 16 planes of m: element state (W P, S^-1, coefficients)
+  double* b;     // 3n right-hand side (-grad)
+  double* dx;    // 3n step (double)
+  // state (precision T of the linear solve)
+  void* vals;    // 9 planes of nnzb
+  void* minv;    // 6 n: inverse diagonal blocks (symmetric)
+  void* r;
+  void* z;
+  void* p0;
+  void* p1;
+  void* q;
+  void* xc;      // PCG iterate
+  // reductions
+  double* part;  // P_COUNT planes of ptile
+  int32_t* flags;
+  double* red;   // P_COUNT per-system results
+};
+
+// Element-state planes (SysDesc::est), 16 planes of m doubles.
+enum EstSlot : int {
+  E_WP = 0,    // 6: W * dPsi/dS (linearised), rotated frame
+  E_TI = 6,    // 6: S_lin^-1 (neo-Hookean)
+  E_CI = 12,   // W mu (ARAP, co-rotated) or W mu / 2 (neo-Hookean)
+  E_C2 = 13,   // W lambda (co-rotated)
+  E_C3 = 14,   // W max(mu - lambda ln J, 0) / 2 (neo-Hookean)
+  E_C4 = 15    // W lambda (neo-Hookean)
+};
+
+// Workgroup -> tile map that keeps consecutive tiles on one XCD: workgroups
+// are dealt round-robin over the 8 XCDs, so workgroup b runs on XCD b % 8;
+// XCD j gets the j-th contiguous chunk of the tile list (neighbouring tiles
+// share vertex gathers and sit in that XCD's L2).
+__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
+  const int j = b & 7, i = b >> 3;
+  const int q = ntiles >> 3, rem = ntiles & 7;
+  return j * q + (j < rem ? j : rem) + i;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Fixed-order workgroup sum: butterfly within each wave, then the four wave
+// totals in order.  Every thread returns the same value.
+__device__ __forceinline__ double block_sum(double v, double* lds4) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds4[w] = v;
+  __syncthreads();
+  return ((lds4[0] + lds4[1]) + lds4[2]) + lds4[3];
+}
+
+__device__ __forceinline__ double block_max(double v, double* lds4) {
+  v = wave_max(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds4[w] = v;
+  __syncthreads();
+  return fmax(fmax(lds4[0], lds4[1]), fmax(lds4[2], lds4[3]));
+}
+
+// Sum of one partial plane over a system's tiles in a fixed order: lane l
+// adds tiles l, l + 64, ... in sequence, then the wave butterfly.  Every lane
+// of every wave returns the same value, independent of which workgroup asks.
+__device__ __forceinline__ double sys_sum(const double* plane, int count) {
+  double acc = 0.0;
+  for (int i = threadIdx.x & 63; i < count; i += 64) acc += plane[i];
+  return wave_sum(acc);
+}
+
+__device__ __forceinline__ double sys_max(const double* plane, int count) {
+  double acc = 0.0;
+  for (int i = threadIdx.x & 63; i < count; i += 64) acc = fmax(acc, plane[i]);
+  return wave_max(acc);
+}
+
+}  // namespace mfs

@@ -1,0 +1,104 @@
+// Host-side internals shared by the library's C++ translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mfs.h"
+#include "common.h"
+
+namespace mfs {
+
+int set_error(int code, const char* fmt, ...);
+void clear_error();
+
+#define MFS_HIP(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return ::mfs::set_error(MFS_E_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                              __LINE__);                                                       \
+  } while (0)
+
+#define MFS_TRY(expr)           \
+  do {                          \
+    int rc_ = (expr);           \
+    if (rc_ < 0) return rc_;    \
+  } while (0)
+
+// Owned device allocation.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  int alloc(size_t nbytes);              // exact size, old contents dropped
+  int reserve(size_t nbytes);            // grow-only
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Grow-only pinned host buffer.
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  PinnedBuf() = default;
+  PinnedBuf(const PinnedBuf&) = delete;
+  PinnedBuf& operator=(const PinnedBuf&) = delete;
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  int reserve(size_t nbytes);
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+}  // namespace mfs
+
+struct mfs_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int lpr = 8;                       // PCG lanes per block row
+  int cg_check = 16;                 // PCG iterations between convergence checks
+  // batch scratch
+  mfs::DevBuf desc, ctrl, flags, red, tiles, sys_ids, tmp;
+  mfs::PinnedBuf h_ctrl, h_flags, h_red, h_tiles, h_stage;
+};
+
+struct mfs_character {
+  mfs_context* ctx = nullptr;
+  int32_t n = 0, m = 0, nh = 0, nnzb = 0, npin = 0;
+  double ks = 0.0, bbox_diag = 0.0, lbar = 0.0;
+  std::vector<int32_t> perm;   // internal vertex -> caller vertex
+  std::vector<int32_t> tperm;  // internal tet -> caller tet
+  int ntv = 0, ntt = 0, nts = 0, ptile = 0;
+  bool has_solution = false;
+  // resident mesh data
+  mfs::DevBuf tets, G, wmu, wlam, info, X, rowptr, colidx, slot_ptr, contrib, diag, vpin_ptr, vpin_h, perm_d,
+      tperm_d;
+  // per-frame rig and solver state
+  mfs::DevBuf Rh, th, x, s, est, b, dx, vals, minv, r, z, p0, p1, q, xc, part, flags, red;
+  mfs::SysDesc desc;  // pointers above, host copy
+  size_t resident_bytes = 0, workspace_bytes = 0;
+};
+
+namespace mfs {
+
+// Driver entry used by mfs_solve_frame / mfs_solve_batch.
+int solve_systems(mfs_context* ctx, int count, mfs_character* const* chars, const double* const* R,
+                  const double* const* t, const mfs_solve_opts* opts, double* const* x_out, mfs_solve_stats* stats);
+
+int check_pose(const mfs_character* ch, const double* R, const double* t);
+int upload_pose(mfs_character* ch, const double* R, const double* t);
+
+}  // namespace mfs

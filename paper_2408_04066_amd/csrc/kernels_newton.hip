@@ -1,0 +1,411 @@
+// Newton-iteration kernels: mixed warm start, element pass, Schur-complement
+// assembly, line-search evaluations and updates.  All reductions are per
+// tile in a fixed order (no atomics); a finalize kernel folds each system's
+// tiles in a fixed order as well, so results do not depend on the batch.
+#include "common.h"
+#include "elem_math.h"
+#include "launch.h"
+
+namespace mfs {
+
+__device__ __forceinline__ void load_rot(const double* __restrict__ Rh, int h, double R[9]) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) R[i] = Rh[9 * h + i];
+}
+
+__device__ __forceinline__ void gather4(const double* __restrict__ x, int4 t, double out[4][3]) {
+  const int v[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) out[a][i] = x[3 * v[a] + i];
+}
+
+// ---------------------------------------------------------------------------
+// Mixed warm start: s0_k = stretch factor of the polar decomposition of
+// F_k(x0) (identity when det F <= 0).  FP32 mode runs the iteration in FP32
+// and re-routes tets whose smallest singular value is below 1e-3 to FP64;
+// the routed count goes to the P_ROUTED partial plane.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_warm_start(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
+                                                       int ntiles, int fp32) {
+  __shared__ double red[4];
+  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
+  const SysDesc& S = sd[t.sys];
+  const int k = t.begin + threadIdx.x;
+  double routed = 0.0;
+  if (k < t.end) {
+    double x[4][3], n[4][3], F[9];
+    gather4(S.x, S.tets[k], x);
+    load_grads(S.G, S.m, k, n);
+    deformation_gradient(x, n, F);
+    double U[9], P[6], sm;
+    bool done = false;
+    if (fp32) {
+      float Ff[9], Uf[9], Pf[6], smf;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Ff[i] = (float)F[i];
+      const bool ok = polar_newton<float>(Ff, Uf, Pf, &smf);
+      if (!ok || smf >= 1e-3f) {
+        done = true;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) P[i] = ok ? (double)Pf[i] : (i < 3 ? 1.0 : 0.0);
+      }
+    }
+    if (!done) {
+      polar_newton<double>(F, U, P, &sm);
+      routed = fp32 ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) S.s[(size_t)i * S.m + k] = P[i];
+  }
+  const double tot = block_sum(routed, red);
+  if (threadIdx.x == 0) S.part[P_ROUTED * S.ptile + t.local] = tot;
+}
+
+// ---------------------------------------------------------------------------
+// Element pass (per Newton iteration).  For each tet: F = sum_a x_a n_a^T,
+// condensed stretch sx = sym(R^T F), then the material linearised at
+// sl = s (mixed phase, the stored mixed variable) or sl = sx (Newton phase).
+// Writes the element state planes and, in the Newton phase, s = sx.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_element(const SysDesc* __restrict__ sd, const Ctrl* __restrict__ ctrl,
+                                                    const Tile* __restrict__ tiles, int ntiles) {
+  __shared__ double red[4];
+  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
+  const SysDesc& S = sd[t.sys];
+  const bool mixed = ctrl[t.sys].phase == 0;
+  const int k = t.begin + threadIdx.x;
+  double clamped = 0.0;
+  if (k < t.end) {
+    const size_t m = S.m;
+    const int info = S.info[k];
+    const int model = info >> 16;
+    double R[9], x[4][3], n[4][3], F[9], sx[6], sl[6];
+    load_rot(S.Rh, info & 0xffff, R);
+    gather4(S.x, S.tets[k], x);
+    load_grads(S.G, S.m, k, n);
+    deformation_gradient(x, n, F);
+    rotated_stretch(R, F, sx);
+    if (mixed) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) sl[i] = S.s[i * m + k];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        sl[i] = sx[i];
+        S.s[i * m + k] = sx[i];
+      }
+    }
+    double WP[6], T[6], c[4];
+    clamped = element_state(model, S.wmu[k], S.wlam[k], sl, sx, WP, T, c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) S.est[(E_WP + i) * m + k] = WP[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) S.est[(E_TI + i) * m + k] = T[i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) S.est[(E_CI + i) * m + k] = c[i];
+  }
+  const double tot = block_sum(clamped, red);
+  if (threadIdx.x == 0) S.part[P_CLAMP * S.ptile + t.local] = tot;
+}
+
+// ---------------------------------------------------------------------------
+// Assembly of the condensed system (eq. 12 read as a Newton increment):
+//   K = k_s P^T P + sum_k W_k J_k^T H_k J_k,  b = -grad C - sum_k W_k J_k^T g_k,
+// gathered per 3x3 block slot from the slot's list of (tet, a, b)
+// contributions (no atomics).  The diagonal slot of vertex r also adds the
+// pins of r, writes b_r and the inverse diagonal block (block Jacobi).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_assemble(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
+                                                     int ntiles) {
+  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
+  const SysDesc& S = sd[t.sys];
+  const int slot = t.begin + threadIdx.x;
+  if (slot >= t.end) return;
+  const size_t m = S.m;
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double f[3] = {0, 0, 0};
+  const int c0 = S.slot_ptr[slot], c1 = S.slot_ptr[slot + 1];
+  int row = -1;
+  bool diag = false;
+  for (int ci = c0; ci < c1; ++ci) {
+    const int code = S.contrib[ci];
+    const int k = code >> 4, a = (code >> 2) & 3, b = code & 3;
+    double n[4][3], R[9], Ti[6], c[4], Kt[9], K[9];
+    load_grads(S.G, S.m, k, n);
+    load_rot(S.Rh, S.info[k] & 0xffff, R);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) Ti[i] = S.est[(E_TI + i) * m + k];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c[i] = S.est[(E_CI + i) * m + k];
+    element_block(n[a], n[b], Ti, c, Kt);
+    rotate_block(R, Kt, K);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) acc[i] += K[i];
+    if (ci == c0) {
+      const int4 tv = S.tets[k];
+      const int v[4] = {tv.x, tv.y, tv.z, tv.w};
+      row = v[a];
+      diag = (a == b);
+    }
+    if (a == b) {
+      double WP[6], g[3];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) WP[i] = S.est[(E_WP + i) * m + k];
+      sym_mv(WP, n[a], g);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) f[i] += R[3 * i] * g[0] + R[3 * i + 1] * g[1] + R[3 * i + 2] * g[2];
+    }
+  }
+  if (diag) {
+    // pins of this vertex: stiffness k_s I each, target R_h X_r + t_h
+    double cnt = 0.0, ys[3] = {0, 0, 0};
+    for (int pi = S.vpin_ptr[row]; pi < S.vpin_ptr[row + 1]; ++pi) {
+      const int h = S.vpin_h[pi];
+      double R[9];
+      load_rot(S.Rh, h, R);
+      cnt += 1.0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        ys[i] += R[3 * i] * S.X[3 * row] + R[3 * i + 1] * S.X[3 * row + 1] + R[3 * i + 2] * S.X[3 * row + 2] +
+                 S.th[3 * h + i];
+    }
+    const double kc = S.ks * cnt;
+    acc[0] += kc;
+    acc[4] += kc;
+    acc[8] += kc;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) S.b[3 * row + i] = -f[i] - (kc * S.x[3 * row + i] - S.ks * ys[i]);
+    // inverse of the symmetrised diagonal block
+    double d6[6] = {acc[0], acc[4], acc[8], 0.5 * (acc[5] + acc[7]), 0.5 * (acc[2] + acc[6]),
+                    0.5 * (acc[1] + acc[3])};
+    double inv[6];
+    sym_inv(d6, sym_det(d6), inv);
+    T* mi = (T*)S.minv;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) mi[6 * row + i] = (T)inv[i];
+  }
+  T* vals = (T*)S.vals;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) vals[(size_t)i * S.nnzb + slot] = (T)acc[i];
+}
+
+// ---------------------------------------------------------------------------
+// Line search, Newton phase: element energies at x + alpha_i dx for the
+// trial step lengths of this pass, with neo-Hookean feasibility.
+// Mixed phase: the number of halvings h (0..41) each neo-Hookean tet needs
+// for s + 2^-h (sym(R^T F(x + dx)) - s) to be positive definite; the step is
+// the one needed by the worst tet (the positive-definite set is convex and
+// contains s, so every smaller step stays feasible).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_linesearch_tets(const SysDesc* __restrict__ sd,
+                                                            const Ctrl* __restrict__ ctrl,
+                                                            const Tile* __restrict__ tiles, int ntiles) {
+  __shared__ double red[4];
+  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
+  const SysDesc& S = sd[t.sys];
+  const Ctrl& C = ctrl[t.sys];
+  const int k = t.begin + threadIdx.x;
+  const bool valid = k < t.end;
+  double s0[6] = {0, 0, 0, 0, 0, 0}, s1[6] = {0, 0, 0, 0, 0, 0};
+  int model = 0;
+  double wmu = 0.0, wlam = 0.0;
+  if (valid) {
+    const int info = S.info[k];
+    model = info >> 16;
+    wmu = S.wmu[k];
+    wlam = S.wlam[k];
+    double R[9], x[4][3], d[4][3], n[4][3], F[9];
+    const int4 tv = S.tets[k];
+    load_rot(S.Rh, info & 0xffff, R);
+    load_grads(S.G, S.m, k, n);
+    gather4(S.x, tv, x);
+    gather4(S.dx, tv, d);
+    deformation_gradient(x, n, F);
+    rotated_stretch(R, F, s0);
+    deformation_gradient(d, n, F);
+    rotated_stretch(R, F, s1);
+  }
+  if (C.phase == 0) {
+    double h = 0.0;
+    if (valid && model == kNeoHookean) {
+      double sm[6], ds[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        sm[i] = S.s[(size_t)i * S.m + k];
+        ds[i] = (s0[i] + s1[i]) - sm[i];
+      }
+      double a = 1.0;
+      int hh = 0;
+      for (; hh <= 40; ++hh, a *= 0.5) {
+        double st[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) st[i] = sm[i] + a * ds[i];
+        if (sym_spd(st)) break;
+      }
+      h = (double)hh;
+    }
+    const double hm = block_max(h, red);
+    if (threadIdx.x == 0) S.part[P_HMAX * S.ptile + t.local] = hm;
+    return;
+  }
+#pragma unroll
+  for (int j = 0; j < kNumTrials; ++j) {
+    double e = 0.0, inf = 0.0;
+    if (valid) {
+      double st[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) st[i] = s0[i] + C.trials[j] * s1[i];
+      bool ok;
+      const double v = element_energy(model, wmu, wlam, st, &ok);
+      if (ok) e = v; else inf = 1.0;
+    }
+    const double es = block_sum(e, red);
+    const double is = block_sum(inf, red);
+    if (threadIdx.x == 0) {
+      S.part[(P_E0 + j) * S.ptile + t.local] = es;
+      S.part[(P_INF0 + j) * S.ptile + t.local] = is;
+    }
+  }
+}
+
+// Vertex part of the line search: b . dx, max_v |dx_v| and the pin energy
+// k_s/2 |x_r + alpha_i dx_r - (R_h X_r + t_h)|^2 at each trial step.
+__global__ __launch_bounds__(kBlock) void k_linesearch_verts(const SysDesc* __restrict__ sd,
+                                                             const Ctrl* __restrict__ ctrl,
+                                                             const Tile* __restrict__ tiles, int ntiles) {
+  __shared__ double red[4];
+  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
+  const SysDesc& S = sd[t.sys];
+  const Ctrl& C = ctrl[t.sys];
+  const int r = t.begin + threadIdx.x;
+  double slope = 0.0, dmax = 0.0, pe[kNumTrials];
+#pragma unroll
+  for (int j = 0; j < kNumTrials; ++j) pe[j] = 0.0;
+  if (r < t.end) {
+    double x[3], d[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      x[i] = S.x[3 * r + i];
+      d[i] = S.dx[3 * r + i];
+      slope += S.b[3 * r + i] * d[i];
+    }
+    dmax = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    for (int pi = S.vpin_ptr[r]; pi < S.vpin_ptr[r + 1]; ++pi) {
+      const int h = S.vpin_h[pi];
+      double R[9], y[3];
+      load_rot(S.Rh, h, R);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        y[i] = R[3 * i] * S.X[3 * r] + R[3 * i + 1] * S.X[3 * r + 1] + R[3 * i + 2] * S.X[3 * r + 2] + S.th[3 * h + i];
+#pragma unroll
+      for (int j = 0; j < kNumTrials; ++j) {
+        double e2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const double e = x[i] + C.trials[j] * d[i] - y[i];
+          e2 += e * e;
+        }
+        pe[j] += 0.5 * S.ks * e2;
+      }
+    }
+  }
+  const double ss = block_sum(slope, red);
+  const double dm = block_max(dmax, red);
+  if (threadIdx.x == 0) {
+    S.part[P_SLOPE * S.ptile + t.local] = ss;
+    S.part[P_DXMAX * S.ptile + t.local] = dm;
+  }
+#pragma unroll
+  for (int j = 0; j < kNumTrials; ++j) {
+    const double ps = block_sum(pe[j], red);
+    if (threadIdx.x == 0) S.part[(P_PIN0 + j) * S.ptile + t.local] = ps;
+  }
+}
+
+// Mixed-phase stretch update s <- s + alpha (sym(R^T F(x + dx)) - s), run
+// before the position update (it reads the old x).
+__global__ __launch_bounds__(kBlock) void k_update_s(const SysDesc* __restrict__ sd, const Ctrl* __restrict__ ctrl,
+                                                     const Tile* __restrict__ tiles, int ntiles) {
+  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
+  const SysDesc& S = sd[t.sys];
+  const Ctrl& C = ctrl[t.sys];
+  const int k = t.begin + threadIdx.x;
+  if (C.phase != 0 || C.update_s == 0 || k >= t.end) return;
+  const int info = S.info[k];
+  double R[9], x[4][3], n[4][3], F[9], sx[6];
+  const int4 tv = S.tets[k];
+  load_rot(S.Rh, info & 0xffff, R);
+  load_grads(S.G, S.m, k, n);
+  gather4(S.x, tv, x);
+  double d[4][3];
+  gather4(S.dx, tv, d);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) x[a][i] += d[a][i];
+  deformation_gradient(x, n, F);
+  rotated_stretch(R, F, sx);
+  const size_t m = S.m;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const double so = S.s[i * m + k];
+    S.s[i * m + k] = so + C.alpha * (sx[i] - so);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_update_x(const SysDesc* __restrict__ sd, const Ctrl* __restrict__ ctrl,
+                                                     const Tile* __restrict__ tiles, int ntiles) {
+  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
+  const SysDesc& S = sd[t.sys];
+  const double a = ctrl[t.sys].alpha;
+  const int r = t.begin + threadIdx.x;
+  if (r >= t.end || a == 0.0) return;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) S.x[3 * r + i] += a * S.dx[3 * r + i];
+}
+
+// Fold each system's partial planes over its tiles (fixed order).
+__global__ __launch_bounds__(64) void k_finalize(const SysDesc* __restrict__ sd, const int32_t* __restrict__ sys_ids) {
+  const SysDesc& S = sd[sys_ids[blockIdx.x]];
+  for (int p = 0; p < P_COUNT; ++p) {
+    const bool vert = (p == P_PQ || p == P_RZ0 || p == P_RZ1 || p == P_RR || p == P_BB || p == P_SLOPE ||
+                       p == P_DXMAX || (p >= P_PIN0 && p < P_PIN0 + kNumTrials));
+    const int cnt = vert ? S.ntv : S.ntt;
+    const double* plane = S.part + (size_t)p * S.ptile;
+    const double v = (p == P_DXMAX || p == P_HMAX) ? sys_max(plane, cnt) : sys_sum(plane, cnt);
+    if (threadIdx.x == 0) S.red[p] = v;
+  }
+}
+
+// ---- launchers ----
+void launch_warm_start(hipStream_t st, const SysDesc* sd, const Tile* tiles, int ntiles, int fp32) {
+  if (ntiles) hipLaunchKernelGGL(k_warm_start, dim3(ntiles), dim3(kBlock), 0, st, sd, tiles, ntiles, fp32);
+}
+void launch_element(hipStream_t st, const SysDesc* sd, const Ctrl* ctrl, const Tile* tiles, int ntiles) {
+  if (ntiles) hipLaunchKernelGGL(k_element, dim3(ntiles), dim3(kBlock), 0, st, sd, ctrl, tiles, ntiles);
+}
+void launch_assemble(hipStream_t st, const SysDesc* sd, const Tile* tiles, int ntiles, int fp32) {
+  if (!ntiles) return;
+  if (fp32)
+    hipLaunchKernelGGL(k_assemble<float>, dim3(ntiles), dim3(kBlock), 0, st, sd, tiles, ntiles);
+  else
+    hipLaunchKernelGGL(k_assemble<double>, dim3(ntiles), dim3(kBlock), 0, st, sd, tiles, ntiles);
+}
+void launch_linesearch(hipStream_t st, const SysDesc* sd, const Ctrl* ctrl, const Tile* tt, int ntt, const Tile* tv,
+                       int ntv) {
+  if (ntt) hipLaunchKernelGGL(k_linesearch_tets, dim3(ntt), dim3(kBlock), 0, st, sd, ctrl, tt, ntt);
+  if (ntv) hipLaunchKernelGGL(k_linesearch_verts, dim3(ntv), dim3(kBlock), 0, st, sd, ctrl, tv, ntv);
+}
+void launch_update(hipStream_t st, const SysDesc* sd, const Ctrl* ctrl, const Tile* tt, int ntt, const Tile* tv,
+                   int ntv) {
+  if (ntt) hipLaunchKernelGGL(k_update_s, dim3(ntt), dim3(kBlock), 0, st, sd, ctrl, tt, ntt);
+  if (ntv) hipLaunchKernelGGL(k_update_x, dim3(ntv), dim3(kBlock), 0, st, sd, ctrl, tv, ntv);
+}
+void launch_finalize(hipStream_t st, const SysDesc* sd, const int32_t* sys_ids, int nsys) {
+  if (nsys) hipLaunchKernelGGL(k_finalize, dim3(nsys), dim3(64), 0, st, sd, sys_ids);
+}
+
+}  // namespace mfs

@@ -1,0 +1,41 @@
+// Host-side launchers of the library's kernels (one per kernel family).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace mfs {
+
+// setup and helpers
+void launch_rest(hipStream_t st, const int4* tets, const double* X, const double* youngs, const double* poisson,
+                 int m, double det_tol, double* G, double* wmu, double* wlam, uint8_t* bad);
+void launch_cluster(hipStream_t st, const double* X, const int32_t* tets, int64_t m, int nseg, const double* sa,
+                    const double* sb, const int32_t* sh, int32_t* out);
+void launch_polar(hipStream_t st, const double* F, int64_t count, int fp32, double* U, double* P, double* smin,
+                  uint8_t* routed);
+void launch_gather_rows(hipStream_t st, const double* src, const int32_t* perm, int count, int width, double* dst);
+void launch_scatter_rows(hipStream_t st, const double* src, const int32_t* perm, int count, int width, double sign,
+                         double* dst);
+void launch_scatter_planes6(hipStream_t st, const double* planes, int m, const int32_t* tperm, double* dst);
+
+// Newton iteration
+void launch_warm_start(hipStream_t st, const SysDesc* sd, const Tile* tiles, int ntiles, int fp32);
+void launch_element(hipStream_t st, const SysDesc* sd, const Ctrl* ctrl, const Tile* tiles, int ntiles);
+void launch_assemble(hipStream_t st, const SysDesc* sd, const Tile* tiles, int ntiles, int fp32);
+void launch_linesearch(hipStream_t st, const SysDesc* sd, const Ctrl* ctrl, const Tile* tt, int ntt, const Tile* tv,
+                       int ntv);
+void launch_update(hipStream_t st, const SysDesc* sd, const Ctrl* ctrl, const Tile* tt, int ntt, const Tile* tv,
+                   int ntv);
+void launch_finalize(hipStream_t st, const SysDesc* sd, const int32_t* sys_ids, int nsys);
+
+// PCG
+void launch_cg_init(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32);
+void launch_cg_iter(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int it, double tol2, int fp32,
+                    int lpr);
+void launch_cg_finish(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32);
+void launch_spmv_plain(hipStream_t st, const int32_t* rowptr, const int32_t* colidx, const double* vals, int nnzb,
+                       int n, const double* v, double* y);
+
+}  // namespace mfs

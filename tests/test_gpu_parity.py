@@ -1,0 +1,211 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Every case builds seeded synthetic inputs, runs the library on the GPU and
+compares element by element with the oracle on the same inputs.
+Tolerances: FP64 frame solves within 1e-9 * bbox diagonal of the oracle's
+positions; FP32 + FP64 refinement within 1e-7 * bbox diagonal; per-element
+and assembled FP64 quantities within a relative 1e-12 of the oracle's (the
+two sides round in different orders); rotation clusters bit-exact.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import (ARAP, COROT, NH, beam, beam_pose, humanoid, random_pose, euler_xyz)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2408_04066_amd as mfs
+    c = mfs.Context(0)
+    yield c
+    c.close()
+
+
+def _mfs():
+    import paper_2408_04066_amd as mfs
+    return mfs
+
+
+def _small_humanoid(seed=21, tets=4000, bones=15):
+    return humanoid(seed, target_tets=tets, n_bones=bones)
+
+
+# --------------------------------------------------------------------------
+# helpers / standalone kernels
+# --------------------------------------------------------------------------
+def test_cluster_kernel_bit_exact(ctx):
+    for prob in (beam(), _small_humanoid()):
+        _say(f"cluster kernel: {prob['name']}")
+        ref = oracle.cluster_by_segments(prob["X"], prob["T"], prob["seg_a"], prob["seg_b"],
+                                         prob["seg_handle"])
+        got = ctx.cluster_by_segments(prob["X"], prob["T"], prob["seg_a"], prob["seg_b"],
+                                      prob["seg_handle"])
+        assert np.array_equal(ref, got)
+
+
+def test_polar_kernel_matches_oracle(ctx):
+    mfs = _mfs()
+    rng = np.random.default_rng(4)
+    F = rng.normal(size=(1000, 3, 3))
+    F[np.linalg.det(F) < 0, :, 0] *= -1.0
+    # near-singular and near-identity members
+    F[:20] = np.eye(3) + 1e-6 * rng.normal(size=(20, 3, 3))
+    Q = np.stack([euler_xyz(*rng.uniform(-3, 3, 3)) for _ in range(20)])
+    F[20:40] = Q @ np.diag([1.0, 0.5, 2e-4])
+    F[40:45] = -np.eye(3)        # det < 0: warm start falls back to identity
+    _say("polar kernel FP64")
+    U, P, smin, routed = ctx.polar(F, mfs.FP64)
+    Uo, Po = oracle.polar(F[45:])
+    assert np.allclose(U[45:], Uo, atol=1e-12)
+    assert np.allclose(P[45:], oracle.vech(Po), atol=1e-12 * np.abs(Po).max())
+    sig = np.linalg.svd(F[45:], compute_uv=False)
+    assert np.allclose(smin[45:], sig[:, 2], rtol=1e-9, atol=1e-13)
+    assert np.all(P[40:45] == np.array([1.0, 1, 1, 0, 0, 0]))
+    assert not routed.any()
+    _say("polar kernel FP32 with FP64 re-route")
+    U32, P32, smin32, routed32 = ctx.polar(F, mfs.FP32_REFINED)
+    r45 = routed32[45:].astype(bool)
+    assert np.all(r45[sig[:, 2] < 0.9e-3]) and not np.any(r45[sig[:, 2] > 1.1e-3])
+    assert routed32[20:40].all()               # sigma_min = 2e-4 -> FP64
+    assert np.allclose(P32[20:40], P[20:40], atol=1e-13)
+    far = ~routed32.astype(bool)
+    far[40:45] = False
+    scale = np.abs(P).max(axis=1)
+    assert np.max(np.abs(P32[far] - P[far]) / scale[far, None]) < 2e-6
+
+
+# --------------------------------------------------------------------------
+# element pass, assembly and SpMV against the oracle's Frame
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("which", ["beam", "humanoid"])
+def test_evaluate_matches_oracle(ctx, which):
+    mfs = _mfs()
+    if which == "beam":
+        prob = beam()
+        pose = beam_pose(prob)
+    else:
+        prob = _small_humanoid()
+        prob["model"] = np.array([(ARAP, COROT, NH)[k % 3] for k in range(len(prob["T"]))],
+                                 dtype=np.int32)
+        pose = random_pose(prob, 77, amp_deg=20.0)
+    fr = oracle.Frame(prob, pose)
+    rng = np.random.default_rng(1)
+    # a feasible deformed state near the rigidly skinned pose
+    x = oracle.solve_frame(prob, pose, iterations=1, frame=fr)["x"]
+    if not fr.feasible(x.reshape(-1)):
+        x = prob["X"].copy()
+    x = x + 1e-5 * prob["bbox_diag"] * rng.normal(size=x.shape)
+    assert fr.feasible(x.reshape(-1))
+    v = rng.normal(size=x.shape)
+    _say(f"evaluate: {which} n={fr.n} m={fr.m}")
+    ch = mfs.Character(ctx, prob)
+    assert np.array_equal(ch.cluster, fr.cluster)
+    out = ch.evaluate(*pose, x, v)
+    E = fr.energy(x.reshape(-1))
+    g = fr.gradient(x.reshape(-1)).reshape(-1, 3)
+    s = fr.stretch(x.reshape(-1))
+    Kv = (fr.hessian(s) @ v.reshape(-1)).reshape(-1, 3)
+    assert abs(out["energy"] - E) <= 1e-12 * abs(E)
+    assert np.max(np.abs(out["grad"] - g)) <= 1e-11 * np.abs(g).max()
+    assert np.max(np.abs(out["stretch"] - s)) <= 1e-13 * max(1.0, np.abs(s).max())
+    assert np.max(np.abs(out["Kv"] - Kv)) <= 1e-12 * np.abs(Kv).max()
+    ch.close()
+
+
+# --------------------------------------------------------------------------
+# frame solves
+# --------------------------------------------------------------------------
+def _err(x, ref, prob):
+    return float(np.max(np.linalg.norm(x - ref, axis=1))) / prob["bbox_diag"]
+
+
+def test_beam_fp64_ten_iterations(ctx):
+    mfs = _mfs()
+    prob = beam()
+    pose = beam_pose(prob)
+    ref = oracle.solve_frame(prob, pose, iterations=10)
+    _say("solve: beam 16x4x4 neo-Hookean, FP64, 10 iterations, cg_tol 1e-10")
+    ch = mfs.Character(ctx, prob)
+    x, st, rc = ch.solve(*pose, max_newton=10, fixed_newton=1, cg_tol=1e-10)
+    _say(f"  stats {st}")
+    assert rc == 0 and st["iterations"] == 10
+    assert _err(x, ref["x"], prob) <= 1e-9
+    # the same solve twice is bitwise identical (fixed-order reductions)
+    x2, _, _ = ch.solve(*pose, max_newton=10, fixed_newton=1, cg_tol=1e-10)
+    assert np.array_equal(x, x2)
+    ch.close()
+
+
+@pytest.mark.parametrize("model", [ARAP, COROT, NH])
+def test_rest_and_rigid_invariants(ctx, model):
+    mfs = _mfs()
+    prob = beam(8, 2, 2, model=model, pin_stiffness=3e3)
+    ch = mfs.Character(ctx, prob)
+    _say(f"solve: rest pose, model {model}")
+    x, st, rc = ch.solve(np.stack([np.eye(3)] * 2), np.zeros((2, 3)))
+    assert rc == 0
+    assert np.max(np.abs(x - prob["X"])) <= 1e-14 * prob["bbox_diag"]
+    Q = euler_xyz(0.9, -0.6, 2.1)
+    c = np.array([3.0, -1.0, 2.0])
+    _say(f"solve: rigid pose, model {model}")
+    x, st, rc = ch.solve(np.stack([Q, Q]), np.stack([c, c]), cg_tol=1e-12, step_tol=1e-13,
+                         max_newton=10)
+    assert rc == 0
+    assert np.max(np.abs(x - (prob["X"] @ Q.T + c))) <= 1e-11 * prob["bbox_diag"]
+    ch.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-9), (1, 1e-7)])
+def test_humanoid_frame(ctx, precision, tol):
+    mfs = _mfs()
+    prob = _small_humanoid(21, 4000, 15)
+    pose = random_pose(prob, 22)
+    ref = oracle.solve_frame(prob, pose)
+    assert ref["status"] == "ok"
+    _say(f"solve: humanoid m={len(prob['T'])} precision={precision}")
+    ch = mfs.Character(ctx, prob)
+    kw = dict(precision=precision)
+    if precision == mfs.FP32_REFINED:
+        kw.update(cg_tol=1e-5, step_tol=1e-9)
+    x, st, rc = ch.solve(*pose, **kw)
+    _say(f"  stats {st}  err/bbox={_err(x, ref['x'], prob):.3e}")
+    assert rc == 0
+    assert _err(x, ref["x"], prob) <= tol
+    ch.close()
+
+
+def test_batch_equals_alone(ctx):
+    mfs = _mfs()
+    probs = [humanoid(100 + i, target_tets=t, n_bones=b, models=(NH, COROT))
+             for i, (t, b) in enumerate([(1500, 8), (3000, 12), (800, 10)])]
+    poses = [random_pose(p, 200 + i) for i, p in enumerate(probs)]
+    chars = [mfs.Character(ctx, p) for p in probs]
+    alone = []
+    for ch, pose in zip(chars, poses):
+        _say(f"solve alone: n={ch.n}")
+        x, st, rc = ch.solve(*pose, precision=mfs.FP32_REFINED, cg_tol=1e-5, step_tol=1e-9)
+        assert rc == 0
+        alone.append(x)
+    _say("solve batch of 3")
+    xs, sts, rc = mfs.solve_batch(ctx, chars, poses, precision=mfs.FP32_REFINED, cg_tol=1e-5,
+                                  step_tol=1e-9)
+    assert rc == 0
+    for a, b in zip(alone, xs):
+        assert np.array_equal(a, b)
+    for ch in chars:
+        ch.close()
