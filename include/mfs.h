@@ -191,6 +191,46 @@ int mfs_solve_batch(mfs_context* ctx, int32_t count, mfs_character* const* chars
                     const mfs_solve_opts* opts, double* const* x_out,
                     mfs_solve_stats* stats);
 
+/* ---- introspection and profiling ------------------------------------- */
+
+typedef struct mfs_character_info {
+  int64_t n_vertices, n_tets, n_blocks;  /* n, m, nonzero 3x3 blocks of K (both triangles) */
+  int64_t n_pins;
+  int32_t n_handles, reserved;
+  double bbox_diag;                      /* rest bounding-box diagonal */
+  double mean_edge;                      /* mean rest edge length */
+} mfs_character_info;
+
+/* Sizes of a created character. */
+int mfs_character_get_info(const mfs_character* ch, mfs_character_info* info);
+
+enum mfs_kernel_family {   /* kernel groups timed by the context profiler */
+  MFS_K_WARM_START = 0,    /* polar-decomposition warm start */
+  MFS_K_ELEMENT = 1,       /* per-element stretch, stress, Hessian state */
+  MFS_K_ASSEMBLE = 2,      /* Schur-complement assembly (3x3 blocks, RHS, block Jacobi) */
+  MFS_K_SPMV = 3,          /* PCG: search direction + block sparse matrix-vector product */
+  MFS_K_CG_UPDATE = 4,     /* PCG: iterate / residual / preconditioner update */
+  MFS_K_LINESEARCH = 5,    /* energy / feasibility evaluations */
+  MFS_K_UPDATE = 6,        /* position and stretch updates */
+  MFS_K_OTHER = 7,         /* PCG init/finish, reductions, permutations */
+  MFS_K_FAMILIES = 8
+};
+
+typedef struct mfs_profile {
+  double gpu_ms[MFS_K_FAMILIES];     /* summed HIP-event time of the timed launches */
+  int64_t timed[MFS_K_FAMILIES];     /* launches that were timed */
+  int64_t launches[MFS_K_FAMILIES];  /* all launches of the family */
+} mfs_profile;
+
+/* Time kernel launches of this context with HIP events on its stream:
+ * every `stride`-th launch of each family is bracketed by an event pair
+ * (stride 0 switches timing off and clears the counters). */
+int mfs_profile_enable(mfs_context* ctx, int32_t stride);
+
+/* Synchronise the context's stream, fold the pending event pairs and copy
+ * the counters; reset != 0 clears them afterwards. */
+int mfs_profile_read(mfs_context* ctx, mfs_profile* out, int32_t reset);
+
 /* ---- evaluation entry points (parity checks) --------------------------- */
 
 /* At positions x (n x 3, caller order, host or device per memory_space) and

@@ -28,7 +28,11 @@ WARM_REST, WARM_PREVIOUS = 0, 1
 EXPORTED = ("mfs_default_opts", "mfs_status_string", "mfs_last_error", "mfs_context_create",
             "mfs_context_destroy", "mfs_character_create", "mfs_character_destroy",
             "mfs_character_footprint", "mfs_cluster_by_segments", "mfs_solve_frame",
-            "mfs_solve_batch", "mfs_evaluate", "mfs_polar")
+            "mfs_solve_batch", "mfs_evaluate", "mfs_polar", "mfs_character_get_info",
+            "mfs_profile_enable", "mfs_profile_read")
+
+KERNEL_FAMILIES = ("warm_start", "element", "assemble", "spmv", "cg_update", "linesearch", "update",
+                   "other")
 
 
 class MfsUnavailable(ImportError):
@@ -68,6 +72,15 @@ class SolveStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class CharacterInfo(ctypes.Structure):
+    _fields_ = [("n_vertices", c_i64), ("n_tets", c_i64), ("n_blocks", c_i64), ("n_pins", c_i64),
+                ("n_handles", c_i32), ("reserved", c_i32), ("bbox_diag", c_dbl), ("mean_edge", c_dbl)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("gpu_ms", c_dbl * 8), ("timed", c_i64 * 8), ("launches", c_i64 * 8)]
+
+
 _lib = None
 
 
@@ -96,6 +109,9 @@ def lib():
                                            P(SolveStats)]),
         "mfs_evaluate": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),
         "mfs_polar": (ctypes.c_int, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, c_vp, c_i32]),
+        "mfs_character_get_info": (ctypes.c_int, [c_vp, P(CharacterInfo)]),
+        "mfs_profile_enable": (ctypes.c_int, [c_vp, c_i32]),
+        "mfs_profile_read": (ctypes.c_int, [c_vp, P(Profile), c_i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -159,6 +175,17 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def profile_enable(self, stride=1):
+        """Time every `stride`-th launch of each kernel family with HIP events
+        (0 = off)."""
+        _check(lib().mfs_profile_enable(self.handle, stride))
+
+    def profile_read(self, reset=False):
+        """{family: (gpu_ms, timed launches, all launches)}."""
+        p = Profile()
+        _check(lib().mfs_profile_read(self.handle, ctypes.byref(p), int(reset)))
+        return {f: (p.gpu_ms[i], p.timed[i], p.launches[i]) for i, f in enumerate(KERNEL_FAMILIES)}
 
     def cluster_by_segments(self, X, T, seg_a, seg_b, seg_handle):
         X = _host(X, np.float64)
@@ -228,6 +255,11 @@ class Character:
             self.close()
         except Exception:
             pass
+
+    def info(self):
+        i = CharacterInfo()
+        _check(lib().mfs_character_get_info(self.handle, ctypes.byref(i)))
+        return {name: getattr(i, name) for name, _ in i._fields_ if name != "reserved"}
 
     def footprint(self):
         r, w = ctypes.c_size_t(), ctypes.c_size_t()

@@ -64,6 +64,13 @@ struct PinnedBuf {
 
 }  // namespace mfs
 
+namespace mfs {
+struct ProfPending {
+  int fam;
+  hipEvent_t a, b;
+};
+}  // namespace mfs
+
 struct mfs_context {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -73,6 +80,14 @@ struct mfs_context {
   // batch scratch
   mfs::DevBuf desc, ctrl, flags, red, tiles, sys_ids, tmp;
   mfs::PinnedBuf h_ctrl, h_flags, h_red, h_tiles, h_stage;
+  // HIP-event profiler (mfs_profile_enable)
+  int prof_stride = 0;
+  double prof_ms[MFS_K_FAMILIES] = {};
+  int64_t prof_timed[MFS_K_FAMILIES] = {};
+  int64_t prof_launches[MFS_K_FAMILIES] = {};
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<mfs::ProfPending> pending;
+  ~mfs_context();
 };
 
 struct mfs_character {
@@ -99,6 +114,18 @@ int solve_systems(mfs_context* ctx, int count, mfs_character* const* chars, cons
                   const double* const* t, const mfs_solve_opts* opts, double* const* x_out, mfs_solve_stats* stats);
 
 int check_pose(const mfs_character* ch, const double* R, const double* t);
+
+// Brackets one launch group of kernel family `fam` with an event pair when
+// the context profiler samples it.
+struct ProfScope {
+  mfs_context* c;
+  int fam;
+  hipEvent_t a = nullptr;
+  ProfScope(mfs_context* ctx, int family);
+  ~ProfScope();
+};
+// Fold completed event pairs into the counters (call after a stream sync).
+void prof_resolve(mfs_context* c);
 int upload_pose(mfs_character* ch, const double* R, const double* t);
 
 }  // namespace mfs

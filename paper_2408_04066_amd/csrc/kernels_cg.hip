@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_plain(const int32_t* __restrict
 
 // ---- launchers ----
 template <typename T>
-static void cg_iter_t(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int it, double tol2, int lpr) {
+static void cg_spmv_t(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int it, double tol2, int lpr) {
   switch (lpr) {
     case 4:
       hipLaunchKernelGGL((k_cg_spmv<T, 4>), dim3(ntv), dim3(kBlock), 0, st, sd, tv, ntv, it, tol2);
@@ -230,7 +230,6 @@ static void cg_iter_t(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv
       hipLaunchKernelGGL((k_cg_spmv<T, 8>), dim3(ntv), dim3(kBlock), 0, st, sd, tv, ntv, it, tol2);
       break;
   }
-  hipLaunchKernelGGL(k_cg_update<T>, dim3(ntv), dim3(kBlock), 0, st, sd, tv, ntv, it);
 }
 
 void launch_cg_init(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32) {
@@ -241,13 +240,21 @@ void launch_cg_init(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, 
     hipLaunchKernelGGL(k_cg_init<double>, dim3(ntv), dim3(kBlock), 0, st, sd, tv, ntv);
 }
 
-void launch_cg_iter(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int it, double tol2, int fp32,
+void launch_cg_spmv(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int it, double tol2, int fp32,
                     int lpr) {
   if (!ntv) return;
   if (fp32)
-    cg_iter_t<float>(st, sd, tv, ntv, it, tol2, lpr);
+    cg_spmv_t<float>(st, sd, tv, ntv, it, tol2, lpr);
   else
-    cg_iter_t<double>(st, sd, tv, ntv, it, tol2, lpr);
+    cg_spmv_t<double>(st, sd, tv, ntv, it, tol2, lpr);
+}
+
+void launch_cg_update(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int it, int fp32) {
+  if (!ntv) return;
+  if (fp32)
+    hipLaunchKernelGGL(k_cg_update<float>, dim3(ntv), dim3(kBlock), 0, st, sd, tv, ntv, it);
+  else
+    hipLaunchKernelGGL(k_cg_update<double>, dim3(ntv), dim3(kBlock), 0, st, sd, tv, ntv, it);
 }
 
 void launch_cg_finish(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32) {

@@ -32,8 +32,9 @@ void launch_finalize(hipStream_t st, const SysDesc* sd, const int32_t* sys_ids, 
 
 // PCG
 void launch_cg_init(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32);
-void launch_cg_iter(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int it, double tol2, int fp32,
+void launch_cg_spmv(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int it, double tol2, int fp32,
                     int lpr);
+void launch_cg_update(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int it, int fp32);
 void launch_cg_finish(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32);
 void launch_spmv_plain(hipStream_t st, const int32_t* rowptr, const int32_t* colidx, const double* vals, int nnzb,
                        int n, const double* v, double* y);

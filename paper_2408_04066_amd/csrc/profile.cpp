@@ -1,0 +1,113 @@
+// Context profiler: sampled HIP-event pairs around kernel launch groups on
+// the context's stream, folded into per-family totals at stream syncs.
+#include <cstring>
+
+#include "internal.h"
+
+namespace mfs {
+
+static hipEvent_t get_event(mfs_context* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+ProfScope::ProfScope(mfs_context* ctx, int family) : c(ctx), fam(family) {
+  const int64_t k = c->prof_launches[fam]++;
+  if (c->prof_stride > 0 && k % c->prof_stride == 0) {
+    a = get_event(c);
+    if (a && hipEventRecord(a, c->stream) != hipSuccess) {
+      c->ev_pool.push_back(a);
+      a = nullptr;
+    }
+  }
+}
+
+ProfScope::~ProfScope() {
+  if (!a) return;
+  hipEvent_t b = get_event(c);
+  if (!b || hipEventRecord(b, c->stream) != hipSuccess) {
+    c->ev_pool.push_back(a);
+    if (b) c->ev_pool.push_back(b);
+    return;
+  }
+  c->pending.push_back(ProfPending{fam, a, b});
+}
+
+void prof_resolve(mfs_context* c) {
+  for (const ProfPending& p : c->pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->prof_ms[p.fam] += ms;
+      c->prof_timed[p.fam]++;
+    }
+    c->ev_pool.push_back(p.a);
+    c->ev_pool.push_back(p.b);
+  }
+  c->pending.clear();
+}
+
+}  // namespace mfs
+
+mfs_context::~mfs_context() {
+  for (const mfs::ProfPending& p : pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+}
+
+using namespace mfs;
+
+extern "C" int mfs_profile_enable(mfs_context* ctx, int32_t stride) {
+  clear_error();
+  if (!ctx || stride < 0) return set_error(MFS_E_INVALID, "null context or negative stride");
+  MFS_HIP(hipSetDevice(ctx->device));
+  MFS_HIP(hipStreamSynchronize(ctx->stream));
+  prof_resolve(ctx);
+  ctx->prof_stride = stride;
+  if (stride == 0) {
+    std::memset(ctx->prof_ms, 0, sizeof ctx->prof_ms);
+    std::memset(ctx->prof_timed, 0, sizeof ctx->prof_timed);
+    std::memset(ctx->prof_launches, 0, sizeof ctx->prof_launches);
+  }
+  return MFS_OK;
+}
+
+extern "C" int mfs_profile_read(mfs_context* ctx, mfs_profile* out, int32_t reset) {
+  clear_error();
+  if (!ctx || !out) return set_error(MFS_E_INVALID, "null argument");
+  MFS_HIP(hipSetDevice(ctx->device));
+  MFS_HIP(hipStreamSynchronize(ctx->stream));
+  prof_resolve(ctx);
+  for (int f = 0; f < MFS_K_FAMILIES; ++f) {
+    out->gpu_ms[f] = ctx->prof_ms[f];
+    out->timed[f] = ctx->prof_timed[f];
+    out->launches[f] = ctx->prof_launches[f];
+  }
+  if (reset) {
+    std::memset(ctx->prof_ms, 0, sizeof ctx->prof_ms);
+    std::memset(ctx->prof_timed, 0, sizeof ctx->prof_timed);
+    std::memset(ctx->prof_launches, 0, sizeof ctx->prof_launches);
+  }
+  return MFS_OK;
+}
+
+extern "C" int mfs_character_get_info(const mfs_character* ch, mfs_character_info* info) {
+  clear_error();
+  if (!ch || !info) return set_error(MFS_E_INVALID, "null argument");
+  std::memset(info, 0, sizeof *info);
+  info->n_vertices = ch->n;
+  info->n_tets = ch->m;
+  info->n_blocks = ch->nnzb;
+  info->n_pins = ch->npin;
+  info->n_handles = ch->nh;
+  info->bbox_diag = ch->bbox_diag;
+  info->mean_edge = ch->lbar;
+  return MFS_OK;
+}

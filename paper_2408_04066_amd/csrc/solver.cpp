@@ -129,6 +129,7 @@ int read_flags(mfs_context* ctx, int count) {
   MFS_HIP(hipMemcpyAsync(ctx->h_flags.p, ctx->flags.p, count * F_COUNT * sizeof(int32_t), hipMemcpyDeviceToHost,
                          ctx->stream));
   MFS_HIP(hipStreamSynchronize(ctx->stream));
+  prof_resolve(ctx);
   return MFS_OK;
 }
 
@@ -136,6 +137,7 @@ int read_red(mfs_context* ctx, int count) {
   MFS_HIP(hipMemcpyAsync(ctx->h_red.p, ctx->red.p, count * P_COUNT * sizeof(double), hipMemcpyDeviceToHost,
                          ctx->stream));
   MFS_HIP(hipStreamSynchronize(ctx->stream));
+  prof_resolve(ctx);
   return MFS_OK;
 }
 
@@ -210,8 +212,14 @@ int solve_systems(mfs_context* ctx, int count, mfs_character* const* chars, cons
   std::vector<int> tile_ids = ids;
 
   // mixed warm start s0 = stretch factor of F(x0)
-  launch_warm_start(st, dsd, ts.dt, ts.nt, fp32);
-  launch_finalize(st, dsd, ctx->sys_ids.as<int32_t>(), (int)ids.size());
+  {
+    ProfScope ps(ctx, MFS_K_WARM_START);
+    launch_warm_start(st, dsd, ts.dt, ts.nt, fp32);
+  }
+  {
+    ProfScope ps(ctx, MFS_K_OTHER);
+    launch_finalize(st, dsd, ctx->sys_ids.as<int32_t>(), (int)ids.size());
+  }
   MFS_HIP(hipGetLastError());
   MFS_TRY(read_red(ctx, count));
   for (int i = 0; i < count; ++i) sys[i].routed = (int)hr[P_COUNT * i + P_ROUTED];
@@ -232,16 +240,32 @@ int solve_systems(mfs_context* ctx, int count, mfs_character* const* chars, cons
       hc[i].alpha = 0.0;
     }
     MFS_TRY(upload_ctrl(ctx, count));
-    launch_element(st, dsd, dctrl, ts.dt, ts.nt);
-    launch_assemble(st, dsd, ts.ds, ts.ns, fp32);
-    launch_cg_init(st, dsd, ts.dv, ts.nv, fp32);
+    {
+      ProfScope ps(ctx, MFS_K_ELEMENT);
+      launch_element(st, dsd, dctrl, ts.dt, ts.nt);
+    }
+    {
+      ProfScope ps(ctx, MFS_K_ASSEMBLE);
+      launch_assemble(st, dsd, ts.ds, ts.ns, fp32);
+    }
+    {
+      ProfScope ps(ctx, MFS_K_OTHER);
+      launch_cg_init(st, dsd, ts.dv, ts.nv, fp32);
+    }
     MFS_HIP(hipGetLastError());
 
     // PCG with periodic convergence checks
     int cit = 0;
     while (cit < o.cg_max) {
       const int chunk = std::min(ctx->cg_check, o.cg_max - cit);
-      for (int j = 0; j < chunk; ++j, ++cit) launch_cg_iter(st, dsd, ts.dv, ts.nv, cit, tol2, fp32, ctx->lpr);
+      for (int j = 0; j < chunk; ++j, ++cit) {
+        {
+          ProfScope ps(ctx, MFS_K_SPMV);
+          launch_cg_spmv(st, dsd, ts.dv, ts.nv, cit, tol2, fp32, ctx->lpr);
+        }
+        ProfScope ps(ctx, MFS_K_CG_UPDATE);
+        launch_cg_update(st, dsd, ts.dv, ts.nv, cit, fp32);
+      }
       MFS_HIP(hipGetLastError());
       MFS_TRY(read_flags(ctx, count));
       bool all = true;
@@ -256,7 +280,10 @@ int solve_systems(mfs_context* ctx, int count, mfs_character* const* chars, cons
         sys[i].cg_fail++;
       }
     }
-    launch_cg_finish(st, dsd, ts.dv, ts.nv, fp32);
+    {
+      ProfScope ps(ctx, MFS_K_OTHER);
+      launch_cg_finish(st, dsd, ts.dv, ts.nv, fp32);
+    }
 
     // line search, first pass: Newton systems evaluate E at {0, 1, 1/2, 1/4, 1/8}
     for (int i : act) {
@@ -275,8 +302,14 @@ int solve_systems(mfs_context* ctx, int count, mfs_character* const* chars, cons
         tile_ids = srch;
       }
       MFS_TRY(upload_ctrl(ctx, count));
-      launch_linesearch(st, dsd, dctrl, ts.dt, ts.nt, ts.dv, ts.nv);
-      launch_finalize(st, dsd, ctx->sys_ids.as<int32_t>(), (int)srch.size());
+      {
+        ProfScope ps(ctx, MFS_K_LINESEARCH);
+        launch_linesearch(st, dsd, dctrl, ts.dt, ts.nt, ts.dv, ts.nv);
+      }
+      {
+        ProfScope ps(ctx, MFS_K_OTHER);
+        launch_finalize(st, dsd, ctx->sys_ids.as<int32_t>(), (int)srch.size());
+      }
       MFS_HIP(hipGetLastError());
       MFS_TRY(read_red(ctx, count));
       std::vector<int> next;
@@ -348,7 +381,10 @@ int solve_systems(mfs_context* ctx, int count, mfs_character* const* chars, cons
       tile_ids = act;
     }
     MFS_TRY(upload_ctrl(ctx, count));
-    launch_update(st, dsd, dctrl, ts.dt, ts.nt, ts.dv, ts.nv);
+    {
+      ProfScope ps(ctx, MFS_K_UPDATE);
+      launch_update(st, dsd, dctrl, ts.dt, ts.nt, ts.dv, ts.nv);
+    }
     MFS_HIP(hipGetLastError());
 
     for (int i : act) {
@@ -418,6 +454,7 @@ int solve_systems(mfs_context* ctx, int count, mfs_character* const* chars, cons
   }
   MFS_HIP(hipGetLastError());
   MFS_HIP(hipStreamSynchronize(st));
+  prof_resolve(ctx);
   if (stats) {
     for (int i = 0; i < count; ++i) {
       mfs_solve_stats& s = stats[i];
