@@ -1,19 +1,26 @@
 """Benchmark of the mixed-FEM skinning frame solve on one MI355X.
 
-Workload (default): a seeded procedural humanoid of ~50k tets / ~10k
-vertices with 20 bone handles, neo-Hookean or ARAP per limb (E log-uniform in
-[1e4, 1e6], nu uniform in [0.3, 0.49]); each step solves one frame at a fresh
-random pose (joint Euler angles uniform in +-45 degrees) from the rest shape.
+Default workload (``--workload c2``): a seeded procedural humanoid of ~50k
+tets / ~10k vertices with 20 bone handles, neo-Hookean or ARAP per limb
+(E log-uniform in [1e4, 1e6], nu uniform in [0.3, 0.49]); each step solves
+one frame at a fresh random pose (joint Euler angles uniform in +-45 degrees)
+from the rest shape.  ``c1`` is the 16x4x4 neo-Hookean beam, ``c3`` the same
+humanoid generator at ~500k tets / 30 handles, ``c4`` a batch of 64 humanoids
+of 5k-200k tets (log-uniform), 8-30 handles, neo-Hookean / co-rotated per
+limb, solved together in one batched run per step.
+
 The timed path is the FP32 + FP64-refinement form (FP32 Hessian values and
-PCG; FP64 residual, energies and updates) run to a 1e-8 * bbox step
-tolerance; the plain FP64 solve of the same poses is timed beside it and the
-two results are compared.  The character is resident in HBM before timing;
-each step uploads only the handle transforms and writes positions to a
-device tensor.
+PCG; FP64 residual, energies and updates), inexact Newton (Eisenstat-Walker
+forcing over a 1e-5 PCG floor), stopped at a 1e-8 * bbox Newton step.  The
+FP64 form of the same solve (identical options, FP64 Hessian and PCG) runs
+beside it on the first poses and the two results are compared.  Characters
+are resident in HBM before timing; a step uploads only handle transforms
+and writes positions to device tensors.
 
 Prints one JSON line: throughput in tet * Newton-iterations / s, frames/s,
 p50/p99 frame latency, the roofline entry of the dominant kernel (the PCG
-block-sparse matrix-vector product, HIP-event timed inside the timed region)
+block-sparse matrix-vector product; algorithmic bytes over HIP-event time,
+measured in a second pass over the same frames with the event profiler on)
 and the FP64 CPU oracle timed on this host on a bounded sample.
 """
 
@@ -31,24 +38,22 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def spmv_bytes(n, nnzb, word):
-    """Algorithmic bytes of one PCG SpMV launch: every block value and column
-    index once, the row pointers, and per row the search-direction inputs z
-    and p_prev (gathered once), the new p and q written."""
-    return nnzb * (9 * word + 4) + (n + 1) * 4 + n * 3 * word * 4
-
-
 def make_workload(name):
-    from workloads import humanoid, random_pose, beam, beam_pose
-    if name == "c2":
-        prob = humanoid(2001, target_tets=50000, n_bones=20)
-        return prob, (lambda i: random_pose(prob, 2002 + i)), "humanoid_50k_tets_20_handles_random_pose"
+    """(problems, pose_of(step) -> list of poses, workload name)."""
+    from workloads import NH, COROT, humanoid, random_pose, beam, beam_pose, character_pool
     if name == "c1":
-        prob = beam()
-        return prob, (lambda i: beam_pose(prob)), "beam_16x4x4_neohookean_twist30_stretch2"
+        p = beam()
+        return [p], (lambda i: [beam_pose(p)]), "beam_16x4x4_neohookean_twist30_stretch2"
+    if name == "c2":
+        p = humanoid(2001, target_tets=50000, n_bones=20)
+        return [p], (lambda i: [random_pose(p, 2002 + i)]), "humanoid_50k_tets_20_handles_random_pose"
     if name == "c3":
-        prob = humanoid(3001, target_tets=500000, n_bones=30)
-        return prob, (lambda i: random_pose(prob, 3002 + i)), "humanoid_500k_tets_30_handles_random_pose"
+        p = humanoid(3001, target_tets=500000, n_bones=30)
+        return [p], (lambda i: [random_pose(p, 3002 + i)]), "humanoid_500k_tets_30_handles_random_pose"
+    if name == "c4":
+        ps = character_pool(64, 4001, (5000, 200000), (8, 30), (NH, COROT))
+        return ps, (lambda i: [random_pose(p, 41000 + 100 * i + k) for k, p in enumerate(ps)]), \
+            "batch_64_humanoids_5k_200k_tets_8_30_handles"
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -66,16 +71,17 @@ def cpu_baseline(prob, pose, iterations=2):
     t1 = time.perf_counter()
     r = oracle.solve_frame(prob, pose, iterations=iterations, frame=fr)
     t2 = time.perf_counter()
-    if limiter is not None:
-        limiter.unregister() if hasattr(limiter, "unregister") else None
+    if limiter is not None and hasattr(limiter, "unregister"):
+        limiter.unregister()
     m = len(prob["T"])
     return {
         "value": m * r["iterations"] / (t2 - t1),
         "unit": "tet*Newton-iter/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"first {r['iterations']} Newton iterations of pose 0 ({m} tets), FP64 numpy/scipy "
-                   f"SuperLU, 1 thread; {t2 - t1:.1f} s solve + {t1 - t0:.1f} s setup (setup excluded)"),
+        "sample": (f"first {r['iterations']} Newton iterations of one frame of a {m}-tet character, "
+                   f"FP64 numpy/scipy SuperLU, 1 thread; {t2 - t1:.1f} s solve + {t1 - t0:.1f} s "
+                   f"setup (setup excluded)"),
     }
 
 
@@ -85,13 +91,14 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2")
-    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--profile-stride", type=int, default=8)
+    ap.add_argument("--roofline-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the frame solve of one character is not split "
-              "across GPUs in this build (see the sharding note in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: one character's frame solve is not split across "
+              "GPUs in this build (DESIGN.md describes how it would shard)", file=sys.stderr)
         return 2
     if int(os.environ.get("RANK", "0")) != 0:
         return 0
@@ -99,60 +106,73 @@ def main():
     import torch
     import paper_2408_04066_amd as mfs
 
-    prob, pose_of, wname = make_workload(args.workload)
+    probs, pose_of, wname = make_workload(args.workload)
     ctx = mfs.Context(0)
-    ch = mfs.Character(ctx, prob)
-    info = ch.info()
-    n, m, nnzb = info["n_vertices"], info["n_tets"], info["n_blocks"]
-    out = torch.empty((n, 3), dtype=torch.float64, device="cuda")
-    poses = [pose_of(i) for i in range(args.warmup + args.steps)]
-    fp32_opts = dict(precision=mfs.FP32_REFINED, cg_tol=1e-5, step_tol=1e-8, max_newton=60)
-    fp64_opts = dict(precision=mfs.FP64, cg_tol=1e-10, step_tol=1e-10, max_newton=60)
+    chars = [mfs.Character(ctx, p) for p in probs]
+    infos = [c.info() for c in chars]
+    m_tot = sum(i["n_tets"] for i in infos)
+    outs = [torch.empty((i["n_vertices"], 3), dtype=torch.float64, device="cuda") for i in infos]
+    steps = [pose_of(i) for i in range(args.warmup + args.steps)]
+    common = dict(cg_tol=1e-5, step_tol=1e-8, max_newton=60, cg_adaptive=1)
+    fp32_opts = dict(precision=mfs.FP32_REFINED, **common)
+    fp64_opts = dict(precision=mfs.FP64, **common)
+
+    def frame(poses, opts):
+        if len(chars) == 1:
+            _, st, rc = chars[0].solve(*poses[0], out=outs[0], **opts)
+            return [st], rc
+        _, sts, rc = mfs.solve_batch(ctx, chars, poses, outs=outs, **opts)
+        return sts, rc
 
     for i in range(args.warmup):
-        ch.solve(*poses[i], out=out, **fp32_opts)
+        frame(steps[i], fp32_opts)
     torch.cuda.synchronize()
 
-    # ---- timed region: FP32 + FP64 refinement ----
-    ctx.profile_enable(args.profile_stride)
-    ctx.profile_read(reset=True)
-    lat, iters, cgs, rcs, x32 = [], [], [], [], []
+    # ---- timed region: FP32 + FP64 refinement (PCG runs replayed as graphs) ----
+    lat, tet_iters, iters, cgs, rcs = [], 0, [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         ts = time.perf_counter()
-        _, st, rc = ch.solve(*poses[args.warmup + i], out=out, **fp32_opts)
+        sts, rc = frame(steps[args.warmup + i], fp32_opts)
         lat.append(time.perf_counter() - ts)
-        iters.append(st["iterations"])
-        cgs.append(st["cg_iterations"])
+        tet_iters += sum(inf["n_tets"] * st["iterations"] for inf, st in zip(infos, sts))
+        iters.append(np.mean([st["iterations"] for st in sts]))
+        cgs.append(np.mean([st["cg_iterations"] for st in sts]))
         rcs.append(rc)
-        if i < args.fp64_steps:
-            x32.append(out.cpu().numpy().copy())
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    total = time.perf_counter() - t0
+
+    # ---- roofline pass: the same frames with sampled HIP-event timing of
+    # every kernel family (direct launches; one event pair per timed launch) ----
+    x32 = []
+    ctx.profile_enable(args.profile_stride)
+    ctx.profile_read(reset=True)
+    for i in range(max(min(args.steps, args.roofline_steps), min(args.steps, args.fp64_steps))):
+        frame(steps[args.warmup + i], fp32_opts)
+        if i < args.fp64_steps:
+            x32.append([o.cpu().numpy().copy() for o in outs])
     prof = ctx.profile_read(reset=True)
     ctx.profile_enable(0)
-    total = t1 - t0
 
-    # ---- the plain FP64 solve of the first poses ----
-    lat64, iters64, err = [], [], []
+    # ---- the FP64 form of the same solve on the first poses ----
+    lat64, tet_iters64, err = [], 0, []
     for i in range(min(args.fp64_steps, args.steps)):
         torch.cuda.synchronize()
         ts = time.perf_counter()
-        _, st, rc = ch.solve(*poses[args.warmup + i], out=out, **fp64_opts)
+        sts, rc = frame(steps[args.warmup + i], fp64_opts)
         torch.cuda.synchronize()
         lat64.append(time.perf_counter() - ts)
-        iters64.append(st["iterations"])
-        x64 = out.cpu().numpy()
-        err.append(float(np.max(np.linalg.norm(x32[i] - x64, axis=1))) / info["bbox_diag"])
+        tet_iters64 += sum(inf["n_tets"] * st["iterations"] for inf, st in zip(infos, sts))
+        for o, a, inf in zip(outs, x32[i], infos):
+            err.append(float(np.max(np.linalg.norm(a - o.cpu().numpy(), axis=1))) / inf["bbox_diag"])
 
-    spmv_ms, spmv_timed, spmv_launches = prof["spmv"]
-    avg_spmv_s = spmv_ms / max(spmv_timed, 1) / 1e3
-    bytes_per_launch = spmv_bytes(n, nnzb, 4)
-    achieved = bytes_per_launch / avg_spmv_s / 1e9 if avg_spmv_s > 0 else None
+    spmv_ms, spmv_timed, spmv_launches, spmv_bytes = prof["spmv"]
+    achieved = spmv_bytes / (spmv_ms * 1e-3) / 1e9 if spmv_ms > 0 else None
+    nchar = len(chars)
     result = {
         "metric": "tet*Newton-iter/s (frames/s at 1e-7 rel err; p50/p99 frame latency)",
-        "value": m * sum(iters) / total,
+        "value": tet_iters / total,
         "unit": "tet*Newton-iter/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -163,21 +183,23 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "frames_per_s": args.steps / total,
+        "frames_per_s": nchar * args.steps / total,
         "latency_ms_p50": 1e3 * float(np.percentile(lat, 50)),
         "latency_ms_p99": 1e3 * float(np.percentile(lat, 99)),
         "newton_iters_per_frame": float(np.mean(iters)),
         "cg_iters_per_frame": float(np.mean(cgs)),
-        "status_codes": sorted(set(rcs)),
+        "status_codes": sorted(set(int(r) for r in rcs)),
         "fp64": {
-            "frames_per_s": len(lat64) / sum(lat64) if lat64 else None,
-            "tet_newton_iter_per_s": m * sum(iters64) / sum(lat64) if lat64 else None,
-            "newton_iters_per_frame": float(np.mean(iters64)) if iters64 else None,
+            "frames_per_s": nchar * len(lat64) / sum(lat64) if lat64 else None,
+            "tet_newton_iter_per_s": tet_iters64 / sum(lat64) if lat64 else None,
             "max_rel_diff_fp32_vs_fp64": max(err) if err else None,
         },
-        "config": {"workload": wname, "tets": m, "vertices": n, "blocks": nnzb,
-                   "handles": info["n_handles"], "precision": "fp32 pcg + fp64 refinement",
-                   "cg_tol": fp32_opts["cg_tol"], "step_tol_bbox": fp32_opts["step_tol"]},
+        "config": {"workload": wname, "characters": nchar, "tets": m_tot,
+                   "vertices": sum(i["n_vertices"] for i in infos),
+                   "blocks": sum(i["n_blocks"] for i in infos),
+                   "handles": [i["n_handles"] for i in infos] if nchar > 1 else infos[0]["n_handles"],
+                   "precision": "fp32 pcg + fp64 refinement", "cg_tol_floor": common["cg_tol"],
+                   "cg_forcing": "eisenstat-walker", "step_tol_bbox": common["step_tol"]},
         "roofline": {
             "bound": "hbm",
             "kernel": "k_cg_spmv<float>",
@@ -186,19 +208,21 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
             "traffic": None,
-            "bytes_per_launch": bytes_per_launch,
-            "avg_launch_us": avg_spmv_s * 1e6,
+            "bytes_per_launch": spmv_bytes / max(spmv_timed, 1),
+            "avg_launch_us": 1e3 * spmv_ms / max(spmv_timed, 1),
             "timed_launches": spmv_timed,
             "launches": spmv_launches,
         },
-        "kernel_ms": {k: v[0] for k, v in prof.items()},
+        "kernel_ms_sampled": {k: v[0] for k, v in prof.items()},
         "kernel_timed": {k: v[1] for k, v in prof.items()},
         "kernel_launches": {k: v[2] for k, v in prof.items()},
     }
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(prob, poses[args.warmup])
+        k = int(np.argmin([len(p["T"]) for p in probs]))
+        result["cpu_baseline"] = cpu_baseline(probs[k], steps[args.warmup][k])
     print(json.dumps(result), flush=True)
-    ch.close()
+    for c in chars:
+        c.close()
     ctx.close()
     return 0
 

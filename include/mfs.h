@@ -100,7 +100,9 @@ typedef struct mfs_solve_opts {
   int32_t cg_max;           /* PCG iteration cap per solve */
   int32_t warm_start;       /* enum mfs_warm_start */
   int32_t output_memory;    /* enum mfs_memory of x_out */
-  int32_t reserved;
+  int32_t cg_adaptive;      /* 1: inexact Newton, each PCG solve stops at
+                               max(cg_tol, eta_k) with the Eisenstat-Walker forcing
+                               eta_k = min(0.1, 0.9 (|g_k| / |g_k-1|)^2) */
 } mfs_solve_opts;
 
 typedef struct mfs_solve_stats {
@@ -121,7 +123,8 @@ typedef struct mfs_solve_stats {
 /* ---- library and context --------------------------------------------- */
 
 /* Fill *opts with the defaults: FP64, max_newton 50, fixed_newton 0,
- * step_tol 1e-10, cg_tol 1e-10, cg_max 20000, warm start REST, host output. */
+ * step_tol 1e-10, cg_tol 1e-10, cg_max 20000, warm start REST, host output,
+ * fixed PCG tolerance (cg_adaptive 0). */
 void mfs_default_opts(mfs_solve_opts* opts);
 
 /* Text for a status code (static storage). */
@@ -135,6 +138,19 @@ const char* mfs_last_error(void);
  * context.  Every kernel and copy of this context is enqueued on it. */
 int mfs_context_create(int device, void* hip_stream, mfs_context** out);
 int mfs_context_destroy(mfs_context* ctx);
+
+/* Launch-shape knobs of a context (set by the autotuner or by hand). */
+typedef struct mfs_tuning {
+  int32_t pcg_lanes_per_row;  /* lanes per block row in the PCG SpMV: 2, 4 or 8 */
+  int32_t use_graphs;         /* 1: replay runs of PCG iterations as captured HIP graphs */
+  int32_t graph_iterations;   /* PCG iterations per captured graph, 1..64 */
+  int32_t first_check;        /* PCG iterations before the first convergence check */
+  int32_t min_run, max_run;   /* bounds of later runs between checks */
+} mfs_tuning;
+
+int mfs_context_get_tuning(const mfs_context* ctx, mfs_tuning* out);
+/* Validates every field (MFS_E_INVALID otherwise) and drops cached graphs. */
+int mfs_context_set_tuning(mfs_context* ctx, const mfs_tuning* tuning);
 
 /* ---- characters (resident per-mesh state) ----------------------------- */
 
@@ -220,6 +236,10 @@ typedef struct mfs_profile {
   double gpu_ms[MFS_K_FAMILIES];     /* summed HIP-event time of the timed launches */
   int64_t timed[MFS_K_FAMILIES];     /* launches that were timed */
   int64_t launches[MFS_K_FAMILIES];  /* all launches of the family */
+  double bytes[MFS_K_FAMILIES];      /* algorithmic HBM bytes of the timed launches (SpMV:
+                                        every block value and column index, row pointers,
+                                        and per row the two gathered inputs and two outputs;
+                                        0 for families without a byte model) */
 } mfs_profile;
 
 /* Time kernel launches of this context with HIP events on its stream:

@@ -29,7 +29,8 @@ EXPORTED = ("mfs_default_opts", "mfs_status_string", "mfs_last_error", "mfs_cont
             "mfs_context_destroy", "mfs_character_create", "mfs_character_destroy",
             "mfs_character_footprint", "mfs_cluster_by_segments", "mfs_solve_frame",
             "mfs_solve_batch", "mfs_evaluate", "mfs_polar", "mfs_character_get_info",
-            "mfs_profile_enable", "mfs_profile_read")
+            "mfs_profile_enable", "mfs_profile_read", "mfs_context_get_tuning",
+            "mfs_context_set_tuning")
 
 KERNEL_FAMILIES = ("warm_start", "element", "assemble", "spmv", "cg_update", "linesearch", "update",
                    "other")
@@ -59,7 +60,7 @@ class MeshDesc(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("precision", c_i32), ("max_newton", c_i32), ("fixed_newton", c_i32),
                 ("step_tol", c_dbl), ("cg_tol", c_dbl), ("cg_max", c_i32), ("warm_start", c_i32),
-                ("output_memory", c_i32), ("reserved", c_i32)]
+                ("output_memory", c_i32), ("cg_adaptive", c_i32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -77,8 +78,14 @@ class CharacterInfo(ctypes.Structure):
                 ("n_handles", c_i32), ("reserved", c_i32), ("bbox_diag", c_dbl), ("mean_edge", c_dbl)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("pcg_lanes_per_row", c_i32), ("use_graphs", c_i32), ("graph_iterations", c_i32),
+                ("first_check", c_i32), ("min_run", c_i32), ("max_run", c_i32)]
+
+
 class Profile(ctypes.Structure):
-    _fields_ = [("gpu_ms", c_dbl * 8), ("timed", c_i64 * 8), ("launches", c_i64 * 8)]
+    _fields_ = [("gpu_ms", c_dbl * 8), ("timed", c_i64 * 8), ("launches", c_i64 * 8),
+                ("bytes", c_dbl * 8)]
 
 
 _lib = None
@@ -112,6 +119,8 @@ def lib():
         "mfs_character_get_info": (ctypes.c_int, [c_vp, P(CharacterInfo)]),
         "mfs_profile_enable": (ctypes.c_int, [c_vp, c_i32]),
         "mfs_profile_read": (ctypes.c_int, [c_vp, P(Profile), c_i32]),
+        "mfs_context_get_tuning": (ctypes.c_int, [c_vp, P(Tuning)]),
+        "mfs_context_set_tuning": (ctypes.c_int, [c_vp, P(Tuning)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -176,16 +185,32 @@ class Context:
         except Exception:
             pass
 
+    def tuning(self):
+        t = Tuning()
+        _check(lib().mfs_context_get_tuning(self.handle, ctypes.byref(t)))
+        return {name: getattr(t, name) for name, _ in t._fields_}
+
+    def set_tuning(self, **kw):
+        t = Tuning()
+        _check(lib().mfs_context_get_tuning(self.handle, ctypes.byref(t)))
+        for k, v in kw.items():
+            if not hasattr(t, k):
+                raise TypeError(f"unknown tuning field {k}")
+            setattr(t, k, int(v))
+        _check(lib().mfs_context_set_tuning(self.handle, ctypes.byref(t)))
+
     def profile_enable(self, stride=1):
         """Time every `stride`-th launch of each kernel family with HIP events
         (0 = off)."""
         _check(lib().mfs_profile_enable(self.handle, stride))
 
     def profile_read(self, reset=False):
-        """{family: (gpu_ms, timed launches, all launches)}."""
+        """{family: (gpu_ms, timed launches, all launches, algorithmic bytes of
+        the timed launches)}."""
         p = Profile()
         _check(lib().mfs_profile_read(self.handle, ctypes.byref(p), int(reset)))
-        return {f: (p.gpu_ms[i], p.timed[i], p.launches[i]) for i, f in enumerate(KERNEL_FAMILIES)}
+        return {f: (p.gpu_ms[i], p.timed[i], p.launches[i], p.bytes[i])
+                for i, f in enumerate(KERNEL_FAMILIES)}
 
     def cluster_by_segments(self, X, T, seg_a, seg_b, seg_handle):
         X = _host(X, np.float64)

@@ -157,3 +157,37 @@ extern "C" int mfs_polar(mfs_context* ctx, const double* F, int64_t count, int32
   MFS_HIP(hipStreamSynchronize(ctx->stream));
   return MFS_OK;
 }
+
+extern "C" int mfs_context_get_tuning(const mfs_context* ctx, mfs_tuning* out) {
+  clear_error();
+  if (!ctx || !out) return set_error(MFS_E_INVALID, "null argument");
+  out->pcg_lanes_per_row = ctx->lpr;
+  out->use_graphs = ctx->use_graphs ? 1 : 0;
+  out->graph_iterations = ctx->graph_iters;
+  out->first_check = ctx->cg_first_run;
+  out->min_run = ctx->cg_min_run;
+  out->max_run = ctx->cg_max_run;
+  return MFS_OK;
+}
+
+extern "C" int mfs_context_set_tuning(mfs_context* ctx, const mfs_tuning* t) {
+  clear_error();
+  if (!ctx || !t) return set_error(MFS_E_INVALID, "null argument");
+  if (t->pcg_lanes_per_row != 2 && t->pcg_lanes_per_row != 4 && t->pcg_lanes_per_row != 8)
+    return set_error(MFS_E_INVALID, "pcg_lanes_per_row must be 2, 4 or 8");
+  if (t->graph_iterations < 1 || t->graph_iterations > 64)
+    return set_error(MFS_E_INVALID, "graph_iterations must be in [1, 64]");
+  if (t->first_check < 1 || t->min_run < 1 || t->max_run < t->min_run)
+    return set_error(MFS_E_INVALID, "invalid PCG run bounds");
+  MFS_HIP(hipSetDevice(ctx->device));
+  MFS_HIP(hipStreamSynchronize(ctx->stream));
+  for (const CgGraph& g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+  ctx->graphs.clear();
+  ctx->lpr = t->pcg_lanes_per_row;
+  ctx->use_graphs = t->use_graphs != 0;
+  ctx->graph_iters = t->graph_iterations;
+  ctx->cg_first_run = t->first_check;
+  ctx->cg_min_run = t->min_run;
+  ctx->cg_max_run = t->max_run;
+  return MFS_OK;
+}

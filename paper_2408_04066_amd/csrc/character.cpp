@@ -413,16 +413,17 @@ extern "C" int mfs_character_create(mfs_context* ctx, const mfs_mesh_desc* d, mf
   }
 
   // ---- per-frame and solver state ----
-  ch->ntv = (n + kTile - 1) / kTile;
-  ch->ntt = (m + kTile - 1) / kTile;
-  ch->nts = (nnzb + kTile - 1) / kTile;
+  ch->ntv = (n + kVTile - 1) / kVTile;
+  ch->ntt = (m + kTTile - 1) / kTTile;
+  ch->nts = (nnzb + kSTile - 1) / kSTile;
   ch->ptile = std::max(ch->ntv, std::max(ch->ntt, ch->nts));
   const size_t n3 = 3 * (size_t)n * sizeof(double);
   MFS_TRY(ch->Rh.alloc(9 * sizeof(double) * kMaxHandles));
   MFS_TRY(ch->th.alloc(3 * sizeof(double) * kMaxHandles));
   MFS_TRY(ch->x.alloc(n3));
   MFS_TRY(ch->s.alloc(6 * sizeof(double) * (size_t)m));
-  MFS_TRY(ch->est.alloc(16 * sizeof(double) * (size_t)m));
+  MFS_TRY(ch->blk.alloc(90 * sizeof(double) * (size_t)m));
+  MFS_TRY(ch->frc.alloc(12 * sizeof(double) * (size_t)m));
   MFS_TRY(ch->b.alloc(n3));
   MFS_TRY(ch->dx.alloc(n3));
   MFS_TRY(ch->vals.alloc(9 * sizeof(double) * (size_t)nnzb));
@@ -467,7 +468,8 @@ extern "C" int mfs_character_create(mfs_context* ctx, const mfs_mesh_desc* d, mf
   s.th = ch->th.as<double>();
   s.x = ch->x.as<double>();
   s.s = ch->s.as<double>();
-  s.est = ch->est.as<double>();
+  s.blk = ch->blk.p;
+  s.frc = ch->frc.as<double>();
   s.b = ch->b.as<double>();
   s.dx = ch->dx.as<double>();
   s.vals = ch->vals.p;
@@ -486,7 +488,7 @@ extern "C" int mfs_character_create(mfs_context* ctx, const mfs_mesh_desc* d, mf
                        ch->rowptr.bytes + ch->colidx.bytes + ch->slot_ptr.bytes + ch->contrib.bytes +
                        ch->diag.bytes + ch->vpin_ptr.bytes + ch->vpin_h.bytes + ch->perm_d.bytes +
                        ch->tperm_d.bytes + ch->x.bytes + ch->s.bytes + ch->Rh.bytes + ch->th.bytes;
-  ch->workspace_bytes = ch->est.bytes + ch->b.bytes + ch->dx.bytes + ch->vals.bytes + ch->minv.bytes + ch->r.bytes +
+  ch->workspace_bytes = ch->blk.bytes + ch->frc.bytes + ch->b.bytes + ch->dx.bytes + ch->vals.bytes + ch->minv.bytes + ch->r.bytes +
                         ch->z.bytes + ch->p0.bytes + ch->p1.bytes + ch->q.bytes + ch->xc.bytes + ch->part.bytes +
                         ch->flags.bytes + ch->red.bytes;
   *out = guard.release();

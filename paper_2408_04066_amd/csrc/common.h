@@ -13,8 +13,10 @@
 
 namespace mfs {
 
-constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
-constexpr int kTile = 256;       // vertices / tets / slots per tile
+constexpr int kBlock = 256;      // threads per workgroup of tet and slot kernels (4 wave64)
+constexpr int kVTile = 64;       // block rows per vertex tile (vertex kernels run one wave64)
+constexpr int kTTile = 256;      // tets per tile
+constexpr int kSTile = 256;      // matrix-block slots per tile
 constexpr int kMaxHandles = 256;
 constexpr int kNumTrials = 5;    // line-search step lengths evaluated per energy pass
 
@@ -40,6 +42,8 @@ enum PartSlot : int {
 enum FlagSlot : int {
   F_CG_DONE = 0,   // PCG converged
   F_CG_ITERS = 1,  // PCG iterations at convergence
+  F_IT_A = 2,      // PCG iteration index read by the SpMV kernel (written by the update kernel)
+  F_IT_B = 3,      // PCG iteration index read by the update kernel (written by the SpMV kernel)
   F_COUNT = 4
 };
 
@@ -48,8 +52,33 @@ struct Ctrl {
   int32_t phase;     // 0: mixed phase (s != J x), 1: Newton phase (s = J x)
   int32_t update_s;  // mixed phase: apply the stretch update this iteration
   double alpha;      // accepted step length (0 = no update)
+  double cg_tol2;    // squared relative PCG tolerance (floor when adaptive)
+  int32_t cg_adaptive;  // 1: Eisenstat-Walker forcing on top of the floor
+  int32_t pad;
+  double cg_g2prev;  // |g|^2 of the previous Newton step (0: first step)
+  double cg_eta_min; // safeguard lower bound on the forcing term
   double trials[kNumTrials];  // step lengths evaluated by the energy pass
 };
+
+// PCG stopping threshold on |r|^2 / |b|^2 for one Newton step: the floor
+// cg_tol^2, raised in adaptive mode to the Eisenstat-Walker (choice 2) forcing
+// eta^2 with eta = min(0.1, 0.9 (|b| / |b_prev|)^2), never below the
+// safeguard eta_min; the first step uses eta = 0.1.
+__host__ __device__ inline double pcg_tol2(const Ctrl& C, double bb) {
+  double tol2 = C.cg_tol2;
+  if (C.cg_adaptive) {
+    double eta2 = 0.01;
+    if (C.cg_g2prev > 0.0) {
+      const double ratio = bb / C.cg_g2prev;
+      eta2 = 0.81 * ratio * ratio;
+      eta2 = eta2 < 0.01 ? eta2 : 0.01;
+      const double lo = C.cg_eta_min * C.cg_eta_min;
+      eta2 = eta2 > lo ? eta2 : lo;
+    }
+    tol2 = tol2 > eta2 ? tol2 : eta2;
+  }
+  return tol2;
+}
 
 struct Tile {
   int32_t sys;     // system (descriptor) index
@@ -82,7 +111,8 @@ struct SysDesc {
   // state (double)
   double* x;     // 3n positions
   double* s;     // 6 planes of m: mixed stretches
-  double* est;   // 16 planes of m: element state (W P, S^-1, coefficients)
+  void* blk;     // m records of 90 (precision T): the tet's 10 unique world-frame 3x3 Hessian blocks
+  double* frc;   // m records of 12: the tet's four corner forces (gradient of W Psi)
   double* b;     // 3n right-hand side (-grad)
   double* dx;    // 3n step (double)
   // state (precision T of the linear solve)
@@ -98,16 +128,8 @@ struct SysDesc {
   double* part;  // P_COUNT planes of ptile
   int32_t* flags;
   double* red;   // P_COUNT per-system results
-};
-
-// Element-state planes (SysDesc::est), 16 planes of m doubles.
-enum EstSlot : int {
-  E_WP = 0,    // 6: W * dPsi/dS (linearised), rotated frame
-  E_TI = 6,    // 6: S_lin^-1 (neo-Hookean)
-  E_CI = 12,   // W mu (ARAP, co-rotated) or W mu / 2 (neo-Hookean)
-  E_C2 = 13,   // W lambda (co-rotated)
-  E_C3 = 14,   // W max(mu - lambda ln J, 0) / 2 (neo-Hookean)
-  E_C4 = 15    // W lambda (neo-Hookean)
+  double* cgres; // 2: r.r and b.b as of the last PCG iteration
+  const Ctrl* ctrl;  // this system's control block (per-step PCG tolerance)
 };
 
 // Workgroup -> tile map that keeps consecutive tiles on one XCD: workgroups
@@ -132,15 +154,20 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Fixed-order workgroup sum: butterfly within each wave, then the four wave
+// Fixed-order workgroup sum: butterfly within each wave, then the wave
 // totals in order.  Every thread returns the same value.
-__device__ __forceinline__ double block_sum(double v, double* lds4) {
+template <int NW = 4>
+__device__ __forceinline__ double block_sum(double v, double* lds) {
   v = wave_sum(v);
+  if (NW == 1) return v;
   const int w = threadIdx.x >> 6;
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) lds4[w] = v;
+  if ((threadIdx.x & 63) == 0) lds[w] = v;
   __syncthreads();
-  return ((lds4[0] + lds4[1]) + lds4[2]) + lds4[3];
+  double acc = lds[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) acc += lds[i];
+  return acc;
 }
 
 __device__ __forceinline__ double block_max(double v, double* lds4) {

@@ -233,6 +233,50 @@ __device__ __forceinline__ void element_block(const double na[3], const double n
   }
 }
 
+// Index of the unique block (a, b), a <= b, among the 10 blocks of a tet:
+// (0,0) (0,1) (0,2) (0,3) (1,1) (1,2) (1,3) (2,2) (2,3) (3,3).
+__host__ __device__ constexpr int pair_index(int a, int b) { return a * 4 - (a * (a - 1)) / 2 + (b - a); }
+
+// R S R^T for symmetric S (6-vector in, 6-vector out).
+__device__ __forceinline__ void sym_rotate(const double R[9], const double s[6], double out[6]) {
+  double S[9], RS[9];
+  sym_full(s, S);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) RS[3 * i + j] = R[3 * i] * S[j] + R[3 * i + 1] * S[3 + j] + R[3 * i + 2] * S[6 + j];
+  auto e = [&](int i, int j) { return RS[3 * i] * R[3 * j] + RS[3 * i + 1] * R[3 * j + 1] + RS[3 * i + 2] * R[3 * j + 2]; };
+  out[0] = e(0, 0); out[1] = e(1, 1); out[2] = e(2, 2);
+  out[3] = e(1, 2); out[4] = e(0, 2); out[5] = e(0, 1);
+}
+
+// World-frame block K_ab = R Kt_ab R^T written with the rotated shape
+// gradients p = R n, q = (R T R^T) p and Tw = R T R^T:
+//   K_ab = cI [(p_a.p_b) I + p_b p_a^T] + c2 p_a p_b^T
+//        + c3 [q_b q_a^T + (p_a . q_b) Tw] + c4 q_a q_b^T.
+__device__ __forceinline__ void world_block(const double pa[3], const double pb[3], const double qa[3],
+                                            const double qb[3], const double Tw[6], const double c[4],
+                                            bool nh, double K[9]) {
+  const double dab = pa[0] * pb[0] + pa[1] * pb[1] + pa[2] * pb[2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) K[3 * i + j] = c[0] * pb[i] * pa[j] + c[1] * pa[i] * pb[j];
+  K[0] += c[0] * dab;
+  K[4] += c[0] * dab;
+  K[8] += c[0] * dab;
+  if (nh) {
+    double Tf[9];
+    sym_full(Tw, Tf);
+    const double aqb = pa[0] * qb[0] + pa[1] * qb[1] + pa[2] * qb[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        K[3 * i + j] += c[2] * (qb[i] * qa[j] + aqb * Tf[3 * i + j]) + c[3] * qa[i] * qb[j];
+  }
+}
+
 // K <- R K R^T
 __device__ __forceinline__ void rotate_block(const double R[9], const double Kt[9], double K[9]) {
   double RK[9];

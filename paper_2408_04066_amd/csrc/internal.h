@@ -67,7 +67,17 @@ struct PinnedBuf {
 namespace mfs {
 struct ProfPending {
   int fam;
+  double bytes;
   hipEvent_t a, b;
+};
+struct CgGraph {
+  const SysDesc* sd;
+  const Tile* tiles;
+  int ntv;
+  int fp32, lpr, iters;
+  bool has_one;      // captured with a single system's descriptor as kernel argument
+  SysDesc one;       // that descriptor (compared bytewise on lookup)
+  hipGraphExec_t exec;
 };
 }  // namespace mfs
 
@@ -75,16 +85,21 @@ struct mfs_context {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  int lpr = 8;                       // PCG lanes per block row
-  int cg_check = 16;                 // PCG iterations between convergence checks
+  int lpr = 4;                       // PCG lanes per block row (2, 4 or 8)
+  int cg_first_run = 32;             // PCG iterations before the first convergence check
+  int cg_min_run = 8, cg_max_run = 512;
+  bool use_graphs = true;            // replay captured runs of PCG iterations
+  int graph_iters = 8;               // PCG iterations per captured graph
+  std::vector<mfs::CgGraph> graphs;
   // batch scratch
-  mfs::DevBuf desc, ctrl, flags, red, tiles, sys_ids, tmp;
-  mfs::PinnedBuf h_ctrl, h_flags, h_red, h_tiles, h_stage;
+  mfs::DevBuf desc, ctrl, flags, red, cgres, tiles, sys_ids, tmp;
+  mfs::PinnedBuf h_ctrl, h_flags, h_red, h_cgres, h_tiles, h_stage;
   // HIP-event profiler (mfs_profile_enable)
   int prof_stride = 0;
   double prof_ms[MFS_K_FAMILIES] = {};
   int64_t prof_timed[MFS_K_FAMILIES] = {};
   int64_t prof_launches[MFS_K_FAMILIES] = {};
+  double prof_bytes[MFS_K_FAMILIES] = {};
   std::vector<hipEvent_t> ev_pool;
   std::vector<mfs::ProfPending> pending;
   ~mfs_context();
@@ -102,7 +117,7 @@ struct mfs_character {
   mfs::DevBuf tets, G, wmu, wlam, info, X, rowptr, colidx, slot_ptr, contrib, diag, vpin_ptr, vpin_h, perm_d,
       tperm_d;
   // per-frame rig and solver state
-  mfs::DevBuf Rh, th, x, s, est, b, dx, vals, minv, r, z, p0, p1, q, xc, part, flags, red;
+  mfs::DevBuf Rh, th, x, s, blk, frc, b, dx, vals, minv, r, z, p0, p1, q, xc, part, flags, red;
   mfs::SysDesc desc;  // pointers above, host copy
   size_t resident_bytes = 0, workspace_bytes = 0;
 };
@@ -120,8 +135,9 @@ int check_pose(const mfs_character* ch, const double* R, const double* t);
 struct ProfScope {
   mfs_context* c;
   int fam;
+  double bytes;
   hipEvent_t a = nullptr;
-  ProfScope(mfs_context* ctx, int family);
+  ProfScope(mfs_context* ctx, int family, double algorithmic_bytes = 0.0);
   ~ProfScope();
 };
 // Fold completed event pairs into the counters (call after a stream sync).

@@ -1,15 +1,20 @@
 // Preconditioned conjugate gradients on the condensed 3x3-block system
 // (the global sparse SPD solve of each Newton step).
 //
-// Two kernels per iteration.  k_cg_spmv(it) forms the search direction
+// Two kernels per iteration.  k_cg_spmv forms the search direction
 // p_it = z + beta p_{it-1} on the fly (double-buffered p, so the gathers of
 // neighbouring rows read the previous buffer) and q = K p_it, with LPR lanes
 // per block row reading the 9 value planes of consecutive slots (coalesced).
-// k_cg_update(it) applies alpha, the block-Jacobi preconditioner and the
-// next dot products.  Dot products are per-tile partials in FP64, folded per
+// k_cg_update applies alpha, the block-Jacobi preconditioner and the next
+// dot products.  Dot products are per-tile partials in FP64, folded per
 // system in a fixed order by every workgroup that needs them.  Convergence
 // (||r|| <= tol ||b||) is decided identically by every workgroup of a system
 // from those partials.
+//
+// The iteration index lives in device memory (two slots, each written by the
+// other kernel of the pair, so no kernel reads a slot it writes): the launch
+// arguments of an iteration do not depend on its index, and a run of
+// iterations can be captured once as a HIP graph and replayed.
 #include "common.h"
 #include "elem_math.h"
 #include "launch.h"
@@ -17,14 +22,16 @@
 namespace mfs {
 
 template <typename T>
-__device__ __forceinline__ T shfl_xor_t(T v, int o) {
-  return __shfl_xor(v, o, 64);
+__device__ __forceinline__ void precondition(const T* __restrict__ mi, const T rv[3], T zv[3]) {
+  zv[0] = mi[0] * rv[0] + mi[5] * rv[1] + mi[4] * rv[2];
+  zv[1] = mi[5] * rv[0] + mi[1] * rv[1] + mi[3] * rv[2];
+  zv[2] = mi[4] * rv[0] + mi[3] * rv[1] + mi[2] * rv[2];
 }
 
+// r = b, x = 0, z = M^-1 r; partials r.z, r.r, b.b.  One wave per tile.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_init(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
-                                                    int ntiles) {
-  __shared__ double red[4];
+__global__ __launch_bounds__(64) void k_cg_init(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
+                                                int ntiles) {
   const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
   const SysDesc& S = sd[t.sys];
   const int row = t.begin + threadIdx.x;
@@ -33,8 +40,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(const SysDesc* __restrict__ 
     T* r = (T*)S.r;
     T* z = (T*)S.z;
     T* xc = (T*)S.xc;
-    const T* mi = (const T*)S.minv + 6 * row;
-    T rv[3];
+    T rv[3], zv[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const double bv = S.b[3 * row + i];
@@ -43,10 +49,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(const SysDesc* __restrict__ 
       r[3 * row + i] = rv[i];
       xc[3 * row + i] = (T)0;
     }
-    T zv[3];
-    zv[0] = mi[0] * rv[0] + mi[5] * rv[1] + mi[4] * rv[2];
-    zv[1] = mi[5] * rv[0] + mi[1] * rv[1] + mi[3] * rv[2];
-    zv[2] = mi[4] * rv[0] + mi[3] * rv[1] + mi[2] * rv[2];
+    precondition((const T*)S.minv + 6 * row, rv, zv);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       z[3 * row + i] = zv[i];
@@ -54,35 +57,57 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(const SysDesc* __restrict__ 
       rr += (double)rv[i] * (double)rv[i];
     }
   }
-  const double s_rz = block_sum(rz, red);
-  const double s_rr = block_sum(rr, red);
-  const double s_bb = block_sum(bb, red);
+  rz = wave_sum(rz);
+  rr = wave_sum(rr);
+  bb = wave_sum(bb);
   if (threadIdx.x == 0) {
-    S.part[P_RZ0 * S.ptile + t.local] = s_rz;
-    S.part[P_RR * S.ptile + t.local] = s_rr;
-    S.part[P_BB * S.ptile + t.local] = s_bb;
+    S.part[P_RZ0 * S.ptile + t.local] = rz;
+    S.part[P_RR * S.ptile + t.local] = rr;
+    S.part[P_BB * S.ptile + t.local] = bb;
     if (t.local == 0) {
       S.flags[F_CG_DONE] = 0;
       S.flags[F_CG_ITERS] = 0;
+      S.flags[F_IT_A] = 0;
+      S.flags[F_IT_B] = 0;
     }
   }
 }
 
-template <typename T, int LPR>
-__global__ __launch_bounds__(kBlock) void k_cg_spmv(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
-                                                    int ntiles, int it, double tol2) {
-  __shared__ double red[4];
-  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
-  const SysDesc& S = sd[t.sys];
+// Search direction and q = K p: one pass of 64 rows, LPR lanes per row.
+// ONE: a single system whose descriptor is the kernel argument `one` and
+// whose tiles are implicit (tile j = rows [64 j, 64 j + 64)); saves the two
+// dependent loads (tile, descriptor) at the head of every workgroup.
+template <bool ONE>
+__device__ __forceinline__ Tile vertex_tile(const Tile* __restrict__ tiles, int ntiles, const SysDesc& one) {
+  const int j = xcd_tile(blockIdx.x, ntiles);
+  if (ONE) return Tile{0, j * kVTile, min(one.n, (j + 1) * kVTile), j};
+  return tiles[j];
+}
+
+template <typename T, int LPR, bool ONE>
+__global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
+                                                      int ntiles, const SysDesc one) {
+  __shared__ double red[LPR];
+  const Tile t = vertex_tile<ONE>(tiles, ntiles, one);
+  const SysDesc& S = ONE ? one : sd[t.sys];
   const double* part = S.part;
   const double rr = sys_sum(part + P_RR * S.ptile, S.ntv);
   const double bb = sys_sum(part + P_BB * S.ptile, S.ntv);
+  const double tol2 = pcg_tol2(*S.ctrl, bb);
+  const int it = S.flags[F_IT_A];
   if (rr <= tol2 * bb) {
     if (t.local == 0 && threadIdx.x == 0 && S.flags[F_CG_DONE] == 0) {
       S.flags[F_CG_DONE] = 1;
       S.flags[F_CG_ITERS] = it;
+      S.cgres[0] = rr;
+      S.cgres[1] = bb;
     }
     return;
+  }
+  if (t.local == 0 && threadIdx.x == 0) {
+    S.flags[F_IT_B] = it;
+    S.cgres[0] = rr;
+    S.cgres[1] = bb;
   }
   const double rz = sys_sum(part + (P_RZ0 + (it & 1)) * S.ptile, S.ntv);
   const double beta = it == 0 ? 0.0 : rz / sys_sum(part + (P_RZ0 + ((it + 1) & 1)) * S.ptile, S.ntv);
@@ -94,59 +119,57 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(const SysDesc* __restrict__ 
   T* q = (T*)S.q;
   const size_t nz = S.nnzb;
   const int lane = threadIdx.x % LPR;
-  constexpr int RPP = kBlock / LPR;
-  double dot = 0.0;
-  for (int r0 = t.begin; r0 < t.end; r0 += RPP) {
-    const int row = r0 + threadIdx.x / LPR;
-    T a0 = 0, a1 = 0, a2 = 0;
-    if (row < t.end) {
-      const int e = S.rowptr[row + 1];
-      for (int sl = S.rowptr[row] + lane; sl < e; sl += LPR) {
-        const int c = S.colidx[sl];
-        T v0 = z[3 * c], v1 = z[3 * c + 1], v2 = z[3 * c + 2];
-        if (it) {
-          v0 += tb * po[3 * c];
-          v1 += tb * po[3 * c + 1];
-          v2 += tb * po[3 * c + 2];
-        }
-        a0 += vals[sl] * v0 + vals[nz + sl] * v1 + vals[2 * nz + sl] * v2;
-        a1 += vals[3 * nz + sl] * v0 + vals[4 * nz + sl] * v1 + vals[5 * nz + sl] * v2;
-        a2 += vals[6 * nz + sl] * v0 + vals[7 * nz + sl] * v1 + vals[8 * nz + sl] * v2;
-      }
-    }
-#pragma unroll
-    for (int o = LPR / 2; o > 0; o >>= 1) {
-      a0 += shfl_xor_t(a0, o);
-      a1 += shfl_xor_t(a1, o);
-      a2 += shfl_xor_t(a2, o);
-    }
-    if (row < t.end && lane == 0) {
-      T p0 = z[3 * row], p1 = z[3 * row + 1], p2 = z[3 * row + 2];
+  const int row = t.begin + threadIdx.x / LPR;
+  T a0 = 0, a1 = 0, a2 = 0;
+  if (row < t.end) {
+    const int e = S.rowptr[row + 1];
+    for (int sl = S.rowptr[row] + lane; sl < e; sl += LPR) {
+      const int c = S.colidx[sl];
+      T v0 = z[3 * c], v1 = z[3 * c + 1], v2 = z[3 * c + 2];
       if (it) {
-        p0 += tb * po[3 * row];
-        p1 += tb * po[3 * row + 1];
-        p2 += tb * po[3 * row + 2];
+        v0 += tb * po[3 * c];
+        v1 += tb * po[3 * c + 1];
+        v2 += tb * po[3 * c + 2];
       }
-      pn[3 * row] = p0;
-      pn[3 * row + 1] = p1;
-      pn[3 * row + 2] = p2;
-      q[3 * row] = a0;
-      q[3 * row + 1] = a1;
-      q[3 * row + 2] = a2;
-      dot += (double)p0 * (double)a0 + (double)p1 * (double)a1 + (double)p2 * (double)a2;
+      a0 += vals[sl] * v0 + vals[nz + sl] * v1 + vals[2 * nz + sl] * v2;
+      a1 += vals[3 * nz + sl] * v0 + vals[4 * nz + sl] * v1 + vals[5 * nz + sl] * v2;
+      a2 += vals[6 * nz + sl] * v0 + vals[7 * nz + sl] * v1 + vals[8 * nz + sl] * v2;
     }
   }
-  const double tot = block_sum(dot, red);
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) {
+    a0 += __shfl_xor(a0, o, 64);
+    a1 += __shfl_xor(a1, o, 64);
+    a2 += __shfl_xor(a2, o, 64);
+  }
+  double dot = 0.0;
+  if (row < t.end && lane == 0) {
+    T p0 = z[3 * row], p1 = z[3 * row + 1], p2 = z[3 * row + 2];
+    if (it) {
+      p0 += tb * po[3 * row];
+      p1 += tb * po[3 * row + 1];
+      p2 += tb * po[3 * row + 2];
+    }
+    pn[3 * row] = p0;
+    pn[3 * row + 1] = p1;
+    pn[3 * row + 2] = p2;
+    q[3 * row] = a0;
+    q[3 * row + 1] = a1;
+    q[3 * row + 2] = a2;
+    dot = (double)p0 * (double)a0 + (double)p1 * (double)a1 + (double)p2 * (double)a2;
+  }
+  const double tot = block_sum<LPR>(dot, red);
   if (threadIdx.x == 0) S.part[P_PQ * S.ptile + t.local] = tot;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_update(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
-                                                      int ntiles, int it) {
-  __shared__ double red[4];
-  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
-  const SysDesc& S = sd[t.sys];
+// alpha = r.z / p.q; x += alpha p; r -= alpha q; z = M^-1 r; partials.
+template <typename T, bool ONE>
+__global__ __launch_bounds__(64) void k_cg_update(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
+                                                  int ntiles, const SysDesc one) {
+  const Tile t = vertex_tile<ONE>(tiles, ntiles, one);
+  const SysDesc& S = ONE ? one : sd[t.sys];
   if (S.flags[F_CG_DONE]) return;
+  const int it = S.flags[F_IT_B];
   const double pq = sys_sum(S.part + P_PQ * S.ptile, S.ntv);
   const double rz = sys_sum(S.part + (P_RZ0 + (it & 1)) * S.ptile, S.ntv);
   const T alpha = (T)(rz / pq);
@@ -158,18 +181,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(const SysDesc* __restrict_
   const int row = t.begin + threadIdx.x;
   double rzn = 0.0, rrn = 0.0;
   if (row < t.end) {
-    T rv[3];
+    T rv[3], zv[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       xc[3 * row + i] += alpha * pn[3 * row + i];
       rv[i] = r[3 * row + i] - alpha * q[3 * row + i];
       r[3 * row + i] = rv[i];
     }
-    const T* mi = (const T*)S.minv + 6 * row;
-    T zv[3];
-    zv[0] = mi[0] * rv[0] + mi[5] * rv[1] + mi[4] * rv[2];
-    zv[1] = mi[5] * rv[0] + mi[1] * rv[1] + mi[3] * rv[2];
-    zv[2] = mi[4] * rv[0] + mi[3] * rv[1] + mi[2] * rv[2];
+    precondition((const T*)S.minv + 6 * row, rv, zv);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       z[3 * row + i] = zv[i];
@@ -177,18 +196,19 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(const SysDesc* __restrict_
       rrn += (double)rv[i] * (double)rv[i];
     }
   }
-  const double s_rz = block_sum(rzn, red);
-  const double s_rr = block_sum(rrn, red);
+  rzn = wave_sum(rzn);
+  rrn = wave_sum(rrn);
   if (threadIdx.x == 0) {
-    S.part[(P_RZ0 + ((it + 1) & 1)) * S.ptile + t.local] = s_rz;
-    S.part[P_RR * S.ptile + t.local] = s_rr;
+    S.part[(P_RZ0 + ((it + 1) & 1)) * S.ptile + t.local] = rzn;
+    S.part[P_RR * S.ptile + t.local] = rrn;
+    if (t.local == 0) S.flags[F_IT_A] = it + 1;
   }
 }
 
 // dx (FP64) <- PCG iterate.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_finish(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
-                                                      int ntiles) {
+__global__ __launch_bounds__(64) void k_cg_finish(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
+                                                  int ntiles) {
   const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
   const SysDesc& S = sd[t.sys];
   const int row = t.begin + threadIdx.x;
@@ -217,17 +237,17 @@ __global__ __launch_bounds__(kBlock) void k_spmv_plain(const int32_t* __restrict
 }
 
 // ---- launchers ----
-template <typename T>
-static void cg_spmv_t(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int it, double tol2, int lpr) {
+template <typename T, bool ONE>
+static void cg_spmv_t(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int lpr, const SysDesc& one) {
   switch (lpr) {
-    case 4:
-      hipLaunchKernelGGL((k_cg_spmv<T, 4>), dim3(ntv), dim3(kBlock), 0, st, sd, tv, ntv, it, tol2);
+    case 2:
+      hipLaunchKernelGGL((k_cg_spmv<T, 2, ONE>), dim3(ntv), dim3(128), 0, st, sd, tv, ntv, one);
       break;
-    case 16:
-      hipLaunchKernelGGL((k_cg_spmv<T, 16>), dim3(ntv), dim3(kBlock), 0, st, sd, tv, ntv, it, tol2);
+    case 8:
+      hipLaunchKernelGGL((k_cg_spmv<T, 8, ONE>), dim3(ntv), dim3(512), 0, st, sd, tv, ntv, one);
       break;
     default:
-      hipLaunchKernelGGL((k_cg_spmv<T, 8>), dim3(ntv), dim3(kBlock), 0, st, sd, tv, ntv, it, tol2);
+      hipLaunchKernelGGL((k_cg_spmv<T, 4, ONE>), dim3(ntv), dim3(256), 0, st, sd, tv, ntv, one);
       break;
   }
 }
@@ -235,34 +255,44 @@ static void cg_spmv_t(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv
 void launch_cg_init(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32) {
   if (!ntv) return;
   if (fp32)
-    hipLaunchKernelGGL(k_cg_init<float>, dim3(ntv), dim3(kBlock), 0, st, sd, tv, ntv);
+    hipLaunchKernelGGL(k_cg_init<float>, dim3(ntv), dim3(64), 0, st, sd, tv, ntv);
   else
-    hipLaunchKernelGGL(k_cg_init<double>, dim3(ntv), dim3(kBlock), 0, st, sd, tv, ntv);
+    hipLaunchKernelGGL(k_cg_init<double>, dim3(ntv), dim3(64), 0, st, sd, tv, ntv);
 }
 
-void launch_cg_spmv(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int it, double tol2, int fp32,
-                    int lpr) {
+void launch_cg_spmv(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, int lpr,
+                    const SysDesc* one) {
   if (!ntv) return;
-  if (fp32)
-    cg_spmv_t<float>(st, sd, tv, ntv, it, tol2, lpr);
-  else
-    cg_spmv_t<double>(st, sd, tv, ntv, it, tol2, lpr);
+  static const SysDesc none{};
+  const SysDesc& o = one ? *one : none;
+  if (fp32) {
+    if (one) cg_spmv_t<float, true>(st, sd, tv, ntv, lpr, o);
+    else cg_spmv_t<float, false>(st, sd, tv, ntv, lpr, o);
+  } else {
+    if (one) cg_spmv_t<double, true>(st, sd, tv, ntv, lpr, o);
+    else cg_spmv_t<double, false>(st, sd, tv, ntv, lpr, o);
+  }
 }
 
-void launch_cg_update(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int it, int fp32) {
+void launch_cg_update(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, const SysDesc* one) {
   if (!ntv) return;
-  if (fp32)
-    hipLaunchKernelGGL(k_cg_update<float>, dim3(ntv), dim3(kBlock), 0, st, sd, tv, ntv, it);
-  else
-    hipLaunchKernelGGL(k_cg_update<double>, dim3(ntv), dim3(kBlock), 0, st, sd, tv, ntv, it);
+  static const SysDesc none{};
+  const SysDesc& o = one ? *one : none;
+  if (fp32) {
+    if (one) hipLaunchKernelGGL((k_cg_update<float, true>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv, o);
+    else hipLaunchKernelGGL((k_cg_update<float, false>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv, o);
+  } else {
+    if (one) hipLaunchKernelGGL((k_cg_update<double, true>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv, o);
+    else hipLaunchKernelGGL((k_cg_update<double, false>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv, o);
+  }
 }
 
 void launch_cg_finish(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32) {
   if (!ntv) return;
   if (fp32)
-    hipLaunchKernelGGL(k_cg_finish<float>, dim3(ntv), dim3(kBlock), 0, st, sd, tv, ntv);
+    hipLaunchKernelGGL(k_cg_finish<float>, dim3(ntv), dim3(64), 0, st, sd, tv, ntv);
   else
-    hipLaunchKernelGGL(k_cg_finish<double>, dim3(ntv), dim3(kBlock), 0, st, sd, tv, ntv);
+    hipLaunchKernelGGL(k_cg_finish<double>, dim3(ntv), dim3(64), 0, st, sd, tv, ntv);
 }
 
 void launch_spmv_plain(hipStream_t st, const int32_t* rowptr, const int32_t* colidx, const double* vals, int nnzb,

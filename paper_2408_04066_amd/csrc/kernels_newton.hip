@@ -67,8 +67,12 @@ __global__ __launch_bounds__(kBlock) void k_warm_start(const SysDesc* __restrict
 // Element pass (per Newton iteration).  For each tet: F = sum_a x_a n_a^T,
 // condensed stretch sx = sym(R^T F), then the material linearised at
 // sl = s (mixed phase, the stored mixed variable) or sl = sx (Newton phase).
-// Writes the element state planes and, in the Newton phase, s = sx.
+// Writes the tet's record: its 10 unique world-frame Hessian blocks
+// (precision T) and its four corner forces (FP64), and in the Newton phase
+// s = sx.  World frame: p_a = R n_a, Tw = R S_lin^-1 R^T, q_a = Tw p_a, and
+// the corner force R (W P) n_a = (R W P R^T) p_a.
 // ---------------------------------------------------------------------------
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_element(const SysDesc* __restrict__ sd, const Ctrl* __restrict__ ctrl,
                                                     const Tile* __restrict__ tiles, int ntiles) {
   __shared__ double red[4];
@@ -97,14 +101,37 @@ __global__ __launch_bounds__(kBlock) void k_element(const SysDesc* __restrict__ 
         S.s[i * m + k] = sx[i];
       }
     }
-    double WP[6], T[6], c[4];
-    clamped = element_state(model, S.wmu[k], S.wlam[k], sl, sx, WP, T, c) ? 1.0 : 0.0;
+    double WP[6], Ti[6], c[4];
+    clamped = element_state(model, S.wmu[k], S.wlam[k], sl, sx, WP, Ti, c) ? 1.0 : 0.0;
+    const bool nh = model == kNeoHookean;
+    double p[4][3], q[4][3], Tw[6] = {0, 0, 0, 0, 0, 0}, Pw[6];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) S.est[(E_WP + i) * m + k] = WP[i];
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int i = 0; i < 6; ++i) S.est[(E_TI + i) * m + k] = T[i];
+      for (int i = 0; i < 3; ++i) p[a][i] = R[3 * i] * n[a][0] + R[3 * i + 1] * n[a][1] + R[3 * i + 2] * n[a][2];
+    if (nh) sym_rotate(R, Ti, Tw);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) S.est[(E_CI + i) * m + k] = c[i];
+    for (int a = 0; a < 4; ++a) sym_mv(Tw, p[a], q[a]);
+    sym_rotate(R, WP, Pw);
+    double* fr = S.frc + 12 * (size_t)k;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      double f[3];
+      sym_mv(Pw, p[a], f);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) fr[3 * a + i] = f[i];
+    }
+    T* bk = (T*)S.blk + 90 * (size_t)k;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = a; b < 4; ++b) {
+        double K[9];
+        world_block(p[a], p[b], q[a], q[b], Tw, c, nh, K);
+        const int pi = pair_index(a, b);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) bk[9 * pi + i] = (T)K[i];
+      }
   }
   const double tot = block_sum(clamped, red);
   if (threadIdx.x == 0) S.part[P_CLAMP * S.ptile + t.local] = tot;
@@ -114,8 +141,9 @@ __global__ __launch_bounds__(kBlock) void k_element(const SysDesc* __restrict__ 
 // Assembly of the condensed system (eq. 12 read as a Newton increment):
 //   K = k_s P^T P + sum_k W_k J_k^T H_k J_k,  b = -grad C - sum_k W_k J_k^T g_k,
 // gathered per 3x3 block slot from the slot's list of (tet, a, b)
-// contributions (no atomics).  The diagonal slot of vertex r also adds the
-// pins of r, writes b_r and the inverse diagonal block (block Jacobi).
+// contributions (no atomics); each contribution is one block of the tet's
+// record (transposed when a > b).  The diagonal slot of vertex r also adds
+// the pins of r, writes b_r and the inverse diagonal block (block Jacobi).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_assemble(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
@@ -124,42 +152,37 @@ __global__ __launch_bounds__(kBlock) void k_assemble(const SysDesc* __restrict__
   const SysDesc& S = sd[t.sys];
   const int slot = t.begin + threadIdx.x;
   if (slot >= t.end) return;
-  const size_t m = S.m;
+  const T* blk = (const T*)S.blk;
   double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   double f[3] = {0, 0, 0};
   const int c0 = S.slot_ptr[slot], c1 = S.slot_ptr[slot + 1];
-  int row = -1;
-  bool diag = false;
+  const int code0 = S.contrib[c0];
+  const int a0 = (code0 >> 2) & 3;
+  const bool diag = a0 == (code0 & 3);
   for (int ci = c0; ci < c1; ++ci) {
     const int code = S.contrib[ci];
     const int k = code >> 4, a = (code >> 2) & 3, b = code & 3;
-    double n[4][3], R[9], Ti[6], c[4], Kt[9], K[9];
-    load_grads(S.G, S.m, k, n);
-    load_rot(S.Rh, S.info[k] & 0xffff, R);
+    if (a <= b) {
+      const T* bp = blk + 90 * (size_t)k + 9 * pair_index(a, b);
 #pragma unroll
-    for (int i = 0; i < 6; ++i) Ti[i] = S.est[(E_TI + i) * m + k];
+      for (int i = 0; i < 9; ++i) acc[i] += (double)bp[i];
+    } else {
+      const T* bp = blk + 90 * (size_t)k + 9 * pair_index(b, a);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) c[i] = S.est[(E_CI + i) * m + k];
-    element_block(n[a], n[b], Ti, c, Kt);
-    rotate_block(R, Kt, K);
+      for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int i = 0; i < 9; ++i) acc[i] += K[i];
-    if (ci == c0) {
-      const int4 tv = S.tets[k];
-      const int v[4] = {tv.x, tv.y, tv.z, tv.w};
-      row = v[a];
-      diag = (a == b);
+        for (int j = 0; j < 3; ++j) acc[3 * i + j] += (double)bp[3 * j + i];
     }
-    if (a == b) {
-      double WP[6], g[3];
+    if (diag) {
+      const double* fr = S.frc + 12 * (size_t)k + 3 * a;
 #pragma unroll
-      for (int i = 0; i < 6; ++i) WP[i] = S.est[(E_WP + i) * m + k];
-      sym_mv(WP, n[a], g);
-#pragma unroll
-      for (int i = 0; i < 3; ++i) f[i] += R[3 * i] * g[0] + R[3 * i + 1] * g[1] + R[3 * i + 2] * g[2];
+      for (int i = 0; i < 3; ++i) f[i] += fr[i];
     }
   }
   if (diag) {
+    const int4 tv = S.tets[code0 >> 4];
+    const int v[4] = {tv.x, tv.y, tv.z, tv.w};
+    const int row = v[a0];
     // pins of this vertex: stiffness k_s I each, target R_h X_r + t_h
     double cnt = 0.0, ys[3] = {0, 0, 0};
     for (int pi = S.vpin_ptr[row]; pi < S.vpin_ptr[row + 1]; ++pi) {
@@ -273,10 +296,9 @@ __global__ __launch_bounds__(kBlock) void k_linesearch_tets(const SysDesc* __res
 
 // Vertex part of the line search: b . dx, max_v |dx_v| and the pin energy
 // k_s/2 |x_r + alpha_i dx_r - (R_h X_r + t_h)|^2 at each trial step.
-__global__ __launch_bounds__(kBlock) void k_linesearch_verts(const SysDesc* __restrict__ sd,
-                                                             const Ctrl* __restrict__ ctrl,
-                                                             const Tile* __restrict__ tiles, int ntiles) {
-  __shared__ double red[4];
+__global__ __launch_bounds__(64) void k_linesearch_verts(const SysDesc* __restrict__ sd,
+                                                         const Ctrl* __restrict__ ctrl,
+                                                         const Tile* __restrict__ tiles, int ntiles) {
   const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
   const SysDesc& S = sd[t.sys];
   const Ctrl& C = ctrl[t.sys];
@@ -312,15 +334,15 @@ __global__ __launch_bounds__(kBlock) void k_linesearch_verts(const SysDesc* __re
       }
     }
   }
-  const double ss = block_sum(slope, red);
-  const double dm = block_max(dmax, red);
+  const double ss = wave_sum(slope);
+  const double dm = wave_max(dmax);
   if (threadIdx.x == 0) {
     S.part[P_SLOPE * S.ptile + t.local] = ss;
     S.part[P_DXMAX * S.ptile + t.local] = dm;
   }
 #pragma unroll
   for (int j = 0; j < kNumTrials; ++j) {
-    const double ps = block_sum(pe[j], red);
+    const double ps = wave_sum(pe[j]);
     if (threadIdx.x == 0) S.part[(P_PIN0 + j) * S.ptile + t.local] = ps;
   }
 }
@@ -356,7 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_update_s(const SysDesc* __restrict__
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_update_x(const SysDesc* __restrict__ sd, const Ctrl* __restrict__ ctrl,
+__global__ __launch_bounds__(64) void k_update_x(const SysDesc* __restrict__ sd, const Ctrl* __restrict__ ctrl,
                                                      const Tile* __restrict__ tiles, int ntiles) {
   const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
   const SysDesc& S = sd[t.sys];
@@ -384,8 +406,12 @@ __global__ __launch_bounds__(64) void k_finalize(const SysDesc* __restrict__ sd,
 void launch_warm_start(hipStream_t st, const SysDesc* sd, const Tile* tiles, int ntiles, int fp32) {
   if (ntiles) hipLaunchKernelGGL(k_warm_start, dim3(ntiles), dim3(kBlock), 0, st, sd, tiles, ntiles, fp32);
 }
-void launch_element(hipStream_t st, const SysDesc* sd, const Ctrl* ctrl, const Tile* tiles, int ntiles) {
-  if (ntiles) hipLaunchKernelGGL(k_element, dim3(ntiles), dim3(kBlock), 0, st, sd, ctrl, tiles, ntiles);
+void launch_element(hipStream_t st, const SysDesc* sd, const Ctrl* ctrl, const Tile* tiles, int ntiles, int fp32) {
+  if (!ntiles) return;
+  if (fp32)
+    hipLaunchKernelGGL(k_element<float>, dim3(ntiles), dim3(kBlock), 0, st, sd, ctrl, tiles, ntiles);
+  else
+    hipLaunchKernelGGL(k_element<double>, dim3(ntiles), dim3(kBlock), 0, st, sd, ctrl, tiles, ntiles);
 }
 void launch_assemble(hipStream_t st, const SysDesc* sd, const Tile* tiles, int ntiles, int fp32) {
   if (!ntiles) return;
@@ -397,12 +423,12 @@ void launch_assemble(hipStream_t st, const SysDesc* sd, const Tile* tiles, int n
 void launch_linesearch(hipStream_t st, const SysDesc* sd, const Ctrl* ctrl, const Tile* tt, int ntt, const Tile* tv,
                        int ntv) {
   if (ntt) hipLaunchKernelGGL(k_linesearch_tets, dim3(ntt), dim3(kBlock), 0, st, sd, ctrl, tt, ntt);
-  if (ntv) hipLaunchKernelGGL(k_linesearch_verts, dim3(ntv), dim3(kBlock), 0, st, sd, ctrl, tv, ntv);
+  if (ntv) hipLaunchKernelGGL(k_linesearch_verts, dim3(ntv), dim3(64), 0, st, sd, ctrl, tv, ntv);
 }
 void launch_update(hipStream_t st, const SysDesc* sd, const Ctrl* ctrl, const Tile* tt, int ntt, const Tile* tv,
                    int ntv) {
   if (ntt) hipLaunchKernelGGL(k_update_s, dim3(ntt), dim3(kBlock), 0, st, sd, ctrl, tt, ntt);
-  if (ntv) hipLaunchKernelGGL(k_update_x, dim3(ntv), dim3(kBlock), 0, st, sd, ctrl, tv, ntv);
+  if (ntv) hipLaunchKernelGGL(k_update_x, dim3(ntv), dim3(64), 0, st, sd, ctrl, tv, ntv);
 }
 void launch_finalize(hipStream_t st, const SysDesc* sd, const int32_t* sys_ids, int nsys) {
   if (nsys) hipLaunchKernelGGL(k_finalize, dim3(nsys), dim3(64), 0, st, sd, sys_ids);

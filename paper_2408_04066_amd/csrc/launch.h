@@ -22,7 +22,7 @@ void launch_scatter_planes6(hipStream_t st, const double* planes, int m, const i
 
 // Newton iteration
 void launch_warm_start(hipStream_t st, const SysDesc* sd, const Tile* tiles, int ntiles, int fp32);
-void launch_element(hipStream_t st, const SysDesc* sd, const Ctrl* ctrl, const Tile* tiles, int ntiles);
+void launch_element(hipStream_t st, const SysDesc* sd, const Ctrl* ctrl, const Tile* tiles, int ntiles, int fp32);
 void launch_assemble(hipStream_t st, const SysDesc* sd, const Tile* tiles, int ntiles, int fp32);
 void launch_linesearch(hipStream_t st, const SysDesc* sd, const Ctrl* ctrl, const Tile* tt, int ntt, const Tile* tv,
                        int ntv);
@@ -32,9 +32,11 @@ void launch_finalize(hipStream_t st, const SysDesc* sd, const int32_t* sys_ids, 
 
 // PCG
 void launch_cg_init(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32);
-void launch_cg_spmv(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int it, double tol2, int fp32,
-                    int lpr);
-void launch_cg_update(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int it, int fp32);
+// `one`: non-null when the launch covers a single system, whose descriptor
+// is then passed by value and whose tiles are implicit.
+void launch_cg_spmv(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, int lpr,
+                    const SysDesc* one);
+void launch_cg_update(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, const SysDesc* one);
 void launch_cg_finish(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32);
 void launch_spmv_plain(hipStream_t st, const int32_t* rowptr, const int32_t* colidx, const double* vals, int nnzb,
                        int n, const double* v, double* y);

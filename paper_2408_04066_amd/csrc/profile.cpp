@@ -17,7 +17,8 @@ static hipEvent_t get_event(mfs_context* c) {
   return e;
 }
 
-ProfScope::ProfScope(mfs_context* ctx, int family) : c(ctx), fam(family) {
+ProfScope::ProfScope(mfs_context* ctx, int family, double algorithmic_bytes)
+    : c(ctx), fam(family), bytes(algorithmic_bytes) {
   const int64_t k = c->prof_launches[fam]++;
   if (c->prof_stride > 0 && k % c->prof_stride == 0) {
     a = get_event(c);
@@ -36,7 +37,7 @@ ProfScope::~ProfScope() {
     if (b) c->ev_pool.push_back(b);
     return;
   }
-  c->pending.push_back(ProfPending{fam, a, b});
+  c->pending.push_back(ProfPending{fam, bytes, a, b});
 }
 
 void prof_resolve(mfs_context* c) {
@@ -45,6 +46,7 @@ void prof_resolve(mfs_context* c) {
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       c->prof_ms[p.fam] += ms;
       c->prof_timed[p.fam]++;
+      c->prof_bytes[p.fam] += p.bytes;
     }
     c->ev_pool.push_back(p.a);
     c->ev_pool.push_back(p.b);
@@ -55,6 +57,7 @@ void prof_resolve(mfs_context* c) {
 }  // namespace mfs
 
 mfs_context::~mfs_context() {
+  for (const mfs::CgGraph& g : graphs) (void)hipGraphExecDestroy(g.exec);
   for (const mfs::ProfPending& p : pending) {
     (void)hipEventDestroy(p.a);
     (void)hipEventDestroy(p.b);
@@ -75,6 +78,7 @@ extern "C" int mfs_profile_enable(mfs_context* ctx, int32_t stride) {
     std::memset(ctx->prof_ms, 0, sizeof ctx->prof_ms);
     std::memset(ctx->prof_timed, 0, sizeof ctx->prof_timed);
     std::memset(ctx->prof_launches, 0, sizeof ctx->prof_launches);
+    std::memset(ctx->prof_bytes, 0, sizeof ctx->prof_bytes);
   }
   return MFS_OK;
 }
@@ -89,11 +93,13 @@ extern "C" int mfs_profile_read(mfs_context* ctx, mfs_profile* out, int32_t rese
     out->gpu_ms[f] = ctx->prof_ms[f];
     out->timed[f] = ctx->prof_timed[f];
     out->launches[f] = ctx->prof_launches[f];
+    out->bytes[f] = ctx->prof_bytes[f];
   }
   if (reset) {
     std::memset(ctx->prof_ms, 0, sizeof ctx->prof_ms);
     std::memset(ctx->prof_timed, 0, sizeof ctx->prof_timed);
     std::memset(ctx->prof_launches, 0, sizeof ctx->prof_launches);
+    std::memset(ctx->prof_bytes, 0, sizeof ctx->prof_bytes);
   }
   return MFS_OK;
 }

@@ -66,6 +66,9 @@ struct HostSys {
   double E = INFINITY;
   bool E_known = false;
   double grad = NAN, step = NAN, relres = NAN;
+  // PCG residual history (run sizing)
+  double rho_prev = -1.0;
+  int it_prev = 0;
   // line search
   bool searching = false;
   double alpha = 0.0;
@@ -97,8 +100,9 @@ int build_tiles(mfs_context* ctx, const std::vector<HostSys>& sys, const std::ve
       const mfs_character* c = sys[i].ch;
       const int total_items = kind == kVert ? c->n : (kind == kTet ? c->m : c->nnzb);
       const int nt = kind == kVert ? c->ntv : (kind == kTet ? c->ntt : c->nts);
+      const int size = kind == kVert ? kVTile : (kind == kTet ? kTTile : kSTile);
       for (int j = 0; j < nt; ++j) {
-        h[pos++] = Tile{i, j * kTile, std::min(total_items, (j + 1) * kTile), j};
+        h[pos++] = Tile{i, j * size, std::min(total_items, (j + 1) * size), j};
         counts[kind]++;
       }
     }
@@ -128,8 +132,72 @@ int upload_ctrl(mfs_context* ctx, int count) {
 int read_flags(mfs_context* ctx, int count) {
   MFS_HIP(hipMemcpyAsync(ctx->h_flags.p, ctx->flags.p, count * F_COUNT * sizeof(int32_t), hipMemcpyDeviceToHost,
                          ctx->stream));
+  MFS_HIP(hipMemcpyAsync(ctx->h_cgres.p, ctx->cgres.p, count * 2 * sizeof(double), hipMemcpyDeviceToHost,
+                         ctx->stream));
   MFS_HIP(hipStreamSynchronize(ctx->stream));
   prof_resolve(ctx);
+  return MFS_OK;
+}
+
+// A run of PCG iterations captured once as a HIP graph per (tiles, sizes,
+// tolerance, precision) and replayed; the kernels take no per-iteration
+// arguments (the iteration index lives in device memory).
+int cg_graph(mfs_context* ctx, const SysDesc* sd, const TileSet& ts, int fp32, int iters, const SysDesc* one,
+             hipGraphExec_t* out) {
+  for (CgGraph& g : ctx->graphs) {
+    if (g.sd == sd && g.tiles == ts.dv && g.ntv == ts.nv && g.fp32 == fp32 &&
+        g.lpr == ctx->lpr && g.iters == iters && g.has_one == (one != nullptr) &&
+        (!one || std::memcmp(&g.one, one, sizeof(SysDesc)) == 0)) {
+      *out = g.exec;
+      return MFS_OK;
+    }
+  }
+  hipGraph_t graph = nullptr;
+  MFS_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  for (int j = 0; j < iters; ++j) {
+    launch_cg_spmv(ctx->stream, sd, ts.dv, ts.nv, fp32, ctx->lpr, one);
+    launch_cg_update(ctx->stream, sd, ts.dv, ts.nv, fp32, one);
+  }
+  MFS_HIP(hipStreamEndCapture(ctx->stream, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return set_error(MFS_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  if (ctx->graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+    ctx->graphs.erase(ctx->graphs.begin());
+  }
+  CgGraph g{sd, ts.dv, ts.nv, fp32, ctx->lpr, iters, one != nullptr, SysDesc{}, exec};
+  if (one) g.one = *one;
+  ctx->graphs.push_back(g);
+  *out = exec;
+  return MFS_OK;
+}
+
+// Enqueue `run` PCG iterations: replayed graphs when enabled and the
+// profiler is off, direct launches (each family timed by the profiler)
+// otherwise.
+int run_cg(mfs_context* ctx, const SysDesc* sd, const TileSet& ts, int fp32, int run, const SysDesc* one,
+           double spmv_bytes) {
+  const int G = ctx->graph_iters;
+  int done = 0;
+  if (ctx->use_graphs && ctx->prof_stride == 0 && G > 0) {
+    hipGraphExec_t exec;
+    MFS_TRY(cg_graph(ctx, sd, ts, fp32, G, one, &exec));
+    for (; done + G <= run; done += G) {
+      MFS_HIP(hipGraphLaunch(exec, ctx->stream));
+      ctx->prof_launches[MFS_K_SPMV] += G;
+      ctx->prof_launches[MFS_K_CG_UPDATE] += G;
+    }
+  }
+  for (; done < run; ++done) {
+    {
+      ProfScope ps(ctx, MFS_K_SPMV, spmv_bytes);
+      launch_cg_spmv(ctx->stream, sd, ts.dv, ts.nv, fp32, ctx->lpr, one);
+    }
+    ProfScope ps(ctx, MFS_K_CG_UPDATE);
+    launch_cg_update(ctx->stream, sd, ts.dv, ts.nv, fp32, one);
+  }
   return MFS_OK;
 }
 
@@ -178,13 +246,17 @@ int solve_systems(mfs_context* ctx, int count, mfs_character* const* chars, cons
   MFS_TRY(ctx->h_ctrl.reserve(count * sizeof(Ctrl)));
   MFS_TRY(ctx->h_flags.reserve(count * F_COUNT * sizeof(int32_t)));
   MFS_TRY(ctx->h_red.reserve(count * P_COUNT * sizeof(double)));
+  MFS_TRY(ctx->cgres.reserve(count * 2 * sizeof(double)));
+  MFS_TRY(ctx->h_cgres.reserve(count * 2 * sizeof(double)));
   MFS_HIP(hipStreamSynchronize(st));  // staging buffers may be reused below
+  std::vector<SysDesc> hd(count);
   {
-    std::vector<SysDesc> hd(count);
     for (int i = 0; i < count; ++i) {
       hd[i] = chars[i]->desc;
       hd[i].flags = ctx->flags.as<int32_t>() + F_COUNT * i;
       hd[i].red = ctx->red.as<double>() + P_COUNT * i;
+      hd[i].cgres = ctx->cgres.as<double>() + 2 * i;
+      hd[i].ctrl = ctx->ctrl.as<Ctrl>() + i;
     }
     MFS_HIP(hipMemcpyAsync(ctx->desc.p, hd.data(), count * sizeof(SysDesc), hipMemcpyHostToDevice, st));
     MFS_HIP(hipStreamSynchronize(st));
@@ -224,7 +296,12 @@ int solve_systems(mfs_context* ctx, int count, mfs_character* const* chars, cons
   MFS_TRY(read_red(ctx, count));
   for (int i = 0; i < count; ++i) sys[i].routed = (int)hr[P_COUNT * i + P_ROUTED];
 
-  const double tol2 = o.cg_tol * o.cg_tol;
+  for (int i = 0; i < count; ++i) {
+    hc[i].cg_tol2 = o.cg_tol * o.cg_tol;
+    hc[i].cg_adaptive = o.cg_adaptive ? 1 : 0;
+    hc[i].cg_g2prev = 0.0;
+    hc[i].cg_eta_min = 0.0;
+  }
   for (int it = 0; it < o.max_newton; ++it) {
     std::vector<int> act;
     for (int i = 0; i < count; ++i)
@@ -242,7 +319,7 @@ int solve_systems(mfs_context* ctx, int count, mfs_character* const* chars, cons
     MFS_TRY(upload_ctrl(ctx, count));
     {
       ProfScope ps(ctx, MFS_K_ELEMENT);
-      launch_element(st, dsd, dctrl, ts.dt, ts.nt);
+      launch_element(st, dsd, dctrl, ts.dt, ts.nt, fp32);
     }
     {
       ProfScope ps(ctx, MFS_K_ASSEMBLE);
@@ -254,23 +331,55 @@ int solve_systems(mfs_context* ctx, int count, mfs_character* const* chars, cons
     }
     MFS_HIP(hipGetLastError());
 
-    // PCG with periodic convergence checks
+    // PCG in runs of iterations; after each run the host reads the
+    // convergence flags and residuals and sizes the next run from the
+    // observed residual decay of the slowest character.
     int cit = 0;
+    int chunk = ctx->cg_first_run;
+    for (int i : act) {
+      sys[i].rho_prev = -1.0;
+      sys[i].it_prev = 0;
+    }
+    const SysDesc* one = act.size() == 1 ? &hd[act[0]] : nullptr;
+    // algorithmic bytes of one SpMV launch over the characters still in PCG
+    // (blocks + column indices + row pointers + 2 gathered inputs and 2
+    // outputs per row), for the profiler's roofline figures
+    const double word = fp32 ? 4.0 : 8.0;
+    auto spmv_bytes = [&]() {
+      double by = 0.0;
+      for (int i : act)
+        if (!hf[F_COUNT * i + F_CG_DONE] || cit == 0)
+          by += chars[i]->nnzb * (9.0 * word + 4.0) + (chars[i]->n + 1) * 4.0 + chars[i]->n * 12.0 * word;
+      return by;
+    };
     while (cit < o.cg_max) {
-      const int chunk = std::min(ctx->cg_check, o.cg_max - cit);
-      for (int j = 0; j < chunk; ++j, ++cit) {
-        {
-          ProfScope ps(ctx, MFS_K_SPMV);
-          launch_cg_spmv(st, dsd, ts.dv, ts.nv, cit, tol2, fp32, ctx->lpr);
-        }
-        ProfScope ps(ctx, MFS_K_CG_UPDATE);
-        launch_cg_update(st, dsd, ts.dv, ts.nv, cit, fp32);
-      }
+      const int run = std::min(chunk, o.cg_max - cit);
+      MFS_TRY(run_cg(ctx, dsd, ts, fp32, run, one, spmv_bytes()));
+      cit += run;
       MFS_HIP(hipGetLastError());
       MFS_TRY(read_flags(ctx, count));
+      const double* hres = ctx->h_cgres.as<double>();
       bool all = true;
-      for (int i : act) all = all && hf[F_COUNT * i + F_CG_DONE] != 0;
+      int need = 0;
+      for (int i : act) {
+        if (hf[F_COUNT * i + F_CG_DONE]) continue;
+        all = false;
+        const double rr = hres[2 * i], bb = hres[2 * i + 1];
+        const double rho = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+        const double tol_i = std::sqrt(pcg_tol2(hc[i], bb));
+        int est = ctx->cg_first_run;
+        HostSys& S = sys[i];
+        if (S.rho_prev > 0.0 && rho > 0.0 && rho < S.rho_prev && cit > S.it_prev) {
+          const double rate = std::pow(rho / S.rho_prev, 1.0 / (cit - S.it_prev));
+          const double left = std::log(tol_i / rho) / std::log(rate);
+          est = (int)std::ceil(1.1 * left) + 2;
+        }
+        S.rho_prev = rho;
+        S.it_prev = cit;
+        need = std::max(need, est);
+      }
       if (all) break;
+      chunk = std::min(std::max(need, ctx->cg_min_run), ctx->cg_max_run);
     }
     for (int i : act) {
       if (hf[F_COUNT * i + F_CG_DONE]) {
@@ -317,6 +426,11 @@ int solve_systems(mfs_context* ctx, int count, mfs_character* const* chars, cons
         HostSys& S = sys[i];
         const double* rd = hr + P_COUNT * i;
         if (first_pass) {
+          // forcing state for the next Newton step (Eisenstat-Walker safeguard)
+          const double eta = std::sqrt(pcg_tol2(hc[i], rd[P_BB]));
+          const double sg = 0.9 * eta * eta;
+          hc[i].cg_eta_min = sg > 0.1 ? sg : 0.0;
+          hc[i].cg_g2prev = rd[P_BB];
           S.grad = std::sqrt(rd[P_BB]);
           S.relres = rd[P_BB] > 0.0 ? std::sqrt(rd[P_RR] / rd[P_BB]) : 0.0;
           S.clamped = (int)rd[P_CLAMP];
@@ -515,12 +629,15 @@ extern "C" int mfs_evaluate(mfs_character* ch, const double* handle_R, const dou
   MFS_TRY(ctx->ctrl.reserve(sizeof(Ctrl)));
   MFS_TRY(ctx->flags.reserve(F_COUNT * sizeof(int32_t)));
   MFS_TRY(ctx->red.reserve(P_COUNT * sizeof(double)));
+  MFS_TRY(ctx->cgres.reserve(2 * sizeof(double)));
   MFS_TRY(ctx->h_ctrl.reserve(sizeof(Ctrl)));
   MFS_TRY(ctx->h_red.reserve(P_COUNT * sizeof(double)));
   MFS_HIP(hipStreamSynchronize(st));
   SysDesc hd = ch->desc;
   hd.flags = ctx->flags.as<int32_t>();
   hd.red = ctx->red.as<double>();
+  hd.cgres = ctx->cgres.as<double>();
+  hd.ctrl = ctx->ctrl.as<Ctrl>();
   MFS_HIP(hipMemcpyAsync(ctx->desc.p, &hd, sizeof(SysDesc), hipMemcpyHostToDevice, st));
   MFS_TRY(upload_pose(ch, handle_R, handle_t));
   double* tmp = ctx->tmp.as<double>();
@@ -541,7 +658,7 @@ extern "C" int mfs_evaluate(mfs_character* ch, const double* handle_R, const dou
   MFS_TRY(upload_ctrl(ctx, 1));
   const SysDesc* dsd = ctx->desc.as<SysDesc>();
   const Ctrl* dctrl = ctx->ctrl.as<Ctrl>();
-  launch_element(st, dsd, dctrl, ts.dt, ts.nt);
+  launch_element(st, dsd, dctrl, ts.dt, ts.nt, 0);
   launch_assemble(st, dsd, ts.ds, ts.ns, 0);
   MFS_HIP(hipMemsetAsync(ch->dx.p, 0, n3, st));
   launch_linesearch(st, dsd, dctrl, ts.dt, ts.nt, ts.dv, ts.nv);

@@ -209,3 +209,63 @@ def test_batch_equals_alone(ctx):
         assert np.array_equal(a, b)
     for ch in chars:
         ch.close()
+
+
+def test_graph_replay_and_lane_counts(ctx):
+    """Replayed PCG graphs give bitwise the same frame as direct launches;
+    other SpMV lane counts agree to the FP64 tolerance."""
+    mfs = _mfs()
+    prob = _small_humanoid(31, 3000, 12)
+    pose = random_pose(prob, 32)
+    ch = mfs.Character(ctx, prob)
+    base = ctx.tuning()
+    try:
+        _say("solve: graphs on")
+        ctx.set_tuning(use_graphs=1, graph_iterations=8)
+        xg, _, rc = ch.solve(*pose)
+        assert rc == 0
+        _say("solve: graphs off")
+        ctx.set_tuning(use_graphs=0)
+        xd, _, rc = ch.solve(*pose)
+        assert rc == 0
+        assert np.array_equal(xg, xd)
+        for lpr in (2, 8):
+            _say(f"solve: lanes per row {lpr}")
+            ctx.set_tuning(use_graphs=1, pcg_lanes_per_row=lpr)
+            xl, _, rc = ch.solve(*pose)
+            assert rc == 0
+            assert _err(xl, xd, prob) <= 1e-9
+    finally:
+        ctx.set_tuning(**base)
+        ch.close()
+
+
+def test_full_size_humanoid_matches_golden(ctx):
+    """~50k-tet humanoid at its benchmark launch shape: FP64 within 1e-9 and
+    FP32 + refinement within 1e-7 of the oracle's stored solution."""
+    import os
+    mfs = _mfs()
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, os.path.join(here, "golden"))
+    from make_golden import input_hash
+    g = np.load(os.path.join(here, "golden", "humanoid50k_pose2002.npz"))
+    prob = humanoid(2001, target_tets=50000, n_bones=20)
+    pose = random_pose(prob, 2002)
+    assert str(g["input_hash"]) == input_hash(prob, pose), "rebuilt inputs differ from the golden's"
+    ch = mfs.Character(ctx, prob)
+    _say("solve: humanoid 50k FP64")
+    x64, st, rc = ch.solve(*pose, precision=mfs.FP64, cg_tol=1e-10, step_tol=1e-10, max_newton=60)
+    _say(f"  stats {st} err/bbox={_err(x64, g['x'], prob):.3e}")
+    assert rc == 0 and _err(x64, g["x"], prob) <= 1e-9
+    _say("solve: humanoid 50k FP32 + refinement")
+    x32, st, rc = ch.solve(*pose, precision=mfs.FP32_REFINED, cg_tol=1e-5, step_tol=1e-8, max_newton=60)
+    _say(f"  stats {st} err/bbox={_err(x32, g['x'], prob):.3e}")
+    assert rc == 0 and _err(x32, g["x"], prob) <= 1e-7
+    # the benchmark's configuration: inexact Newton with Eisenstat-Walker forcing
+    for prec in (mfs.FP32_REFINED, mfs.FP64):
+        _say(f"solve: humanoid 50k precision {prec}, adaptive PCG tolerance")
+        xa, st, rc = ch.solve(*pose, precision=prec, cg_tol=1e-5, step_tol=1e-8, max_newton=60,
+                              cg_adaptive=1)
+        _say(f"  stats {st} err/bbox={_err(xa, g['x'], prob):.3e}")
+        assert rc == 0 and _err(xa, g["x"], prob) <= 1e-7
+    ch.close()
