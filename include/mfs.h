@@ -100,9 +100,19 @@ typedef struct mfs_solve_opts {
   int32_t cg_max;           /* PCG iteration cap per solve */
   int32_t warm_start;       /* enum mfs_warm_start */
   int32_t output_memory;    /* enum mfs_memory of x_out */
-  int32_t cg_adaptive;      /* 1: inexact Newton, each PCG solve stops at
+  int32_t cg_adaptive;      /* 1: inexact Newton: once s = J x, each PCG solve stops at
                                max(cg_tol, eta_k) with the Eisenstat-Walker forcing
-                               eta_k = min(0.1, 0.9 (|g_k| / |g_k-1|)^2) */
+                               eta_k = min(0.1, 0.9 (|g_k| / |g_k-1|)^2); mixed-phase
+                               solves keep cg_tol */
+  int32_t load_bisections;  /* robustness for large poses (0: off): when the mixed phase
+                               stalls (more than 6 mixed steps, or no feasible step),
+                               return to the last converged state and approach the pose
+                               through intermediate poses -- each handle's screw motion
+                               T(tau) = T0 exp(tau log(T0^-1 T1)) in SE(3) from the
+                               warm-start pose T0 to the target T1 -- halving the increment
+                               at most this many times and doubling it after each
+                               intermediate pose converges (to a 1e-4 * bbox step) */
+  int32_t reserved;
 } mfs_solve_opts;
 
 typedef struct mfs_solve_stats {
@@ -124,7 +134,8 @@ typedef struct mfs_solve_stats {
 
 /* Fill *opts with the defaults: FP64, max_newton 50, fixed_newton 0,
  * step_tol 1e-10, cg_tol 1e-10, cg_max 20000, warm start REST, host output,
- * fixed PCG tolerance (cg_adaptive 0). */
+ * fixed PCG tolerance (cg_adaptive 0), load_bisections 6 (ignored when
+ * fixed_newton is set). */
 void mfs_default_opts(mfs_solve_opts* opts);
 
 /* Text for a status code (static storage). */

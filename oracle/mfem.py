@@ -49,6 +49,7 @@ Readings taken where the paper is silent, garbled or inconsistent:
       only feasibility when E(x0) = +inf, else E(x1) <= E(x0) + 1e-12 |E(x0)|.
   R11 Stop after a fixed iteration count (predictor counts as iteration 1),
       or when max_v ||alpha dx_v|| <= step_tol * bbox_diag.
+  R12 Load stepping for poses whose mixed phase stalls (see solve_frame).
 """
 
 import numpy as np
@@ -407,8 +408,41 @@ def _linear_solve(K, b, method):
     return spla.splu(K.tocsc()).solve(b)
 
 
+def _se3_V(w):
+    """V(w) = I + (1 - cos th)/th^2 [w] + (th - sin th)/th^3 [w]^2 (SE(3) exp)."""
+    th = np.linalg.norm(w)
+    K = np.array([[0.0, -w[2], w[1]], [w[2], 0.0, -w[0]], [-w[1], w[0], 0.0]])
+    if th < 1e-8:
+        return np.eye(3) + 0.5 * K
+    return np.eye(3) + (1 - np.cos(th)) / th ** 2 * K + (th - np.sin(th)) / th ** 3 * (K @ K)
+
+
+def interpolate_pose(pose0, pose1, tau):
+    """Handle transforms a fraction tau of the way from pose0 to pose1 along
+    each handle's screw motion: T(tau) = T0 exp(tau log(T0^-1 T1)) in SE(3)
+    (a rotation about a fixed joint keeps that joint fixed); tau = 1 gives
+    pose1 exactly."""
+    from scipy.spatial.transform import Rotation
+    R0, t0 = (np.asarray(a, dtype=np.float64) for a in pose0)
+    R1, t1 = (np.asarray(a, dtype=np.float64) for a in pose1)
+    if tau >= 1.0:
+        return R1.copy(), t1.copy()
+    R = np.empty_like(R1)
+    t = np.empty_like(t1)
+    for h in range(R1.shape[0]):
+        Rr = R0[h].T @ R1[h]
+        tr = R0[h].T @ (t1[h] - t0[h])
+        w = Rotation.from_matrix(Rr).as_rotvec()
+        v = np.linalg.solve(_se3_V(w), tr)
+        Re = Rotation.from_rotvec(tau * w).as_matrix()
+        te = _se3_V(tau * w) @ (tau * v)
+        R[h] = R0[h] @ Re
+        t[h] = R0[h] @ te + t0[h]
+    return R, t
+
+
 def solve_frame(prob, pose, x0=None, iterations=None, max_iterations=50, step_tol=1e-12,
-                linear_solver="splu", frame=None):
+                linear_solver="splu", frame=None, load_bisections=6, pose0=None):
     """One frame of Algorithm 1 as a Newton iteration on the mixed problem.
 
     State: vertex positions x and per-element stretches s (the mixed variable
@@ -427,30 +461,58 @@ def solve_frame(prob, pose, x0=None, iterations=None, max_iterations=50, step_to
     co-rotated elements the first step is already the optimum (end of
     Section 3).
 
+    Load stepping (reading R12, not in the paper; off for a fixed iteration
+    count): if the mixed phase of a load step takes more than 6 steps or no
+    step is feasible, x returns to the last converged state and the pose is
+    approached through intermediate poses (``interpolate_pose``: screw
+    motion of each handle from ``pose0``, the identity pose by default, whose
+    solution is the rest shape); the increment is halved at most
+    ``load_bisections`` times and doubled after each intermediate pose
+    converges to a 1e-4 * bbox step.
+
     Returns a dict with the final positions ``x`` (n, 3), the final stretches
-    ``s`` (m, 6), per-iteration energies E(x) (+inf where infeasible),
-    gradient norms, step lengths, step sizes and phases, the iteration count,
-    the number of clamped neo-Hookean elements per iteration, and ``status``
-    ("ok" or "not_converged").
+    ``s`` (m, 6), per-iteration energies E(x) (+inf where infeasible) of the
+    pose being solved, gradient norms, step lengths, step sizes, phases and
+    load-step fractions, the iteration count, the number of clamped
+    neo-Hookean elements per iteration, and ``status`` ("ok" or
+    "not_converged").
     """
+    nh = int(prob["n_handles"])
+    if pose0 is None:
+        pose0 = (np.tile(np.eye(3), (nh, 1, 1)), np.zeros((nh, 3)))
+    loadstep = load_bisections > 0 and iterations is None
     fr = frame if frame is not None else Frame(prob, pose)
     x = (fr.X if x0 is None else np.asarray(x0, dtype=np.float64)).reshape(-1).copy()
+    x_backup = x.copy()
+    tau, tau_done, delta, bisections, load_mixed = 1.0, 0.0, 1.0, 0, 0
     s = polar_stretch(fr.deformation_gradient(x))
     s0 = s.copy()
     on_constraint = False
-    nh = fr.model == NH
-    hist = {"energy": [], "grad_norm": [], "alpha": [], "step": [], "clamped": [], "phase": []}
+    nh_mask = fr.model == NH
+    hist = {"energy": [], "grad_norm": [], "alpha": [], "step": [], "clamped": [], "phase": [],
+            "tau": []}
     status = "ok"
     n_iter = iterations if iterations is not None else max_iterations
-    it = 0
+    converged = False
+
+    def restart(new_tau):
+        nonlocal fr, x, s, on_constraint, load_mixed, tau
+        tau = new_tau
+        fr = Frame(prob, interpolate_pose(pose0, pose, tau), clusters=fr.cluster)
+        x = x_backup.copy()
+        s = polar_stretch(fr.deformation_gradient(x))
+        on_constraint = False
+        load_mixed = 0
+
+    it = -1
     for it in range(n_iter):
         E0 = fr.energy(x)
         grad = fr.gradient(x) if np.isfinite(E0) else None
         rhs = -fr.gradient(x, s_lin=s)
         K = fr.hessian(s)
-        if np.any(nh):
+        if np.any(nh_mask):
             _, _, lnJ = _nh_parts(unvech(s), fr.model)
-            hist["clamped"].append(int(np.sum(nh & (fr.mu - fr.lam * lnJ < 0))))
+            hist["clamped"].append(int(np.sum(nh_mask & (fr.mu - fr.lam * lnJ < 0))))
         else:
             hist["clamped"].append(0)
         dx = _linear_solve(K, rhs, linear_solver)
@@ -458,6 +520,7 @@ def solve_frame(prob, pose, x0=None, iterations=None, max_iterations=50, step_to
         hist["energy"].append(E0)
         hist["grad_norm"].append(float(np.linalg.norm(grad)) if grad is not None else float("inf"))
         hist["phase"].append("newton" if on_constraint else "mixed")
+        hist["tau"].append(tau)
         alpha, accepted = 1.0, False
         for _ in range(41):
             if on_constraint:
@@ -466,10 +529,21 @@ def solve_frame(prob, pose, x0=None, iterations=None, max_iterations=50, step_to
                     Et <= E0 + 1e-4 * alpha * float(grad @ dx) + 1e-12 * abs(E0))
             else:
                 st = s + alpha * ds
-                accepted = bool(np.all(_spd(unvech(st[nh])))) if np.any(nh) else True
+                accepted = bool(np.all(_spd(unvech(st[nh_mask])))) if np.any(nh_mask) else True
             if accepted:
                 break
             alpha *= 0.5
+        was_newton = on_constraint
+        if not was_newton:
+            load_mixed += 1
+        stalled = (not accepted) or (not was_newton and alpha < 1.0 and load_mixed > 6)
+        if stalled and loadstep and bisections < load_bisections and it + 1 < n_iter:
+            bisections += 1
+            delta *= 0.5
+            hist["alpha"].append(0.0)
+            hist["step"].append(0.0)
+            restart(tau_done + delta)
+            continue
         if not accepted:
             status = "not_converged"
             hist["alpha"].append(0.0)
@@ -484,12 +558,18 @@ def solve_frame(prob, pose, x0=None, iterations=None, max_iterations=50, step_to
         step = float(np.max(np.linalg.norm((alpha * dx).reshape(-1, 3), axis=1)))
         hist["alpha"].append(alpha)
         hist["step"].append(step)
-        if (iterations is None and on_constraint and hist["phase"][-1] == "newton"
-                and step <= step_tol * fr.bbox_diag):
-            break
-    else:
-        if iterations is None or not on_constraint:
-            status = "not_converged"
+        if iterations is None and was_newton:
+            tol = step_tol if tau >= 1.0 else 1e-4
+            if step <= tol * fr.bbox_diag:
+                if tau >= 1.0:
+                    converged = True
+                    break
+                x_backup = x.copy()
+                tau_done = tau
+                delta *= 2.0
+                restart(min(1.0, tau_done + delta))
+    if iterations is None and not converged and status == "ok":
+        status = "not_converged"
     Ef = fr.energy(x)
     hist["energy"].append(Ef)
     hist["grad_norm"].append(float(np.linalg.norm(fr.gradient(x))) if np.isfinite(Ef)

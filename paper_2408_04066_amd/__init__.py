@@ -60,7 +60,8 @@ class MeshDesc(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("precision", c_i32), ("max_newton", c_i32), ("fixed_newton", c_i32),
                 ("step_tol", c_dbl), ("cg_tol", c_dbl), ("cg_max", c_i32), ("warm_start", c_i32),
-                ("output_memory", c_i32), ("cg_adaptive", c_i32)]
+                ("output_memory", c_i32), ("cg_adaptive", c_i32), ("load_bisections", c_i32),
+                ("reserved", c_i32)]
 
 
 class SolveStats(ctypes.Structure):

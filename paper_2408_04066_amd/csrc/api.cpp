@@ -22,6 +22,8 @@ extern "C" void mfs_default_opts(mfs_solve_opts* o) {
   o->cg_max = 20000;
   o->warm_start = MFS_WARM_REST;
   o->output_memory = MFS_MEM_HOST;
+  o->cg_adaptive = 0;
+  o->load_bisections = 6;
 }
 
 extern "C" const char* mfs_status_string(int s) {

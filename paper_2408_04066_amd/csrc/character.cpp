@@ -421,6 +421,7 @@ extern "C" int mfs_character_create(mfs_context* ctx, const mfs_mesh_desc* d, mf
   MFS_TRY(ch->Rh.alloc(9 * sizeof(double) * kMaxHandles));
   MFS_TRY(ch->th.alloc(3 * sizeof(double) * kMaxHandles));
   MFS_TRY(ch->x.alloc(n3));
+  MFS_TRY(ch->xb.alloc(n3));
   MFS_TRY(ch->s.alloc(6 * sizeof(double) * (size_t)m));
   MFS_TRY(ch->blk.alloc(90 * sizeof(double) * (size_t)m));
   MFS_TRY(ch->frc.alloc(12 * sizeof(double) * (size_t)m));
@@ -435,7 +436,6 @@ extern "C" int mfs_character_create(mfs_context* ctx, const mfs_mesh_desc* d, mf
   MFS_TRY(ch->q.alloc(n3));
   MFS_TRY(ch->xc.alloc(n3));
   MFS_TRY(ch->part.alloc(sizeof(double) * P_COUNT * (size_t)ch->ptile));
-  MFS_TRY(ch->flags.alloc(sizeof(int32_t) * F_COUNT));
   MFS_TRY(ch->red.alloc(sizeof(double) * P_COUNT));
   MFS_HIP(hipMemcpyAsync(ch->x.p, ch->X.p, n3, hipMemcpyDeviceToDevice, ctx->stream));
   MFS_HIP(hipStreamSynchronize(ctx->stream));
@@ -450,6 +450,7 @@ extern "C" int mfs_character_create(mfs_context* ctx, const mfs_mesh_desc* d, mf
   s.ntt = ch->ntt;
   s.nts = ch->nts;
   s.ptile = ch->ptile;
+  s.ticket = ch->ntv > kAllReadTiles ? 1 : 0;
   s.ks = ch->ks;
   s.tets = ch->tets.as<int4>();
   s.G = ch->G.as<double>();
@@ -481,16 +482,14 @@ extern "C" int mfs_character_create(mfs_context* ctx, const mfs_mesh_desc* d, mf
   s.q = ch->q.p;
   s.xc = ch->xc.p;
   s.part = ch->part.as<double>();
-  s.flags = ch->flags.as<int32_t>();
   s.red = ch->red.as<double>();
 
   ch->resident_bytes = ch->tets.bytes + ch->G.bytes + ch->wmu.bytes + ch->wlam.bytes + ch->info.bytes + ch->X.bytes +
                        ch->rowptr.bytes + ch->colidx.bytes + ch->slot_ptr.bytes + ch->contrib.bytes +
                        ch->diag.bytes + ch->vpin_ptr.bytes + ch->vpin_h.bytes + ch->perm_d.bytes +
-                       ch->tperm_d.bytes + ch->x.bytes + ch->s.bytes + ch->Rh.bytes + ch->th.bytes;
+                       ch->tperm_d.bytes + ch->x.bytes + ch->xb.bytes + ch->s.bytes + ch->Rh.bytes + ch->th.bytes;
   ch->workspace_bytes = ch->blk.bytes + ch->frc.bytes + ch->b.bytes + ch->dx.bytes + ch->vals.bytes + ch->minv.bytes + ch->r.bytes +
-                        ch->z.bytes + ch->p0.bytes + ch->p1.bytes + ch->q.bytes + ch->xc.bytes + ch->part.bytes +
-                        ch->flags.bytes + ch->red.bytes;
+                        ch->z.bytes + ch->p0.bytes + ch->p1.bytes + ch->q.bytes + ch->xc.bytes + ch->part.bytes + ch->red.bytes;
   *out = guard.release();
   return MFS_OK;
 }

@@ -38,13 +38,32 @@ enum PartSlot : int {
   P_COUNT = 10 + 3 * kNumTrials
 };
 
-// Per-system integer flags (SysDesc::flags).
-enum FlagSlot : int {
-  F_CG_DONE = 0,   // PCG converged
-  F_CG_ITERS = 1,  // PCG iterations at convergence
-  F_IT_A = 2,      // PCG iteration index read by the SpMV kernel (written by the update kernel)
-  F_IT_B = 3,      // PCG iteration index read by the update kernel (written by the SpMV kernel)
-  F_COUNT = 4
+// Per-system PCG scalars.  Every PCG kernel ends with an arrival ticket:
+// the last workgroup of a system to finish folds that system's per-tile
+// partials in a fixed order and writes the sums here, so the next kernel
+// reads a few scalars instead of every tile's partial.  Each field is written
+// only by that last workgroup, after every workgroup of the system has read
+// the old values.
+//
+// Systems with at most kAllReadTiles vertex tiles skip the tickets (whose
+// release fence costs a few microseconds per workgroup): there every
+// workgroup folds the few partials itself ("all-read" mode) and the
+// iteration index is double-buffered in it_a / it_b (each written only by
+// the other kernel of the PCG pair).
+constexpr int kAllReadTiles = 256;
+
+struct CgState {
+  double rz;       // r . z of the current iterate (ticket mode)
+  double rz_prev;  // r . z of the previous iterate (ticket mode; beta = rz / rz_prev)
+  double rr;       // r . r of the current iterate (both modes; for the host)
+  double bb;       // b . b (both modes)
+  double pq;       // p . K p of the last SpMV (ticket mode)
+  int32_t it;      // iterations completed (ticket mode)
+  int32_t done;    // 1 once r . r <= tol^2 b . b
+  int32_t iters;   // iterations at convergence
+  uint32_t arrive_init, arrive_spmv, arrive_update;  // arrival tickets (0 between kernels)
+  int32_t it_a;    // all-read mode: iteration index read by the SpMV kernel
+  int32_t it_b;    // all-read mode: iteration index read by the update kernel
 };
 
 // Per-system control block, written by the host driver each iteration.
@@ -90,6 +109,8 @@ struct Tile {
 struct SysDesc {
   int32_t n, m, nnzb, nh;
   int32_t ntv, ntt, nts, ptile;   // tiles per system: vertex, tet, slot; partial stride
+  int32_t ticket;                 // PCG reductions by arrival ticket (ntv > kAllReadTiles)
+  int32_t pad0;
   double ks;                      // pin stiffness
   // resident (reordered) mesh data
   const int4* tets;        // m
@@ -126,9 +147,8 @@ struct SysDesc {
   void* xc;      // PCG iterate
   // reductions
   double* part;  // P_COUNT planes of ptile
-  int32_t* flags;
-  double* red;   // P_COUNT per-system results
-  double* cgres; // 2: r.r and b.b as of the last PCG iteration
+  double* red;   // P_COUNT per-system results of the finalize kernel
+  CgState* cg;   // PCG scalars of this system
   const Ctrl* ctrl;  // this system's control block (per-step PCG tolerance)
 };
 
@@ -185,6 +205,33 @@ __device__ __forceinline__ double block_max(double v, double* lds4) {
 __device__ __forceinline__ double sys_sum(const double* plane, int count) {
   double acc = 0.0;
   for (int i = threadIdx.x & 63; i < count; i += 64) acc += plane[i];
+  return wave_sum(acc);
+}
+
+// Arrival ticket at the end of a kernel: thread 0 has stored this
+// workgroup's partial; returns true (in every thread) in the workgroup that
+// arrives last among `count`.  The release fence orders the partial store
+// before the ticket; the last workgroup then reads the partials coherently.
+__device__ __forceinline__ bool last_arrival(uint32_t* ticket, uint32_t count, int* lds_flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t t = atomicAdd(ticket, 1u);
+    *lds_flag = (t == count - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  const bool last = *lds_flag != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+// Fixed-order sum of one partial plane with device-coherent loads (the
+// partials were written by other workgroups of the running kernel, possibly
+// on other XCDs).  Lane l adds entries l, l + 64, ...; then the butterfly.
+__device__ __forceinline__ double coherent_sum(const double* plane, int count) {
+  double acc = 0.0;
+  for (int i = threadIdx.x & 63; i < count; i += 64)
+    acc += __hip_atomic_load(plane + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return wave_sum(acc);
 }
 

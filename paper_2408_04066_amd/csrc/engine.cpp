@@ -1,0 +1,725 @@
+// Batch engine: one Newton iteration per step() over the occupied slots.
+//
+// Iteration (state x, s; s is the mixed stretch variable of the paper's
+// Section 3):
+//   solve K(s) dx = -[grad C(x) + sum_k W_k J_k^T (g_k(s) + H_k(s)(J_k x - s_k))]
+//   mixed phase (s != J x): alpha = the step the worst neo-Hookean tet allows
+//     along s + alpha (J(x + dx) - s) while staying positive definite
+//     (halvings of 1); s <- s + alpha (J(x + dx) - s); alpha = 1 lands on the
+//     constraint s = J x and starts the Newton phase.
+//   Newton phase (s = J x): Armijo on E, E(x + a dx) <= E(x) + 1e-4 a gradE.dx
+//     + 1e-12 |E(x)|, with every neo-Hookean stretch positive definite.
+//   stop: fixed iteration count, or a Newton-phase step with
+//     max_v |alpha dx_v| <= step_tol * bbox diagonal.
+// The host reads back only per-slot scalars: PCG flags and residuals after
+// each run of PCG iterations, and the line-search reductions.
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "launch.h"
+
+namespace mfs {
+
+int upload_ctrl(mfs_context* ctx, int count) {
+  MFS_HIP(hipMemcpyAsync(ctx->ctrl.p, ctx->h_ctrl.p, count * sizeof(Ctrl), hipMemcpyHostToDevice, ctx->stream));
+  return MFS_OK;
+}
+
+int read_cg(mfs_context* ctx, int count) {
+  MFS_HIP(hipMemcpyAsync(ctx->h_cg.p, ctx->cg.p, count * sizeof(CgState), hipMemcpyDeviceToHost, ctx->stream));
+  MFS_HIP(hipStreamSynchronize(ctx->stream));
+  prof_resolve(ctx);
+  return MFS_OK;
+}
+
+int read_red(mfs_context* ctx, int count) {
+  MFS_HIP(hipMemcpyAsync(ctx->h_red.p, ctx->red.p, count * P_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  MFS_HIP(hipStreamSynchronize(ctx->stream));
+  prof_resolve(ctx);
+  return MFS_OK;
+}
+
+int build_tile_list(mfs_context* ctx, const std::vector<mfs_character*>& by_slot, const std::vector<int>& ids,
+                    TileSet* ts) {
+  size_t total = 0;
+  for (int i : ids) total += by_slot[i]->ntv + by_slot[i]->ntt + by_slot[i]->nts;
+  MFS_TRY(ctx->h_tiles.reserve(std::max<size_t>(total, 1) * sizeof(Tile)));
+  MFS_TRY(ctx->tiles.reserve(std::max<size_t>(total, 1) * sizeof(Tile)));
+  Tile* h = ctx->h_tiles.as<Tile>();
+  size_t pos = 0;
+  int counts[3] = {0, 0, 0};
+  for (int kind = 0; kind < 3; ++kind) {
+    for (int i : ids) {
+      const mfs_character* c = by_slot[i];
+      const int items = kind == 0 ? c->n : (kind == 1 ? c->m : c->nnzb);
+      const int nt = kind == 0 ? c->ntv : (kind == 1 ? c->ntt : c->nts);
+      const int size = kind == 0 ? kVTile : (kind == 1 ? kTTile : kSTile);
+      for (int j = 0; j < nt; ++j) {
+        h[pos++] = Tile{i, j * size, std::min(items, (j + 1) * size), j};
+        counts[kind]++;
+      }
+    }
+  }
+  MFS_HIP(hipMemcpyAsync(ctx->tiles.p, h, pos * sizeof(Tile), hipMemcpyHostToDevice, ctx->stream));
+  Tile* d = ctx->tiles.as<Tile>();
+  ts->nv = counts[0];
+  ts->nt = counts[1];
+  ts->ns = counts[2];
+  ts->dv = d;
+  ts->dt = d + counts[0];
+  ts->ds = d + counts[0] + counts[1];
+  MFS_TRY(ctx->sys_ids.reserve(std::max<size_t>(ids.size(), 1) * sizeof(int32_t)));
+  MFS_TRY(ctx->h_stage.reserve(std::max<size_t>(ids.size(), 1) * sizeof(int32_t)));
+  std::memcpy(ctx->h_stage.p, ids.data(), ids.size() * sizeof(int32_t));
+  MFS_HIP(hipMemcpyAsync(ctx->sys_ids.p, ctx->h_stage.p, ids.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                         ctx->stream));
+  return MFS_OK;
+}
+
+// A run of PCG iterations captured once as a HIP graph per (tiles, sizes,
+// precision, launch shape, single-system descriptor) and replayed; the
+// kernels take no per-iteration arguments (the iteration index and the
+// per-step tolerance live in device memory).
+static int cg_graph(mfs_context* ctx, const SysDesc* sd, const TileSet& ts, int fp32, int iters,
+                    const SysDesc* one, hipGraphExec_t* out) {
+  for (CgGraph& g : ctx->graphs) {
+    if (g.sd == sd && g.tiles == ts.dv && g.ntv == ts.nv && g.fp32 == fp32 && g.lpr == ctx->lpr &&
+        g.iters == iters && g.has_one == (one != nullptr) &&
+        (!one || std::memcmp(&g.one, one, sizeof(SysDesc)) == 0)) {
+      *out = g.exec;
+      return MFS_OK;
+    }
+  }
+  hipGraph_t graph = nullptr;
+  MFS_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  for (int j = 0; j < iters; ++j) {
+    launch_cg_spmv(ctx->stream, sd, ts.dv, ts.nv, fp32, ctx->lpr, one);
+    launch_cg_update(ctx->stream, sd, ts.dv, ts.nv, fp32, one);
+  }
+  MFS_HIP(hipStreamEndCapture(ctx->stream, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return set_error(MFS_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  if (ctx->graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+    ctx->graphs.erase(ctx->graphs.begin());
+  }
+  CgGraph g{sd, ts.dv, ts.nv, fp32, ctx->lpr, iters, one != nullptr, SysDesc{}, exec};
+  if (one) g.one = *one;
+  ctx->graphs.push_back(g);
+  *out = exec;
+  return MFS_OK;
+}
+
+// Enqueue `run` PCG iterations: replayed graphs when enabled and the
+// profiler is off, direct launches (each family timed by the profiler)
+// otherwise.
+static int enqueue_cg(mfs_context* ctx, const SysDesc* sd, const TileSet& ts, int fp32, int run,
+                      const SysDesc* one, double spmv_bytes) {
+  const int G = ctx->graph_iters;
+  int done = 0;
+  if (ctx->use_graphs && ctx->prof_stride == 0 && G > 0) {
+    hipGraphExec_t exec;
+    MFS_TRY(cg_graph(ctx, sd, ts, fp32, G, one, &exec));
+    for (; done + G <= run; done += G) {
+      MFS_HIP(hipGraphLaunch(exec, ctx->stream));
+      ctx->prof_launches[MFS_K_SPMV] += G;
+      ctx->prof_launches[MFS_K_CG_UPDATE] += G;
+    }
+  }
+  for (; done < run; ++done) {
+    {
+      ProfScope ps(ctx, MFS_K_SPMV, spmv_bytes);
+      launch_cg_spmv(ctx->stream, sd, ts.dv, ts.nv, fp32, ctx->lpr, one);
+    }
+    ProfScope ps(ctx, MFS_K_CG_UPDATE);
+    launch_cg_update(ctx->stream, sd, ts.dv, ts.nv, fp32, one);
+  }
+  return MFS_OK;
+}
+
+// ---- rigid-motion interpolation of handle poses (load stepping) ----
+
+static void rot_log(const double R[9], double w[3]) {
+  const double c = std::min(1.0, std::max(-1.0, 0.5 * (R[0] + R[4] + R[8] - 1.0)));
+  const double th = std::acos(c);
+  const double v[3] = {R[7] - R[5], R[2] - R[6], R[3] - R[1]};  // 2 sin(th) * axis
+  if (th < 1e-6) {
+    for (int i = 0; i < 3; ++i) w[i] = 0.5 * v[i];
+    return;
+  }
+  if (M_PI - th < 1e-6) {  // axis from (R + I) / 2 = a a^T
+    int k = 0;
+    for (int i = 1; i < 3; ++i)
+      if (R[4 * i] > R[4 * k]) k = i;
+    double a[3];
+    for (int i = 0; i < 3; ++i) a[i] = 0.5 * (R[3 * i + k] + (i == k ? 1.0 : 0.0));
+    const double nrm = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    for (int i = 0; i < 3; ++i) w[i] = th * a[i] / nrm;
+    return;
+  }
+  const double f = th / (2.0 * std::sin(th));
+  for (int i = 0; i < 3; ++i) w[i] = f * v[i];
+}
+
+static void rot_exp(const double w[3], double R[9]) {
+  const double th = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  const double K[9] = {0.0, -w[2], w[1], w[2], 0.0, -w[0], -w[1], w[0], 0.0};
+  double K2[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) K2[3 * i + j] = K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j] + K[3 * i + 2] * K[6 + j];
+  double a = 1.0, b = 0.5;  // sin(th)/th, (1 - cos(th))/th^2
+  if (th > 1e-8) {
+    a = std::sin(th) / th;
+    b = (1.0 - std::cos(th)) / (th * th);
+  }
+  for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0 ? 1.0 : 0.0) + a * K[i] + b * K2[i];
+}
+
+// V(w) = I + (1 - cos th)/th^2 [w] + (th - sin th)/th^3 [w]^2, the
+// translation part of the SE(3) exponential.
+static void se3_V(const double w[3], double V[9]) {
+  const double th = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  const double K[9] = {0.0, -w[2], w[1], w[2], 0.0, -w[0], -w[1], w[0], 0.0};
+  double K2[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) K2[3 * i + j] = K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j] + K[3 * i + 2] * K[6 + j];
+  double a = 0.5, b = 1.0 / 6.0;
+  if (th > 1e-8) {
+    a = (1.0 - std::cos(th)) / (th * th);
+    b = (th - std::sin(th)) / (th * th * th);
+  }
+  for (int i = 0; i < 9; ++i) V[i] = (i % 4 == 0 ? 1.0 : 0.0) + a * K[i] + b * K2[i];
+}
+
+static void solve3(const double A[9], const double b[3], double x[3]) {  // Cramer's rule
+  const double d = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                   A[2] * (A[3] * A[7] - A[4] * A[6]);
+  for (int c = 0; c < 3; ++c) {
+    double M[9];
+    for (int i = 0; i < 9; ++i) M[i] = A[i];
+    for (int r = 0; r < 3; ++r) M[3 * r + c] = b[r];
+    x[c] = (M[0] * (M[4] * M[8] - M[5] * M[7]) - M[1] * (M[3] * M[8] - M[5] * M[6]) +
+            M[2] * (M[3] * M[7] - M[4] * M[6])) / d;
+  }
+}
+
+// Handle transforms a fraction tau of the way from (R0, t0) to (R1, t1)
+// along each handle's screw motion, T(tau) = T0 exp(tau log(T0^-1 T1)) in
+// SE(3): a rotation about a fixed joint keeps the joint fixed on the way.
+int Engine::set_pose(int i, double tau) {
+  SlotState& S = slot_[i];
+  const int nh = S.ch->nh;
+  S.tau = tau;
+  if (tau >= 1.0) {
+    S.Rc = S.R1;
+    S.tc = S.t1;
+  } else {
+    S.Rc.assign(9 * nh, 0.0);
+    S.tc.assign(3 * nh, 0.0);
+    for (int h = 0; h < nh; ++h) {
+      const double* A = &S.R0[9 * h];
+      const double* B = &S.R1[9 * h];
+      const double* a = &S.t0[3 * h];
+      const double* bt = &S.t1[3 * h];
+      double D[9], dt[3], w[3], v[3], V[9], E[9], Vt[9], te[3];
+      for (int r = 0; r < 3; ++r) {  // relative motion: D = A^T B, dt = A^T (t1 - t0)
+        for (int c = 0; c < 3; ++c) D[3 * r + c] = A[r] * B[c] + A[3 + r] * B[3 + c] + A[6 + r] * B[6 + c];
+        dt[r] = A[r] * (bt[0] - a[0]) + A[3 + r] * (bt[1] - a[1]) + A[6 + r] * (bt[2] - a[2]);
+      }
+      rot_log(D, w);
+      se3_V(w, V);
+      solve3(V, dt, v);
+      for (int k = 0; k < 3; ++k) {
+        w[k] *= tau;
+        v[k] *= tau;
+      }
+      rot_exp(w, E);
+      se3_V(w, Vt);
+      for (int r = 0; r < 3; ++r) te[r] = Vt[3 * r] * v[0] + Vt[3 * r + 1] * v[1] + Vt[3 * r + 2] * v[2];
+      for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c)
+          S.Rc[9 * h + 3 * r + c] = A[3 * r] * E[c] + A[3 * r + 1] * E[3 + c] + A[3 * r + 2] * E[6 + c];
+        S.tc[3 * h + r] = A[3 * r] * te[0] + A[3 * r + 1] * te[1] + A[3 * r + 2] * te[2] + a[r];
+      }
+    }
+  }
+  return upload_pose(S.ch, S.Rc.data(), S.tc.data());
+}
+
+// Start a new load step from the state in xb: the slot re-enters the mixed
+// phase with a fresh warm start and restarted forcing.
+int Engine::restart_load_step(int i) {
+  SlotState& S = slot_[i];
+  mfs_character* ch = S.ch;
+  MFS_HIP(hipMemcpyAsync(ch->x.p, ch->xb.p, 3 * sizeof(double) * ch->n, hipMemcpyDeviceToDevice, ctx_->stream));
+  S.phase = 0;
+  S.fresh = true;
+  S.load_mixed = 0;
+  S.E_known = false;
+  Ctrl& c = ctx_->h_ctrl.as<Ctrl>()[i];
+  c.cg_g2prev = 0.0;
+  c.cg_eta_min = 0.0;
+  return MFS_OK;
+}
+
+int Engine::configure(const mfs_solve_opts* opts) {
+  mfs_default_opts(&o_);
+  if (opts) o_ = *opts;
+  if (o_.precision != MFS_FP64 && o_.precision != MFS_FP32_REFINED)
+    return set_error(MFS_E_INVALID, "unknown precision %d", o_.precision);
+  if (o_.max_newton < 1 || o_.cg_max < 1 || !(o_.cg_tol >= 0.0) || !(o_.step_tol >= 0.0))
+    return set_error(MFS_E_INVALID, "invalid solve options");
+  if (o_.output_memory != MFS_MEM_HOST && o_.output_memory != MFS_MEM_DEVICE)
+    return set_error(MFS_E_INVALID, "invalid output memory space");
+  if (o_.warm_start != MFS_WARM_REST && o_.warm_start != MFS_WARM_PREVIOUS)
+    return set_error(MFS_E_INVALID, "invalid warm-start option");
+  fp32_ = o_.precision == MFS_FP32_REFINED;
+  return MFS_OK;
+}
+
+int Engine::reserve(int n) {
+  if (n < 1) return set_error(MFS_E_INVALID, "engine needs at least one slot");
+  MFS_HIP(hipSetDevice(ctx_->device));
+  MFS_HIP(hipStreamSynchronize(ctx_->stream));  // staging buffers may be reallocated
+  MFS_TRY(ctx_->desc.reserve(n * sizeof(SysDesc)));
+  MFS_TRY(ctx_->ctrl.reserve(n * sizeof(Ctrl)));
+  MFS_TRY(ctx_->red.reserve(n * P_COUNT * sizeof(double)));
+  MFS_TRY(ctx_->cg.reserve(n * sizeof(CgState)));
+  MFS_TRY(ctx_->h_ctrl.reserve(n * sizeof(Ctrl)));
+  MFS_TRY(ctx_->h_red.reserve(n * P_COUNT * sizeof(double)));
+  MFS_TRY(ctx_->h_cg.reserve(n * sizeof(CgState)));
+  // arrival tickets start at zero (each kernel's last workgroup resets its own)
+  MFS_HIP(hipMemsetAsync(ctx_->cg.p, 0, n * sizeof(CgState), ctx_->stream));
+  MFS_TRY(ctx_->h_desc.reserve(n * sizeof(SysDesc)));
+  std::memset(ctx_->h_ctrl.p, 0, n * sizeof(Ctrl));
+  slot_.assign(n, SlotState());
+  hd_.assign(n, SysDesc{});
+  desc_dirty_ = true;
+  tiles_valid_ = false;
+  return MFS_OK;
+}
+
+bool Engine::any_busy() const {
+  for (const SlotState& s : slot_)
+    if (s.used && !s.done) return true;
+  return false;
+}
+
+int Engine::attach(int i, mfs_character* ch, const double* R, const double* t) {
+  if (i < 0 || i >= (int)slot_.size() || slot_[i].used) return set_error(MFS_E_INVALID, "slot %d unavailable", i);
+  if (!ch || ch->ctx != ctx_) return set_error(MFS_E_INVALID, "character is null or of another context");
+  for (const SlotState& s : slot_)
+    if (s.used && s.ch == ch) return set_error(MFS_E_INVALID, "character already has a frame in flight");
+  MFS_TRY(check_pose(ch, R, t));
+  const bool warm = o_.warm_start == MFS_WARM_PREVIOUS && ch->has_solution;
+  if (!warm)
+    MFS_HIP(hipMemcpyAsync(ch->x.p, ch->X.p, 3 * sizeof(double) * ch->n, hipMemcpyDeviceToDevice, ctx_->stream));
+  MFS_HIP(hipMemcpyAsync(ch->xb.p, ch->x.p, 3 * sizeof(double) * ch->n, hipMemcpyDeviceToDevice, ctx_->stream));
+  ch->has_solution = false;
+  SlotState& S = slot_[i];
+  S = SlotState();
+  S.ch = ch;
+  S.used = true;
+  S.fresh = true;
+  const int nh = ch->nh;
+  S.R1.assign(R, R + 9 * nh);
+  S.t1.assign(t, t + 3 * nh);
+  if (warm && (int)ch->last_R.size() == 9 * nh) {
+    S.R0 = ch->last_R;
+    S.t0 = ch->last_t;
+  } else {  // the rest shape is the solution of the identity pose
+    S.R0.assign(9 * nh, 0.0);
+    S.t0.assign(3 * nh, 0.0);
+    for (int h = 0; h < nh; ++h) S.R0[9 * h] = S.R0[9 * h + 4] = S.R0[9 * h + 8] = 1.0;
+  }
+  MFS_TRY(set_pose(i, 1.0));
+  SysDesc& d = hd_[i];
+  d = ch->desc;
+  d.red = ctx_->red.as<double>() + P_COUNT * i;
+  d.cg = ctx_->cg.as<CgState>() + i;
+  d.ctrl = ctx_->ctrl.as<Ctrl>() + i;
+  Ctrl& c = ctx_->h_ctrl.as<Ctrl>()[i];
+  std::memset(&c, 0, sizeof c);
+  c.cg_tol2 = o_.cg_tol * o_.cg_tol;
+  c.cg_adaptive = o_.cg_adaptive ? 1 : 0;
+  desc_dirty_ = true;
+  return MFS_OK;
+}
+
+int Engine::upload_desc() {
+  if (!desc_dirty_) return MFS_OK;
+  const int n = (int)slot_.size();
+  std::memcpy(ctx_->h_desc.p, hd_.data(), n * sizeof(SysDesc));
+  MFS_HIP(hipMemcpyAsync(ctx_->desc.p, ctx_->h_desc.p, n * sizeof(SysDesc), hipMemcpyHostToDevice, ctx_->stream));
+  desc_dirty_ = false;
+  return MFS_OK;
+}
+
+int Engine::tiles_for(const std::vector<int>& ids) {
+  if (tiles_valid_ && ids == tile_ids_) return MFS_OK;
+  std::vector<mfs_character*> by_slot(slot_.size(), nullptr);
+  for (size_t i = 0; i < slot_.size(); ++i) by_slot[i] = slot_[i].ch;
+  MFS_TRY(build_tile_list(ctx_, by_slot, ids, &ts_));
+  tile_ids_ = ids;
+  tiles_valid_ = true;
+  return MFS_OK;
+}
+
+int Engine::run_cg(const std::vector<int>& act) {
+  mfs_context* ctx = ctx_;
+  const SysDesc* dsd = ctx->desc.as<SysDesc>();
+  const int n = (int)slot_.size();
+  const CgState* hg = ctx->h_cg.as<CgState>();
+  const Ctrl* hc = ctx->h_ctrl.as<Ctrl>();
+  int cit = 0;
+  int chunk = ctx->cg_first_run;
+  for (int i : act) {
+    slot_[i].rho_prev = -1.0;
+    slot_[i].it_prev = 0;
+  }
+  const SysDesc* one = act.size() == 1 ? &hd_[act[0]] : nullptr;
+  // algorithmic bytes of one SpMV launch over the slots still in PCG
+  // (blocks + column indices + row pointers + 2 gathered inputs and 2
+  // outputs per row), for the profiler's roofline figures
+  const double word = fp32_ ? 4.0 : 8.0;
+  auto spmv_bytes = [&]() {
+    double by = 0.0;
+    for (int i : act)
+      if (cit == 0 || !hg[i].done) {
+        const mfs_character* c = slot_[i].ch;
+        by += c->nnzb * (9.0 * word + 4.0) + (c->n + 1) * 4.0 + c->n * 12.0 * word;
+      }
+    return by;
+  };
+  // PCG in runs of iterations; after each run the host reads the
+  // convergence flags and residuals and sizes the next run from the
+  // observed residual decay of the slowest slot.
+  while (cit < o_.cg_max) {
+    const int run = std::min(chunk, o_.cg_max - cit);
+    MFS_TRY(enqueue_cg(ctx, dsd, ts_, fp32_, run, one, spmv_bytes()));
+    cit += run;
+    MFS_HIP(hipGetLastError());
+    MFS_TRY(read_cg(ctx, n));
+    bool all = true;
+    int need = 0;
+    for (int i : act) {
+      if (hg[i].done) continue;
+      all = false;
+      const double rr = hg[i].rr, bb = hg[i].bb;
+      const double rho = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+      const double tol_i = std::sqrt(pcg_tol2(hc[i], bb));
+      int est = ctx->cg_first_run;
+      SlotState& S = slot_[i];
+      if (S.rho_prev > 0.0 && rho > 0.0 && rho < S.rho_prev && cit > S.it_prev) {
+        const double rate = std::pow(rho / S.rho_prev, 1.0 / (cit - S.it_prev));
+        const double left = std::log(tol_i / rho) / std::log(rate);
+        est = (int)std::ceil(1.1 * left) + 2;
+      }
+      S.rho_prev = rho;
+      S.it_prev = cit;
+      need = std::max(need, est);
+    }
+    if (all) break;
+    chunk = std::min(std::max(need, ctx->cg_min_run), ctx->cg_max_run);
+  }
+  for (int i : act) {
+    if (hg[i].done) {
+      slot_[i].cg += hg[i].iters;
+    } else {
+      slot_[i].cg += o_.cg_max;
+      slot_[i].cg_fail++;
+    }
+  }
+  ProfScope ps(ctx, MFS_K_OTHER);
+  launch_cg_finish(ctx->stream, dsd, ts_.dv, ts_.nv, fp32_);
+  return MFS_OK;
+}
+
+int Engine::linesearch(const std::vector<int>& act) {
+  mfs_context* ctx = ctx_;
+  hipStream_t st = ctx->stream;
+  const SysDesc* dsd = ctx->desc.as<SysDesc>();
+  const Ctrl* dctrl = ctx->ctrl.as<Ctrl>();
+  Ctrl* hc = ctx->h_ctrl.as<Ctrl>();
+  const double* hr = ctx->h_red.as<double>();
+  const int n = (int)slot_.size();
+  // first pass: Newton slots evaluate E at {0, 1, 1/2, 1/4, 1/8}; mixed
+  // slots get the halving count their worst tet needs
+  for (int i : act) {
+    slot_[i].alpha = 0.0;
+    hc[i].phase = slot_[i].phase;
+    hc[i].trials[0] = 0.0;
+    for (int j = 1; j < kNumTrials; ++j) hc[i].trials[j] = std::ldexp(1.0, -(j - 1));
+  }
+  std::vector<int> srch = act;
+  bool first_pass = true;
+  while (!srch.empty()) {
+    MFS_TRY(tiles_for(srch));
+    MFS_TRY(upload_ctrl(ctx, n));
+    {
+      ProfScope ps(ctx, MFS_K_LINESEARCH);
+      launch_linesearch(st, dsd, dctrl, ts_.dt, ts_.nt, ts_.dv, ts_.nv);
+    }
+    {
+      ProfScope ps(ctx, MFS_K_OTHER);
+      launch_finalize(st, dsd, ctx->sys_ids.as<int32_t>(), (int)srch.size());
+    }
+    MFS_HIP(hipGetLastError());
+    MFS_TRY(read_red(ctx, n));
+    std::vector<int> next;
+    for (int i : srch) {
+      SlotState& S = slot_[i];
+      const double* rd = hr + P_COUNT * i;
+      if (first_pass) {
+        // forcing state for the next Newton step (Eisenstat-Walker safeguard)
+        const double eta = std::sqrt(pcg_tol2(hc[i], rd[P_BB]));
+        const double sg = 0.9 * eta * eta;
+        hc[i].cg_eta_min = sg > 0.1 ? sg : 0.0;
+        hc[i].cg_g2prev = rd[P_BB];
+        S.grad = std::sqrt(rd[P_BB]);
+        S.relres = rd[P_BB] > 0.0 ? std::sqrt(rd[P_RR] / rd[P_BB]) : 0.0;
+        S.clamped = (int)rd[P_CLAMP];
+        S.step = rd[P_DXMAX];  // scaled by alpha after the update
+      }
+      if (S.phase == 0) {
+        const int h = (int)rd[P_HMAX];
+        if (h <= 40) {
+          S.alpha = std::ldexp(1.0, -h);
+          S.halvings += h;
+        }
+        continue;
+      }
+      int j0 = 0;
+      if (first_pass) {
+        S.E = rd[P_INF0] > 0.0 ? INFINITY : rd[P_E0] + rd[P_PIN0];
+        S.E_known = true;
+        j0 = 1;
+      }
+      const double slope = -rd[P_SLOPE];  // grad E . dx, with b = -grad E
+      const double E0 = S.E;
+      bool acc = false;
+      for (int j = j0; j < kNumTrials && !acc; ++j) {
+        const double a = hc[i].trials[j];
+        if (rd[P_INF0 + j] > 0.0) continue;
+        const double Ej = rd[P_E0 + j] + rd[P_PIN0 + j];
+        if (std::isfinite(E0) && Ej <= E0 + 1e-4 * a * slope + 1e-12 * std::fabs(E0)) {
+          acc = true;
+          S.alpha = a;
+          S.E = Ej;
+          S.halvings += (int)std::lround(-std::log2(a));
+        }
+      }
+      if (!acc) {
+        const double last = hc[i].trials[kNumTrials - 1];
+        if (last > std::ldexp(1.0, -40) && std::isfinite(E0)) {
+          for (int j = 0; j < kNumTrials; ++j) hc[i].trials[j] = last * std::ldexp(1.0, -(j + 1));
+          next.push_back(i);
+        }
+      }
+    }
+    srch.swap(next);
+    first_pass = false;
+  }
+  return MFS_OK;
+}
+
+int Engine::step() {
+  mfs_context* ctx = ctx_;
+  hipStream_t st = ctx->stream;
+  MFS_HIP(hipSetDevice(ctx->device));
+  const int n = (int)slot_.size();
+  const SysDesc* dsd = ctx->desc.as<SysDesc>();
+  const Ctrl* dctrl = ctx->ctrl.as<Ctrl>();
+  Ctrl* hc = ctx->h_ctrl.as<Ctrl>();
+  const double* hr = ctx->h_red.as<double>();
+  MFS_TRY(upload_desc());
+
+  // mixed warm start of newly attached slots: s0 = stretch factor of F(x0)
+  std::vector<int> fresh;
+  for (int i = 0; i < n; ++i)
+    if (slot_[i].used && slot_[i].fresh) fresh.push_back(i);
+  if (!fresh.empty()) {
+    MFS_TRY(tiles_for(fresh));
+    {
+      ProfScope ps(ctx, MFS_K_WARM_START);
+      launch_warm_start(st, dsd, ts_.dt, ts_.nt, fp32_);
+    }
+    {
+      ProfScope ps(ctx, MFS_K_OTHER);
+      launch_finalize(st, dsd, ctx->sys_ids.as<int32_t>(), (int)fresh.size());
+    }
+    MFS_HIP(hipGetLastError());
+    MFS_TRY(read_red(ctx, n));
+    for (int i : fresh) {
+      slot_[i].routed = (int)hr[P_COUNT * i + P_ROUTED];
+      slot_[i].fresh = false;
+    }
+  }
+
+  std::vector<int> act;
+  for (int i = 0; i < n; ++i)
+    if (slot_[i].used && !slot_[i].done) act.push_back(i);
+  if (act.empty()) return MFS_OK;
+  MFS_TRY(tiles_for(act));
+  for (int i : act) {
+    hc[i].phase = slot_[i].phase;
+    hc[i].update_s = 0;
+    hc[i].alpha = 0.0;
+    // inexact Newton only on the constraint: mixed-phase solves use the floor
+    // tolerance (a loose mixed step can leave the positive-definite cone in
+    // single tets and stall the mixed line search)
+    hc[i].cg_adaptive = (o_.cg_adaptive && slot_[i].phase == 1) ? 1 : 0;
+  }
+  MFS_TRY(upload_ctrl(ctx, n));
+  {
+    ProfScope ps(ctx, MFS_K_ELEMENT);
+    launch_element(st, dsd, dctrl, ts_.dt, ts_.nt, fp32_);
+  }
+  {
+    ProfScope ps(ctx, MFS_K_ASSEMBLE);
+    launch_assemble(st, dsd, ts_.ds, ts_.ns, fp32_);
+  }
+  {
+    ProfScope ps(ctx, MFS_K_OTHER);
+    launch_cg_init(st, dsd, ts_.dv, ts_.nv, fp32_);
+  }
+  MFS_HIP(hipGetLastError());
+  MFS_TRY(run_cg(act));
+  MFS_TRY(linesearch(act));
+
+  // updates
+  for (int i : act) {
+    hc[i].alpha = slot_[i].alpha;
+    hc[i].update_s = (slot_[i].phase == 0 && slot_[i].alpha > 0.0 && slot_[i].alpha < 1.0) ? 1 : 0;
+    hc[i].phase = slot_[i].phase;
+  }
+  MFS_TRY(tiles_for(act));
+  MFS_TRY(upload_ctrl(ctx, n));
+  {
+    ProfScope ps(ctx, MFS_K_UPDATE);
+    launch_update(st, dsd, dctrl, ts_.dt, ts_.nt, ts_.dv, ts_.nv);
+  }
+  MFS_HIP(hipGetLastError());
+
+  const bool loadstep = o_.load_bisections > 0 && !o_.fixed_newton;
+  for (int i : act) {
+    SlotState& S = slot_[i];
+    const bool was_newton = S.phase == 1;
+    S.iters++;
+    S.step = S.alpha * S.step;
+    if (!was_newton) {
+      S.mixed++;
+      S.load_mixed++;
+      S.E_known = false;
+    }
+    const bool stalled = S.alpha == 0.0 || (!was_newton && S.alpha < 1.0 && S.load_mixed > 6);
+    if (stalled && loadstep && S.bisections < o_.load_bisections && S.iters < o_.max_newton) {
+      // back to the last converged pose; approach the target in a shorter step
+      S.bisections++;
+      S.delta *= 0.5;
+      MFS_TRY(restart_load_step(i));
+      MFS_TRY(set_pose(i, S.tau_done + S.delta));
+      continue;
+    }
+    if (S.alpha == 0.0) {  // line search failed: keep the iterate
+      S.done = true;
+      S.status = MFS_W_NOT_CONVERGED;
+      continue;
+    }
+    if (!was_newton && S.alpha == 1.0) {
+      S.phase = 1;
+      hc[i].cg_g2prev = 0.0;  // forcing restarts at the first Newton-phase step
+      hc[i].cg_eta_min = 0.0;
+    }
+    const bool final_pose = S.tau >= 1.0;
+    const double tol = final_pose ? o_.step_tol : 1e-4;
+    if (o_.fixed_newton) {
+      if (S.iters >= o_.max_newton) S.done = true;
+    } else if (was_newton && S.step <= tol * S.ch->bbox_diag) {
+      if (final_pose) {
+        S.done = true;
+      } else {  // intermediate pose reached: keep it, lengthen the next step
+        MFS_HIP(hipMemcpyAsync(S.ch->xb.p, S.ch->x.p, 3 * sizeof(double) * S.ch->n, hipMemcpyDeviceToDevice, st));
+        S.tau_done = S.tau;
+        S.delta *= 2.0;
+        MFS_TRY(restart_load_step(i));
+        MFS_TRY(set_pose(i, std::min(1.0, S.tau_done + S.delta)));
+      }
+    }
+    if (!S.done && S.iters >= o_.max_newton) {
+      S.done = true;
+      S.status = MFS_W_NOT_CONVERGED;
+    }
+  }
+  return MFS_OK;
+}
+
+int Engine::finish_energies() {
+  const int n = (int)slot_.size();
+  std::vector<int> need;
+  for (int i = 0; i < n; ++i)
+    if (slot_[i].used && slot_[i].done && !slot_[i].E_known) need.push_back(i);
+  if (need.empty()) return MFS_OK;
+  mfs_context* ctx = ctx_;
+  Ctrl* hc = ctx->h_ctrl.as<Ctrl>();
+  MFS_TRY(upload_desc());
+  MFS_TRY(tiles_for(need));
+  for (int i : need) {
+    hc[i].phase = 1;
+    for (int j = 0; j < kNumTrials; ++j) hc[i].trials[j] = 0.0;
+  }
+  MFS_TRY(upload_ctrl(ctx, n));
+  launch_linesearch(ctx->stream, ctx->desc.as<SysDesc>(), ctx->ctrl.as<Ctrl>(), ts_.dt, ts_.nt, ts_.dv, ts_.nv);
+  launch_finalize(ctx->stream, ctx->desc.as<SysDesc>(), ctx->sys_ids.as<int32_t>(), (int)need.size());
+  MFS_HIP(hipGetLastError());
+  MFS_TRY(read_red(ctx, n));
+  const double* hr = ctx->h_red.as<double>();
+  for (int i : need) {
+    const double* rd = hr + P_COUNT * i;
+    slot_[i].E = rd[P_INF0] > 0.0 ? INFINITY : rd[P_E0] + rd[P_PIN0];
+    slot_[i].E_known = true;
+  }
+  return MFS_OK;
+}
+
+int Engine::output(int i, double* x_out, int mem) {
+  mfs_character* ch = slot_[i].ch;
+  hipStream_t st = ctx_->stream;
+  if (mem == MFS_MEM_DEVICE) {
+    launch_scatter_rows(st, ch->x.as<double>(), ch->perm_d.as<int32_t>(), ch->n, 3, 1.0, x_out);
+  } else {
+    launch_scatter_rows(st, ch->x.as<double>(), ch->perm_d.as<int32_t>(), ch->n, 3, 1.0, ch->r.as<double>());
+    MFS_HIP(hipMemcpyAsync(x_out, ch->r.p, 3 * sizeof(double) * ch->n, hipMemcpyDeviceToHost, st));
+  }
+  MFS_HIP(hipGetLastError());
+  MFS_HIP(hipStreamSynchronize(st));
+  prof_resolve(ctx_);
+  ch->has_solution = true;
+  ch->last_R = slot_[i].R1;
+  ch->last_t = slot_[i].t1;
+  return MFS_OK;
+}
+
+void Engine::stats(int i, mfs_solve_stats* s) const {
+  const SlotState& S = slot_[i];
+  s->status = S.status;
+  s->iterations = S.iters;
+  s->mixed_iterations = S.mixed;
+  s->cg_iterations = S.cg;
+  s->halvings = S.halvings;
+  s->clamped = S.clamped;
+  s->fp64_routed = S.routed;
+  s->cg_not_converged = S.cg_fail;
+  s->energy = S.E;
+  s->grad_norm = S.grad;
+  s->last_step = S.step;
+  s->cg_rel_residual = S.relres;
+}
+
+}  // namespace mfs

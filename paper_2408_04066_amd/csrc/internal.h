@@ -92,8 +92,8 @@ struct mfs_context {
   int graph_iters = 8;               // PCG iterations per captured graph
   std::vector<mfs::CgGraph> graphs;
   // batch scratch
-  mfs::DevBuf desc, ctrl, flags, red, cgres, tiles, sys_ids, tmp;
-  mfs::PinnedBuf h_ctrl, h_flags, h_red, h_cgres, h_tiles, h_stage;
+  mfs::DevBuf desc, ctrl, red, cg, tiles, sys_ids, tmp;
+  mfs::PinnedBuf h_ctrl, h_red, h_cg, h_tiles, h_stage, h_desc;
   // HIP-event profiler (mfs_profile_enable)
   int prof_stride = 0;
   double prof_ms[MFS_K_FAMILIES] = {};
@@ -117,7 +117,8 @@ struct mfs_character {
   mfs::DevBuf tets, G, wmu, wlam, info, X, rowptr, colidx, slot_ptr, contrib, diag, vpin_ptr, vpin_h, perm_d,
       tperm_d;
   // per-frame rig and solver state
-  mfs::DevBuf Rh, th, x, s, blk, frc, b, dx, vals, minv, r, z, p0, p1, q, xc, part, flags, red;
+  mfs::DevBuf Rh, th, x, xb, s, blk, frc, b, dx, vals, minv, r, z, p0, p1, q, xc, part, red;
+  std::vector<double> last_R, last_t;  // pose of the last solved frame (warm-start homotopy origin)
   mfs::SysDesc desc;  // pointers above, host copy
   size_t resident_bytes = 0, workspace_bytes = 0;
 };

@@ -6,14 +6,15 @@
 // neighbouring rows read the previous buffer) and q = K p_it, with LPR lanes
 // per block row reading the 9 value planes of consecutive slots (coalesced).
 // k_cg_update applies alpha, the block-Jacobi preconditioner and the next
-// dot products.  Dot products are per-tile partials in FP64, folded per
-// system in a fixed order by every workgroup that needs them.  Convergence
-// (||r|| <= tol ||b||) is decided identically by every workgroup of a system
-// from those partials.
+// dot products.  Dot products are per-tile partials in FP64, folded in a
+// fixed order: for systems with many tiles by the last workgroup to finish
+// each kernel (arrival ticket) into the system's PCG state, which the next
+// kernel reads as a few scalars; for systems with few tiles by every
+// workgroup of the next kernel ("all-read", no fences).  Convergence
+// (||r|| <= tol ||b||) is decided from those folds.
 //
-// The iteration index lives in device memory (two slots, each written by the
-// other kernel of the pair, so no kernel reads a slot it writes): the launch
-// arguments of an iteration do not depend on its index, and a run of
+// The iteration index and the per-step tolerance live in device memory: the
+// launch arguments of an iteration do not depend on its index, and a run of
 // iterations can be captured once as a HIP graph and replayed.
 #include "common.h"
 #include "elem_math.h"
@@ -28,10 +29,24 @@ __device__ __forceinline__ void precondition(const T* __restrict__ mi, const T r
   zv[2] = mi[4] * rv[0] + mi[3] * rv[1] + mi[2] * rv[2];
 }
 
-// r = b, x = 0, z = M^-1 r; partials r.z, r.r, b.b.  One wave per tile.
+// ONE: a single system whose descriptor is the kernel argument `one` and
+// whose tiles are implicit (tile j = rows [64 j, 64 j + 64)); saves the two
+// dependent loads (tile, descriptor) at the head of every workgroup.
+template <bool ONE>
+__device__ __forceinline__ Tile vertex_tile(const Tile* __restrict__ tiles, int ntiles, const SysDesc& one) {
+  const int j = xcd_tile(blockIdx.x, ntiles);
+  if (ONE) return Tile{0, j * kVTile, min(one.n, (j + 1) * kVTile), j};
+  return tiles[j];
+}
+
+// r = b, x = 0, z = M^-1 r; partials r.z, r.r, b.b.  Ticket mode: the last
+// workgroup of a system sets its PCG state (and `done` when b is already
+// within tolerance).  All-read mode: tile 0 resets the state; the first SpMV
+// folds the partials and tests convergence.
 template <typename T>
 __global__ __launch_bounds__(64) void k_cg_init(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
                                                 int ntiles) {
+  __shared__ int last;
   const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
   const SysDesc& S = sd[t.sys];
   const int row = t.begin + threadIdx.x;
@@ -64,53 +79,82 @@ __global__ __launch_bounds__(64) void k_cg_init(const SysDesc* __restrict__ sd, 
     S.part[P_RZ0 * S.ptile + t.local] = rz;
     S.part[P_RR * S.ptile + t.local] = rr;
     S.part[P_BB * S.ptile + t.local] = bb;
-    if (t.local == 0) {
-      S.flags[F_CG_DONE] = 0;
-      S.flags[F_CG_ITERS] = 0;
-      S.flags[F_IT_A] = 0;
-      S.flags[F_IT_B] = 0;
+  }
+  CgState* st = S.cg;
+  if (!S.ticket) {
+    if (t.local == 0 && threadIdx.x == 0) {
+      st->done = 0;
+      st->iters = 0;
+      st->it_a = 0;
+      st->it_b = 0;
+    }
+    return;
+  }
+  if (last_arrival(&st->arrive_init, S.ntv, &last)) {
+    const double srz = coherent_sum(S.part + P_RZ0 * S.ptile, S.ntv);
+    const double srr = coherent_sum(S.part + P_RR * S.ptile, S.ntv);
+    const double sbb = coherent_sum(S.part + P_BB * S.ptile, S.ntv);
+    if (threadIdx.x == 0) {
+      st->rz = srz;
+      st->rz_prev = 0.0;
+      st->rr = srr;
+      st->bb = sbb;
+      st->pq = 0.0;
+      st->it = 0;
+      st->iters = 0;
+      st->done = srr <= pcg_tol2(*S.ctrl, sbb) * sbb ? 1 : 0;
+      st->arrive_init = 0;
     }
   }
 }
 
-// Search direction and q = K p: one pass of 64 rows, LPR lanes per row.
-// ONE: a single system whose descriptor is the kernel argument `one` and
-// whose tiles are implicit (tile j = rows [64 j, 64 j + 64)); saves the two
-// dependent loads (tile, descriptor) at the head of every workgroup.
-template <bool ONE>
-__device__ __forceinline__ Tile vertex_tile(const Tile* __restrict__ tiles, int ntiles, const SysDesc& one) {
-  const int j = xcd_tile(blockIdx.x, ntiles);
-  if (ONE) return Tile{0, j * kVTile, min(one.n, (j + 1) * kVTile), j};
-  return tiles[j];
-}
-
+// Search direction p_it = z + beta p_{it-1} and q = K p_it: one pass of 64
+// rows, LPR lanes per row; partial p.q.
 template <typename T, int LPR, bool ONE>
 __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
                                                       int ntiles, const SysDesc one) {
   __shared__ double red[LPR];
+  __shared__ double bcast[2];
+  __shared__ int last;
   const Tile t = vertex_tile<ONE>(tiles, ntiles, one);
   const SysDesc& S = ONE ? one : sd[t.sys];
-  const double* part = S.part;
-  const double rr = sys_sum(part + P_RR * S.ptile, S.ntv);
-  const double bb = sys_sum(part + P_BB * S.ptile, S.ntv);
-  const double tol2 = pcg_tol2(*S.ctrl, bb);
-  const int it = S.flags[F_IT_A];
-  if (rr <= tol2 * bb) {
-    if (t.local == 0 && threadIdx.x == 0 && S.flags[F_CG_DONE] == 0) {
-      S.flags[F_CG_DONE] = 1;
-      S.flags[F_CG_ITERS] = it;
-      S.cgres[0] = rr;
-      S.cgres[1] = bb;
+  CgState* st = S.cg;
+  int it;
+  double beta;
+  if (S.ticket) {
+    if (st->done) return;
+    it = st->it;
+    beta = it == 0 ? 0.0 : st->rz / st->rz_prev;
+  } else {
+    // all-read: wave 0 folds this system's partials, the workgroup shares them
+    it = st->it_a;
+    if (threadIdx.x < 64) {
+      const double* part = S.part;
+      const double rr = sys_sum(part + P_RR * S.ptile, S.ntv);
+      const double bb = sys_sum(part + P_BB * S.ptile, S.ntv);
+      const bool conv = rr <= pcg_tol2(*S.ctrl, bb) * bb;
+      double b = 0.0;
+      if (!conv && it > 0)
+        b = sys_sum(part + (P_RZ0 + (it & 1)) * S.ptile, S.ntv) /
+            sys_sum(part + (P_RZ0 + ((it + 1) & 1)) * S.ptile, S.ntv);
+      if (threadIdx.x == 0) {
+        bcast[0] = conv ? 1.0 : 0.0;
+        bcast[1] = b;
+        if (t.local == 0) {
+          st->rr = rr;
+          st->bb = bb;
+          if (conv && st->done == 0) {
+            st->done = 1;
+            st->iters = it;
+          }
+          if (!conv) st->it_b = it;
+        }
+      }
     }
-    return;
+    __syncthreads();
+    if (bcast[0] != 0.0) return;
+    beta = bcast[1];
   }
-  if (t.local == 0 && threadIdx.x == 0) {
-    S.flags[F_IT_B] = it;
-    S.cgres[0] = rr;
-    S.cgres[1] = bb;
-  }
-  const double rz = sys_sum(part + (P_RZ0 + (it & 1)) * S.ptile, S.ntv);
-  const double beta = it == 0 ? 0.0 : rz / sys_sum(part + (P_RZ0 + ((it + 1) & 1)) * S.ptile, S.ntv);
   const T tb = (T)beta;
   T* pn = (T*)((it & 1) ? S.p1 : S.p0);
   const T* po = (const T*)((it & 1) ? S.p0 : S.p1);
@@ -160,19 +204,38 @@ __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict_
   }
   const double tot = block_sum<LPR>(dot, red);
   if (threadIdx.x == 0) S.part[P_PQ * S.ptile + t.local] = tot;
+  if (S.ticket && last_arrival(&st->arrive_spmv, S.ntv, &last) && threadIdx.x < 64) {
+    const double pq = coherent_sum(S.part + P_PQ * S.ptile, S.ntv);
+    if (threadIdx.x == 0) {
+      st->pq = pq;
+      st->arrive_spmv = 0;
+    }
+  }
 }
 
-// alpha = r.z / p.q; x += alpha p; r -= alpha q; z = M^-1 r; partials.
+// alpha = r.z / p.q; x += alpha p; r -= alpha q; z = M^-1 r; partials r.z
+// and r.r.  Ticket mode: the last workgroup folds them, advances the
+// iteration and decides convergence with this Newton step's tolerance.
 template <typename T, bool ONE>
 __global__ __launch_bounds__(64) void k_cg_update(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
                                                   int ntiles, const SysDesc one) {
+  __shared__ int last;
   const Tile t = vertex_tile<ONE>(tiles, ntiles, one);
   const SysDesc& S = ONE ? one : sd[t.sys];
-  if (S.flags[F_CG_DONE]) return;
-  const int it = S.flags[F_IT_B];
-  const double pq = sys_sum(S.part + P_PQ * S.ptile, S.ntv);
-  const double rz = sys_sum(S.part + (P_RZ0 + (it & 1)) * S.ptile, S.ntv);
-  const T alpha = (T)(rz / pq);
+  CgState* st = S.cg;
+  if (st->done) return;
+  int it;
+  double rz_old, pq;
+  if (S.ticket) {
+    it = st->it;
+    rz_old = st->rz;
+    pq = st->pq;
+  } else {
+    it = st->it_b;
+    pq = sys_sum(S.part + P_PQ * S.ptile, S.ntv);
+    rz_old = sys_sum(S.part + (P_RZ0 + (it & 1)) * S.ptile, S.ntv);
+  }
+  const T alpha = (T)(rz_old / pq);
   const T* pn = (const T*)((it & 1) ? S.p1 : S.p0);
   const T* q = (const T*)S.q;
   T* r = (T*)S.r;
@@ -198,10 +261,27 @@ __global__ __launch_bounds__(64) void k_cg_update(const SysDesc* __restrict__ sd
   }
   rzn = wave_sum(rzn);
   rrn = wave_sum(rrn);
+  const int rz_plane = S.ticket ? P_RZ0 : P_RZ0 + ((it + 1) & 1);
   if (threadIdx.x == 0) {
-    S.part[(P_RZ0 + ((it + 1) & 1)) * S.ptile + t.local] = rzn;
+    S.part[rz_plane * S.ptile + t.local] = rzn;
     S.part[P_RR * S.ptile + t.local] = rrn;
-    if (t.local == 0) S.flags[F_IT_A] = it + 1;
+    if (!S.ticket && t.local == 0) st->it_a = it + 1;
+  }
+  if (S.ticket && last_arrival(&st->arrive_update, S.ntv, &last)) {
+    const double srz = coherent_sum(S.part + P_RZ0 * S.ptile, S.ntv);
+    const double srr = coherent_sum(S.part + P_RR * S.ptile, S.ntv);
+    if (threadIdx.x == 0) {
+      const double bb = st->bb;
+      st->rz_prev = rz_old;
+      st->rz = srz;
+      st->rr = srr;
+      st->it = it + 1;
+      if (srr <= pcg_tol2(*S.ctrl, bb) * bb) {
+        st->done = 1;
+        st->iters = it + 1;
+      }
+      st->arrive_update = 0;
+    }
   }
 }
 

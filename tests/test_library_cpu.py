@@ -43,7 +43,7 @@ def test_struct_layouts_match_header():
     # offsets implied by the C declarations (natural alignment, LP64)
     assert ctypes.sizeof(mfs.MeshDesc) == 112
     assert mfs.MeshDesc.pin_stiffness.offset == 96
-    assert ctypes.sizeof(mfs.SolveOpts) == 48
+    assert ctypes.sizeof(mfs.SolveOpts) == 56
     assert mfs.SolveOpts.step_tol.offset == 16 and mfs.SolveOpts.cg_max.offset == 32
     assert ctypes.sizeof(mfs.SolveStats) == 64
     assert mfs.SolveStats.energy.offset == 32
