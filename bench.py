@@ -57,6 +57,40 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_spmv_humanoid50k.md")
+TRAFFIC_SOURCES = ("paper_2408_04066_amd/csrc/kernels_cg.hip", "paper_2408_04066_amd/csrc/common.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counted_traffic(workload):
+    """HBM bytes per SpMV launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (copy-kernel scaled), or None when that summary is
+    for another workload or the kernel sources changed since it was taken."""
+    try:
+        lines = open(TRAFFIC_SUMMARY).read().splitlines()
+    except OSError:
+        return None
+    kv = {}
+    for line in lines:
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            kv[k.strip("`")] = v.strip().strip("`")
+    if kv.get("workload") != workload or kv.get("kernel_sources_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(prob, pose, iterations=2):
     """The FP64 oracle, single-threaded, on the first `iterations` Newton
     iterations of one frame (rest -> pose)."""
@@ -95,6 +129,9 @@ def main():
     ap.add_argument("--profile-stride", type=int, default=8)
     ap.add_argument("--roofline-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (the reference kernel "
+                         "that scales HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: one character's frame solve is not split across "
@@ -105,6 +142,14 @@ def main():
 
     import torch
     import paper_2408_04066_amd as mfs
+
+    if args.copy_mb > 0:
+        src = torch.ones(args.copy_mb << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     probs, pose_of, wname = make_workload(args.workload)
     ctx = mfs.Context(0)
@@ -129,7 +174,7 @@ def main():
     torch.cuda.synchronize()
 
     # ---- timed region: FP32 + FP64 refinement (PCG runs replayed as graphs) ----
-    lat, tet_iters, iters, cgs, rcs = [], 0, [], [], []
+    lat, tet_iters, iters, cgs, rcs, conv = [], 0, [], [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -140,6 +185,7 @@ def main():
         iters.append(np.mean([st["iterations"] for st in sts]))
         cgs.append(np.mean([st["cg_iterations"] for st in sts]))
         rcs.append(rc)
+        conv += [st["status"] == 0 for st in sts]
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
 
@@ -149,9 +195,9 @@ def main():
     ctx.profile_enable(args.profile_stride)
     ctx.profile_read(reset=True)
     for i in range(max(min(args.steps, args.roofline_steps), min(args.steps, args.fp64_steps))):
-        frame(steps[args.warmup + i], fp32_opts)
+        sts32, _ = frame(steps[args.warmup + i], fp32_opts)
         if i < args.fp64_steps:
-            x32.append([o.cpu().numpy().copy() for o in outs])
+            x32.append(([o.cpu().numpy().copy() for o in outs], [st["status"] for st in sts32]))
     prof = ctx.profile_read(reset=True)
     ctx.profile_enable(0)
 
@@ -164,8 +210,11 @@ def main():
         torch.cuda.synchronize()
         lat64.append(time.perf_counter() - ts)
         tet_iters64 += sum(inf["n_tets"] * st["iterations"] for inf, st in zip(infos, sts))
-        for o, a, inf in zip(outs, x32[i], infos):
-            err.append(float(np.max(np.linalg.norm(a - o.cpu().numpy(), axis=1))) / inf["bbox_diag"])
+        # compared where both forms converged (a frame stopped by the Newton
+        # cap is an unconverged iterate in either precision)
+        for o, a, s32, st, inf in zip(outs, x32[i][0], x32[i][1], sts, infos):
+            if s32 == 0 and st["status"] == 0:
+                err.append(float(np.max(np.linalg.norm(a - o.cpu().numpy(), axis=1))) / inf["bbox_diag"])
 
     spmv_ms, spmv_timed, spmv_launches, spmv_bytes = prof["spmv"]
     achieved = spmv_bytes / (spmv_ms * 1e-3) / 1e9 if spmv_ms > 0 else None
@@ -189,6 +238,7 @@ def main():
         "newton_iters_per_frame": float(np.mean(iters)),
         "cg_iters_per_frame": float(np.mean(cgs)),
         "status_codes": sorted(set(int(r) for r in rcs)),
+        "converged_fraction": float(np.mean(conv)),
         "fp64": {
             "frames_per_s": nchar * len(lat64) / sum(lat64) if lat64 else None,
             "tet_newton_iter_per_s": tet_iters64 / sum(lat64) if lat64 else None,
@@ -207,7 +257,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
-            "traffic": None,
+            "traffic": counted_traffic(wname),
             "bytes_per_launch": spmv_bytes / max(spmv_timed, 1),
             "avg_launch_us": 1e3 * spmv_ms / max(spmv_timed, 1),
             "timed_launches": spmv_timed,

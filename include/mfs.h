@@ -182,6 +182,13 @@ int mfs_character_destroy(mfs_character* ch);
 int mfs_character_footprint(const mfs_character* ch, size_t* resident_bytes,
                             size_t* workspace_bytes);
 
+/* Free the character's own solve workspace (workspace_bytes of device
+ * memory), keeping its resident data and last solution.  A server then
+ * lends it a workspace from its arena for each admitted frame; a later
+ * standalone call (solve, batch, evaluate) allocates the workspace again.
+ * Synchronises the context's stream. */
+int mfs_character_release_workspace(mfs_character* ch);
+
 /* ---- rig helpers ------------------------------------------------------ */
 
 /* Rotation clusters (Section 3.1): each tet takes the handle of the bone
@@ -217,6 +224,70 @@ int mfs_solve_batch(mfs_context* ctx, int32_t count, mfs_character* const* chars
                     const double* const* handle_R, const double* const* handle_t,
                     const mfs_solve_opts* opts, double* const* x_out,
                     mfs_solve_stats* stats);
+
+/* ---- serving ------------------------------------------------------------ */
+
+/* A request loop with continuous batching over one context.  A worker
+ * thread owns the context's stream while the server exists: between
+ * server_create and server_destroy the context and its characters are used
+ * only through mfs_server_* calls (which may come from any host thread).
+ * Each request is one frame solve (as mfs_solve_frame, with the server's
+ * solve options).  Between Newton steps the worker admits queued requests
+ * in submission order into free slots of the running batch; a request
+ * waits while its character has a frame in flight (frames of a character
+ * run in order, so MFS_WARM_PREVIOUS starts from the previous frame's
+ * result) and, when its character released its workspace, until that
+ * workspace fits in the server's device arena.  A request's result and
+ * statistics do not depend on the other requests in the batch. */
+typedef struct mfs_server mfs_server;
+
+typedef struct mfs_server_opts {
+  int32_t slots;                    /* frame solves in flight at once, 1..1024 */
+  int32_t queue_capacity;           /* queued requests beyond which submit is MFS_E_BUSY */
+  uint64_t workspace_budget_bytes;  /* device arena lent to requests whose character has no
+                                       workspace of its own; 0 = no arena */
+  mfs_solve_opts solve;             /* options of every solve; output_memory must be host */
+} mfs_server_opts;
+
+typedef struct mfs_request_times {  /* seconds since the server was created (steady clock) */
+  double submit_s;                  /* mfs_server_submit returned */
+  double admit_s;                   /* the request joined the batch */
+  double done_s;                    /* its result was copied out */
+} mfs_request_times;
+
+typedef struct mfs_server_info {
+  int64_t submitted, completed;     /* requests so far */
+  int64_t steps;                    /* batched Newton steps run */
+  int32_t queued, running;          /* requests waiting / in the batch now */
+  uint64_t arena_bytes;             /* arena capacity */
+  uint64_t arena_in_use, arena_peak;
+  double slot_steps;                /* sum over steps of requests in the batch
+                                       (slot_steps / steps = mean batch width) */
+} mfs_server_info;
+
+/* slots 16, queue 4096, no arena, mfs_default_opts. */
+void mfs_default_server_opts(mfs_server_opts* opts);
+/* opts may be NULL (defaults).  Errors: MFS_E_INVALID, MFS_E_UNSUPPORTED,
+ * MFS_E_OOM (arena), MFS_E_HIP. */
+int mfs_server_create(mfs_context* ctx, const mfs_server_opts* opts, mfs_server** out);
+/* Stops the worker after its current step; requests not yet taken are
+ * dropped. */
+int mfs_server_destroy(mfs_server* srv);
+/* Queue one frame solve; the pose (n_handles x 9 and x 3, host) is copied
+ * and validated as in mfs_solve_frame.  Returns at once with a ticket.
+ * MFS_E_BUSY: queue full, or the request's workspace exceeds the arena. */
+int mfs_server_submit(mfs_server* srv, mfs_character* ch, const double* handle_R,
+                      const double* handle_t, uint64_t* ticket);
+/* *done = 0 while the request is queued or running.  Once done, writes
+ * x_out (n x 3 host, caller order), stats and times (each may be NULL),
+ * forgets the ticket and returns the solve's status. */
+int mfs_server_poll(mfs_server* srv, uint64_t ticket, double* x_out, mfs_solve_stats* stats,
+                    mfs_request_times* times, int32_t* done);
+/* As poll, blocking until the request is done. */
+int mfs_server_wait(mfs_server* srv, uint64_t ticket, double* x_out, mfs_solve_stats* stats,
+                    mfs_request_times* times);
+/* Counters of the server; returns the worker's error if it stopped on one. */
+int mfs_server_get_info(mfs_server* srv, mfs_server_info* info);
 
 /* ---- introspection and profiling ------------------------------------- */
 
@@ -254,8 +325,11 @@ typedef struct mfs_profile {
 } mfs_profile;
 
 /* Time kernel launches of this context with HIP events on its stream:
- * every `stride`-th launch of each family is bracketed by an event pair
- * (stride 0 switches timing off and clears the counters). */
+ * every `stride`-th launch group of each family carries an event pair in
+ * its kernel dispatches (start of the first kernel, end of the last), so a
+ * timed interval is kernel execution only.  Timed runs launch kernels
+ * directly instead of replaying graphs.  Stride 0 switches timing off and
+ * clears the counters. */
 int mfs_profile_enable(mfs_context* ctx, int32_t stride);
 
 /* Synchronise the context's stream, fold the pending event pairs and copy

@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 __all__ = ["MfsError", "MfsUnavailable", "Context", "Character", "SolveOpts", "SolveStats",
-           "solve_batch", "lib", "EXPORTED", "ARAP", "COROT", "NEOHOOKEAN", "FP64", "FP32_REFINED",
+           "solve_batch", "Server", "lib", "EXPORTED", "ARAP", "COROT", "NEOHOOKEAN", "FP64", "FP32_REFINED",
            "MEM_HOST", "MEM_DEVICE", "WARM_REST", "WARM_PREVIOUS"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmfs.so")
@@ -30,7 +30,9 @@ EXPORTED = ("mfs_default_opts", "mfs_status_string", "mfs_last_error", "mfs_cont
             "mfs_character_footprint", "mfs_cluster_by_segments", "mfs_solve_frame",
             "mfs_solve_batch", "mfs_evaluate", "mfs_polar", "mfs_character_get_info",
             "mfs_profile_enable", "mfs_profile_read", "mfs_context_get_tuning",
-            "mfs_context_set_tuning")
+            "mfs_context_set_tuning", "mfs_character_release_workspace", "mfs_default_server_opts",
+            "mfs_server_create", "mfs_server_destroy", "mfs_server_submit", "mfs_server_poll",
+            "mfs_server_wait", "mfs_server_get_info")
 
 KERNEL_FAMILIES = ("warm_start", "element", "assemble", "spmv", "cg_update", "linesearch", "update",
                    "other")
@@ -92,6 +94,21 @@ class Profile(ctypes.Structure):
 _lib = None
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("slots", c_i32), ("queue_capacity", c_i32), ("workspace_budget_bytes", ctypes.c_uint64),
+                ("solve", SolveOpts)]
+
+
+class RequestTimes(ctypes.Structure):
+    _fields_ = [("submit_s", c_dbl), ("admit_s", c_dbl), ("done_s", c_dbl)]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("submitted", c_i64), ("completed", c_i64), ("steps", c_i64), ("queued", c_i32),
+                ("running", c_i32), ("arena_bytes", ctypes.c_uint64), ("arena_in_use", ctypes.c_uint64),
+                ("arena_peak", ctypes.c_uint64), ("slot_steps", c_dbl)]
+
+
 def lib():
     """The loaded library (loads it on first call)."""
     global _lib
@@ -122,6 +139,15 @@ def lib():
         "mfs_profile_read": (ctypes.c_int, [c_vp, P(Profile), c_i32]),
         "mfs_context_get_tuning": (ctypes.c_int, [c_vp, P(Tuning)]),
         "mfs_context_set_tuning": (ctypes.c_int, [c_vp, P(Tuning)]),
+        "mfs_character_release_workspace": (ctypes.c_int, [c_vp]),
+        "mfs_default_server_opts": (None, [P(ServerOpts)]),
+        "mfs_server_create": (ctypes.c_int, [c_vp, P(ServerOpts), P(c_vp)]),
+        "mfs_server_destroy": (ctypes.c_int, [c_vp]),
+        "mfs_server_submit": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, P(ctypes.c_uint64)]),
+        "mfs_server_poll": (ctypes.c_int, [c_vp, ctypes.c_uint64, c_vp, P(SolveStats), P(RequestTimes),
+                                           P(c_i32)]),
+        "mfs_server_wait": (ctypes.c_int, [c_vp, ctypes.c_uint64, c_vp, P(SolveStats), P(RequestTimes)]),
+        "mfs_server_get_info": (ctypes.c_int, [c_vp, P(ServerInfo)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -292,6 +318,10 @@ class Character:
         _check(lib().mfs_character_footprint(self.handle, ctypes.byref(r), ctypes.byref(w)))
         return r.value, w.value
 
+    def release_workspace(self):
+        """Free the solve workspace; a server lends one per admitted frame."""
+        _check(lib().mfs_character_release_workspace(self.handle))
+
     def _pose(self, R, t):
         R = _host(R, np.float64).reshape(self.n_handles, 9)
         t = _host(t, np.float64).reshape(self.n_handles, 3)
@@ -344,3 +374,70 @@ def solve_batch(ctx, chars, poses, outs=None, **opts):
                                       arr([_ptr(R) for R in Rs]), arr([_ptr(t) for t in ts]),
                                       ctypes.byref(o), arr([_ptr(x) for x in outs]), st))
     return outs, [s.as_dict() for s in st], rc
+
+
+class Server:
+    """Request loop with continuous batching (``mfs_server_*``).
+
+    While the server exists its worker thread owns the context: use the
+    context and its characters only through the server.  ``submit`` returns
+    a ticket at once; ``poll`` returns None until the frame is done, then
+    (x, stats, times, rc); ``wait`` blocks for it.  ``times`` holds submit,
+    admit and completion times in seconds on the server's clock."""
+
+    def __init__(self, ctx, slots=16, queue_capacity=4096, workspace_budget_bytes=0, **solve_opts):
+        o = ServerOpts()
+        lib().mfs_default_server_opts(ctypes.byref(o))
+        o.slots, o.queue_capacity = slots, queue_capacity
+        o.workspace_budget_bytes = int(workspace_budget_bytes)
+        o.solve = default_opts(**solve_opts)
+        o.solve.output_memory = MEM_HOST
+        h = c_vp()
+        _check(lib().mfs_server_create(ctx.handle, ctypes.byref(o), ctypes.byref(h)))
+        self.handle, self.ctx = h, ctx
+        self._n = {}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mfs_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, ch, R, t):
+        R, t = ch._pose(R, t)
+        tk = ctypes.c_uint64()
+        _check(lib().mfs_server_submit(self.handle, ch.handle, _ptr(R), _ptr(t), ctypes.byref(tk)))
+        self._n[tk.value] = ch.n
+        return tk.value
+
+    def _result(self, ticket, fn, *extra):
+        x = np.empty((self._n[ticket], 3))
+        st, tm = SolveStats(), RequestTimes()
+        rc = fn(self.handle, ticket, _ptr(x), ctypes.byref(st), ctypes.byref(tm), *extra)
+        return x, st, tm, rc
+
+    def poll(self, ticket):
+        done = c_i32()
+        x, st, tm, rc = self._result(ticket, lib().mfs_server_poll, ctypes.byref(done))
+        if not done.value:
+            _check(rc)
+            return None
+        del self._n[ticket]
+        _check(rc)
+        return x, st.as_dict(), {k: getattr(tm, k) for k, _ in tm._fields_}, rc
+
+    def wait(self, ticket):
+        x, st, tm, rc = self._result(ticket, lib().mfs_server_wait)
+        del self._n[ticket]
+        _check(rc)
+        return x, st.as_dict(), {k: getattr(tm, k) for k, _ in tm._fields_}, rc
+
+    def info(self):
+        i = ServerInfo()
+        _check(lib().mfs_server_get_info(self.handle, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in i._fields_}

@@ -5,10 +5,6 @@
 #include "internal.h"
 #include "launch.h"
 
-namespace mfs {
-const char* last_error_text();
-}
-
 using namespace mfs;
 
 extern "C" void mfs_default_opts(mfs_solve_opts* o) {

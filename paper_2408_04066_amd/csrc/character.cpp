@@ -170,6 +170,72 @@ static bool finite_all(const std::vector<double>& v) {
 
 using namespace mfs;
 
+namespace mfs {
+
+namespace {
+// Byte sizes of the workspace pieces, in carving order.
+int workspace_pieces(const mfs_character* ch, size_t* sz) {
+  const size_t n3 = 3 * sizeof(double) * (size_t)ch->n;
+  const size_t m = (size_t)ch->m;
+  int k = 0;
+  sz[k++] = 90 * sizeof(double) * m;                          // blk
+  sz[k++] = 12 * sizeof(double) * m;                          // frc
+  sz[k++] = n3;                                               // b
+  sz[k++] = n3;                                               // dx
+  sz[k++] = 9 * sizeof(double) * (size_t)ch->nnzb;            // vals
+  sz[k++] = 6 * sizeof(double) * (size_t)ch->n;               // minv
+  for (int v = 0; v < 6; ++v) sz[k++] = n3;                   // r z p0 p1 q xc
+  sz[k++] = sizeof(double) * P_COUNT * (size_t)ch->ptile;     // part
+  sz[k++] = sizeof(double) * P_COUNT;                         // red
+  return k;
+}
+constexpr size_t kWsAlign = 256;
+size_t align_up(size_t v) { return (v + kWsAlign - 1) / kWsAlign * kWsAlign; }
+}  // namespace
+
+size_t workspace_layout(const mfs_character* ch) {
+  size_t sz[16];
+  const int k = workspace_pieces(ch, sz);
+  size_t total = 0;
+  for (int i = 0; i < k; ++i) total += align_up(sz[i]);
+  return total;
+}
+
+void bind_workspace(const mfs_character* ch, char* base, SysDesc* d) {
+  size_t sz[16];
+  const int k = workspace_pieces(ch, sz);
+  void* ptr[16];
+  size_t off = 0;
+  for (int i = 0; i < k; ++i) {
+    ptr[i] = base ? base + off : nullptr;
+    off += align_up(sz[i]);
+  }
+  d->blk = ptr[0];
+  d->frc = static_cast<double*>(ptr[1]);
+  d->b = static_cast<double*>(ptr[2]);
+  d->dx = static_cast<double*>(ptr[3]);
+  d->vals = ptr[4];
+  d->minv = ptr[5];
+  d->r = ptr[6];
+  d->z = ptr[7];
+  d->p0 = ptr[8];
+  d->p1 = ptr[9];
+  d->q = ptr[10];
+  d->xc = ptr[11];
+  d->part = static_cast<double*>(ptr[12]);
+  d->red = static_cast<double*>(ptr[13]);
+}
+
+int ensure_workspace(mfs_character* ch) {
+  if (ch->ws.p) return MFS_OK;
+  MFS_HIP(hipSetDevice(ch->ctx->device));
+  MFS_TRY(ch->ws.alloc(ch->workspace_bytes));
+  bind_workspace(ch, ch->ws.as<char>(), &ch->desc);
+  return MFS_OK;
+}
+
+}  // namespace mfs
+
 extern "C" int mfs_character_create(mfs_context* ctx, const mfs_mesh_desc* d, mfs_character** out) {
   clear_error();
   if (!out) return set_error(MFS_E_INVALID, "out is NULL");
@@ -423,20 +489,8 @@ extern "C" int mfs_character_create(mfs_context* ctx, const mfs_mesh_desc* d, mf
   MFS_TRY(ch->x.alloc(n3));
   MFS_TRY(ch->xb.alloc(n3));
   MFS_TRY(ch->s.alloc(6 * sizeof(double) * (size_t)m));
-  MFS_TRY(ch->blk.alloc(90 * sizeof(double) * (size_t)m));
-  MFS_TRY(ch->frc.alloc(12 * sizeof(double) * (size_t)m));
-  MFS_TRY(ch->b.alloc(n3));
-  MFS_TRY(ch->dx.alloc(n3));
-  MFS_TRY(ch->vals.alloc(9 * sizeof(double) * (size_t)nnzb));
-  MFS_TRY(ch->minv.alloc(6 * sizeof(double) * (size_t)n));
-  MFS_TRY(ch->r.alloc(n3));
-  MFS_TRY(ch->z.alloc(n3));
-  MFS_TRY(ch->p0.alloc(n3));
-  MFS_TRY(ch->p1.alloc(n3));
-  MFS_TRY(ch->q.alloc(n3));
-  MFS_TRY(ch->xc.alloc(n3));
-  MFS_TRY(ch->part.alloc(sizeof(double) * P_COUNT * (size_t)ch->ptile));
-  MFS_TRY(ch->red.alloc(sizeof(double) * P_COUNT));
+  ch->workspace_bytes = workspace_layout(ch);
+  MFS_TRY(ch->ws.alloc(ch->workspace_bytes));
   MFS_HIP(hipMemcpyAsync(ch->x.p, ch->X.p, n3, hipMemcpyDeviceToDevice, ctx->stream));
   MFS_HIP(hipStreamSynchronize(ctx->stream));
 
@@ -469,27 +523,12 @@ extern "C" int mfs_character_create(mfs_context* ctx, const mfs_mesh_desc* d, mf
   s.th = ch->th.as<double>();
   s.x = ch->x.as<double>();
   s.s = ch->s.as<double>();
-  s.blk = ch->blk.p;
-  s.frc = ch->frc.as<double>();
-  s.b = ch->b.as<double>();
-  s.dx = ch->dx.as<double>();
-  s.vals = ch->vals.p;
-  s.minv = ch->minv.p;
-  s.r = ch->r.p;
-  s.z = ch->z.p;
-  s.p0 = ch->p0.p;
-  s.p1 = ch->p1.p;
-  s.q = ch->q.p;
-  s.xc = ch->xc.p;
-  s.part = ch->part.as<double>();
-  s.red = ch->red.as<double>();
+  bind_workspace(ch, ch->ws.as<char>(), &s);
 
   ch->resident_bytes = ch->tets.bytes + ch->G.bytes + ch->wmu.bytes + ch->wlam.bytes + ch->info.bytes + ch->X.bytes +
                        ch->rowptr.bytes + ch->colidx.bytes + ch->slot_ptr.bytes + ch->contrib.bytes +
                        ch->diag.bytes + ch->vpin_ptr.bytes + ch->vpin_h.bytes + ch->perm_d.bytes +
                        ch->tperm_d.bytes + ch->x.bytes + ch->xb.bytes + ch->s.bytes + ch->Rh.bytes + ch->th.bytes;
-  ch->workspace_bytes = ch->blk.bytes + ch->frc.bytes + ch->b.bytes + ch->dx.bytes + ch->vals.bytes + ch->minv.bytes + ch->r.bytes +
-                        ch->z.bytes + ch->p0.bytes + ch->p1.bytes + ch->q.bytes + ch->xc.bytes + ch->part.bytes + ch->red.bytes;
   *out = guard.release();
   return MFS_OK;
 }
@@ -498,6 +537,16 @@ extern "C" int mfs_character_destroy(mfs_character* ch) {
   if (!ch) return MFS_OK;
   if (ch->ctx) (void)hipSetDevice(ch->ctx->device);
   delete ch;
+  return MFS_OK;
+}
+
+extern "C" int mfs_character_release_workspace(mfs_character* ch) {
+  if (!ch) return set_error(MFS_E_INVALID, "null character");
+  if (!ch->ws.p) return MFS_OK;
+  MFS_HIP(hipSetDevice(ch->ctx->device));
+  MFS_HIP(hipStreamSynchronize(ch->ctx->stream));
+  ch->ws.release();
+  bind_workspace(ch, nullptr, &ch->desc);
   return MFS_OK;
 }
 

@@ -352,6 +352,17 @@ int Engine::attach(int i, mfs_character* ch, const double* R, const double* t) {
   return MFS_OK;
 }
 
+int Engine::bind_workspace(int i, char* base) {
+  if (i < 0 || i >= (int)slot_.size() || !slot_[i].used) return set_error(MFS_E_INVALID, "slot %d is empty", i);
+  if (!base) return set_error(MFS_E_INVALID, "null workspace");
+  SysDesc& d = hd_[i];
+  double* red = d.red;
+  mfs::bind_workspace(slot_[i].ch, base, &d);
+  d.red = red;  // the slot's reduction row stays in the context
+  desc_dirty_ = true;
+  return MFS_OK;
+}
+
 int Engine::upload_desc() {
   if (!desc_dirty_) return MFS_OK;
   const int n = (int)slot_.size();
@@ -538,6 +549,9 @@ int Engine::step() {
   const Ctrl* dctrl = ctx->ctrl.as<Ctrl>();
   Ctrl* hc = ctx->h_ctrl.as<Ctrl>();
   const double* hr = ctx->h_red.as<double>();
+  for (int i = 0; i < n; ++i)
+    if (slot_[i].used && !slot_[i].done && !hd_[i].blk)
+      return set_error(MFS_E_INVALID, "slot %d has no workspace bound", i);
   MFS_TRY(upload_desc());
 
   // mixed warm start of newly attached slots: s0 = stretch factor of F(x0)
@@ -694,8 +708,9 @@ int Engine::output(int i, double* x_out, int mem) {
   if (mem == MFS_MEM_DEVICE) {
     launch_scatter_rows(st, ch->x.as<double>(), ch->perm_d.as<int32_t>(), ch->n, 3, 1.0, x_out);
   } else {
-    launch_scatter_rows(st, ch->x.as<double>(), ch->perm_d.as<int32_t>(), ch->n, 3, 1.0, ch->r.as<double>());
-    MFS_HIP(hipMemcpyAsync(x_out, ch->r.p, 3 * sizeof(double) * ch->n, hipMemcpyDeviceToHost, st));
+    double* stage = static_cast<double*>(hd_[i].r);  // the slot's PCG residual, free after the solve
+    launch_scatter_rows(st, ch->x.as<double>(), ch->perm_d.as<int32_t>(), ch->n, 3, 1.0, stage);
+    MFS_HIP(hipMemcpyAsync(x_out, stage, 3 * sizeof(double) * ch->n, hipMemcpyDeviceToHost, st));
   }
   MFS_HIP(hipGetLastError());
   MFS_HIP(hipStreamSynchronize(st));

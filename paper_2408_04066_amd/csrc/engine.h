@@ -66,6 +66,10 @@ class Engine {
   // uploaded, x0 set per the warm-start option.  The warm start runs at the
   // slot's first step.
   int attach(int slot, mfs_character* ch, const double* R, const double* t);
+  // Points the slot's workspace (element records, BSR values, PCG vectors)
+  // at `base`, workspace_layout(ch) bytes of device memory that stay valid
+  // until the slot retires; by default a slot uses the character's own.
+  int bind_workspace(int slot, char* base);
   // One Newton iteration for every occupied, unfinished slot.
   int step();
   // E(x) for finished slots whose last step did not produce it.

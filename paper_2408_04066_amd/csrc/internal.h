@@ -15,6 +15,7 @@ namespace mfs {
 
 int set_error(int code, const char* fmt, ...);
 void clear_error();
+const char* last_error_text();  // this thread's last error
 
 #define MFS_HIP(expr)                                                                          \
   do {                                                                                         \
@@ -117,9 +118,13 @@ struct mfs_character {
   mfs::DevBuf tets, G, wmu, wlam, info, X, rowptr, colidx, slot_ptr, contrib, diag, vpin_ptr, vpin_h, perm_d,
       tperm_d;
   // per-frame rig and solver state
-  mfs::DevBuf Rh, th, x, xb, s, blk, frc, b, dx, vals, minv, r, z, p0, p1, q, xc, part, red;
+  mfs::DevBuf Rh, th, x, xb, s;
+  // per-frame workspace (element records, BSR values, PCG vectors, partials):
+  // one allocation carved by workspace_layout; empty after
+  // mfs_character_release_workspace until a standalone solve needs it again
+  mfs::DevBuf ws;
   std::vector<double> last_R, last_t;  // pose of the last solved frame (warm-start homotopy origin)
-  mfs::SysDesc desc;  // pointers above, host copy
+  mfs::SysDesc desc;  // resident pointers + the own workspace's, host copy
   size_t resident_bytes = 0, workspace_bytes = 0;
 };
 
@@ -131,13 +136,20 @@ int solve_systems(mfs_context* ctx, int count, mfs_character* const* chars, cons
 
 int check_pose(const mfs_character* ch, const double* R, const double* t);
 
+// Workspace of one frame solve of `ch`: total bytes (pieces 256-byte
+// aligned), and the SysDesc workspace pointers carved from `base`.
+size_t workspace_layout(const mfs_character* ch);
+void bind_workspace(const mfs_character* ch, char* base, SysDesc* d);
+// Re-allocates the character's own workspace after a release.
+int ensure_workspace(mfs_character* ch);
+
 // Brackets one launch group of kernel family `fam` with an event pair when
 // the context profiler samples it.
 struct ProfScope {
   mfs_context* c;
   int fam;
   double bytes;
-  hipEvent_t a = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
   ProfScope(mfs_context* ctx, int family, double algorithmic_bytes = 0.0);
   ~ProfScope();
 };

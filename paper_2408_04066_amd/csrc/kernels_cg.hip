@@ -321,13 +321,13 @@ template <typename T, bool ONE>
 static void cg_spmv_t(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int lpr, const SysDesc& one) {
   switch (lpr) {
     case 2:
-      hipLaunchKernelGGL((k_cg_spmv<T, 2, ONE>), dim3(ntv), dim3(128), 0, st, sd, tv, ntv, one);
+      MFS_LAUNCH((k_cg_spmv<T, 2, ONE>), dim3(ntv), dim3(128), 0, st, sd, tv, ntv, one);
       break;
     case 8:
-      hipLaunchKernelGGL((k_cg_spmv<T, 8, ONE>), dim3(ntv), dim3(512), 0, st, sd, tv, ntv, one);
+      MFS_LAUNCH((k_cg_spmv<T, 8, ONE>), dim3(ntv), dim3(512), 0, st, sd, tv, ntv, one);
       break;
     default:
-      hipLaunchKernelGGL((k_cg_spmv<T, 4, ONE>), dim3(ntv), dim3(256), 0, st, sd, tv, ntv, one);
+      MFS_LAUNCH((k_cg_spmv<T, 4, ONE>), dim3(ntv), dim3(256), 0, st, sd, tv, ntv, one);
       break;
   }
 }
@@ -335,9 +335,9 @@ static void cg_spmv_t(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv
 void launch_cg_init(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32) {
   if (!ntv) return;
   if (fp32)
-    hipLaunchKernelGGL(k_cg_init<float>, dim3(ntv), dim3(64), 0, st, sd, tv, ntv);
+    MFS_LAUNCH(k_cg_init<float>, dim3(ntv), dim3(64), 0, st, sd, tv, ntv);
   else
-    hipLaunchKernelGGL(k_cg_init<double>, dim3(ntv), dim3(64), 0, st, sd, tv, ntv);
+    MFS_LAUNCH(k_cg_init<double>, dim3(ntv), dim3(64), 0, st, sd, tv, ntv);
 }
 
 void launch_cg_spmv(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, int lpr,
@@ -359,25 +359,25 @@ void launch_cg_update(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv
   static const SysDesc none{};
   const SysDesc& o = one ? *one : none;
   if (fp32) {
-    if (one) hipLaunchKernelGGL((k_cg_update<float, true>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv, o);
-    else hipLaunchKernelGGL((k_cg_update<float, false>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv, o);
+    if (one) MFS_LAUNCH((k_cg_update<float, true>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv, o);
+    else MFS_LAUNCH((k_cg_update<float, false>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv, o);
   } else {
-    if (one) hipLaunchKernelGGL((k_cg_update<double, true>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv, o);
-    else hipLaunchKernelGGL((k_cg_update<double, false>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv, o);
+    if (one) MFS_LAUNCH((k_cg_update<double, true>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv, o);
+    else MFS_LAUNCH((k_cg_update<double, false>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv, o);
   }
 }
 
 void launch_cg_finish(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32) {
   if (!ntv) return;
   if (fp32)
-    hipLaunchKernelGGL(k_cg_finish<float>, dim3(ntv), dim3(64), 0, st, sd, tv, ntv);
+    MFS_LAUNCH(k_cg_finish<float>, dim3(ntv), dim3(64), 0, st, sd, tv, ntv);
   else
-    hipLaunchKernelGGL(k_cg_finish<double>, dim3(ntv), dim3(64), 0, st, sd, tv, ntv);
+    MFS_LAUNCH(k_cg_finish<double>, dim3(ntv), dim3(64), 0, st, sd, tv, ntv);
 }
 
 void launch_spmv_plain(hipStream_t st, const int32_t* rowptr, const int32_t* colidx, const double* vals, int nnzb,
                        int n, const double* v, double* y) {
-  hipLaunchKernelGGL(k_spmv_plain, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, rowptr, colidx, vals, nnzb,
+  MFS_LAUNCH(k_spmv_plain, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, rowptr, colidx, vals, nnzb,
                      n, v, y);
 }
 

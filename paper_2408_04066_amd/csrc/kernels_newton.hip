@@ -404,34 +404,34 @@ __global__ __launch_bounds__(64) void k_finalize(const SysDesc* __restrict__ sd,
 
 // ---- launchers ----
 void launch_warm_start(hipStream_t st, const SysDesc* sd, const Tile* tiles, int ntiles, int fp32) {
-  if (ntiles) hipLaunchKernelGGL(k_warm_start, dim3(ntiles), dim3(kBlock), 0, st, sd, tiles, ntiles, fp32);
+  if (ntiles) MFS_LAUNCH(k_warm_start, dim3(ntiles), dim3(kBlock), 0, st, sd, tiles, ntiles, fp32);
 }
 void launch_element(hipStream_t st, const SysDesc* sd, const Ctrl* ctrl, const Tile* tiles, int ntiles, int fp32) {
   if (!ntiles) return;
   if (fp32)
-    hipLaunchKernelGGL(k_element<float>, dim3(ntiles), dim3(kBlock), 0, st, sd, ctrl, tiles, ntiles);
+    MFS_LAUNCH(k_element<float>, dim3(ntiles), dim3(kBlock), 0, st, sd, ctrl, tiles, ntiles);
   else
-    hipLaunchKernelGGL(k_element<double>, dim3(ntiles), dim3(kBlock), 0, st, sd, ctrl, tiles, ntiles);
+    MFS_LAUNCH(k_element<double>, dim3(ntiles), dim3(kBlock), 0, st, sd, ctrl, tiles, ntiles);
 }
 void launch_assemble(hipStream_t st, const SysDesc* sd, const Tile* tiles, int ntiles, int fp32) {
   if (!ntiles) return;
   if (fp32)
-    hipLaunchKernelGGL(k_assemble<float>, dim3(ntiles), dim3(kBlock), 0, st, sd, tiles, ntiles);
+    MFS_LAUNCH(k_assemble<float>, dim3(ntiles), dim3(kBlock), 0, st, sd, tiles, ntiles);
   else
-    hipLaunchKernelGGL(k_assemble<double>, dim3(ntiles), dim3(kBlock), 0, st, sd, tiles, ntiles);
+    MFS_LAUNCH(k_assemble<double>, dim3(ntiles), dim3(kBlock), 0, st, sd, tiles, ntiles);
 }
 void launch_linesearch(hipStream_t st, const SysDesc* sd, const Ctrl* ctrl, const Tile* tt, int ntt, const Tile* tv,
                        int ntv) {
-  if (ntt) hipLaunchKernelGGL(k_linesearch_tets, dim3(ntt), dim3(kBlock), 0, st, sd, ctrl, tt, ntt);
-  if (ntv) hipLaunchKernelGGL(k_linesearch_verts, dim3(ntv), dim3(64), 0, st, sd, ctrl, tv, ntv);
+  if (ntt) MFS_LAUNCH(k_linesearch_tets, dim3(ntt), dim3(kBlock), 0, st, sd, ctrl, tt, ntt);
+  if (ntv) MFS_LAUNCH(k_linesearch_verts, dim3(ntv), dim3(64), 0, st, sd, ctrl, tv, ntv);
 }
 void launch_update(hipStream_t st, const SysDesc* sd, const Ctrl* ctrl, const Tile* tt, int ntt, const Tile* tv,
                    int ntv) {
-  if (ntt) hipLaunchKernelGGL(k_update_s, dim3(ntt), dim3(kBlock), 0, st, sd, ctrl, tt, ntt);
-  if (ntv) hipLaunchKernelGGL(k_update_x, dim3(ntv), dim3(64), 0, st, sd, ctrl, tv, ntv);
+  if (ntt) MFS_LAUNCH(k_update_s, dim3(ntt), dim3(kBlock), 0, st, sd, ctrl, tt, ntt);
+  if (ntv) MFS_LAUNCH(k_update_x, dim3(ntv), dim3(64), 0, st, sd, ctrl, tv, ntv);
 }
 void launch_finalize(hipStream_t st, const SysDesc* sd, const int32_t* sys_ids, int nsys) {
-  if (nsys) hipLaunchKernelGGL(k_finalize, dim3(nsys), dim3(64), 0, st, sd, sys_ids);
+  if (nsys) MFS_LAUNCH(k_finalize, dim3(nsys), dim3(64), 0, st, sd, sys_ids);
 }
 
 }  // namespace mfs

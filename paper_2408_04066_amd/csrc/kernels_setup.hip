@@ -156,31 +156,31 @@ static inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock
 
 void launch_rest(hipStream_t st, const int4* tets, const double* X, const double* youngs, const double* poisson,
                  int m, double det_tol, double* G, double* wmu, double* wlam, uint8_t* bad) {
-  hipLaunchKernelGGL(k_rest, dim3(blocks_for(m)), dim3(kBlock), 0, st, tets, X, youngs, poisson, m, det_tol, G, wmu,
+  MFS_LAUNCH(k_rest, dim3(blocks_for(m)), dim3(kBlock), 0, st, tets, X, youngs, poisson, m, det_tol, G, wmu,
                      wlam, bad);
 }
 
 void launch_cluster(hipStream_t st, const double* X, const int32_t* tets, int64_t m, int nseg, const double* sa,
                     const double* sb, const int32_t* sh, int32_t* out) {
-  hipLaunchKernelGGL(k_cluster, dim3(blocks_for(m)), dim3(kBlock), 0, st, X, tets, m, nseg, sa, sb, sh, out);
+  MFS_LAUNCH(k_cluster, dim3(blocks_for(m)), dim3(kBlock), 0, st, X, tets, m, nseg, sa, sb, sh, out);
 }
 
 void launch_polar(hipStream_t st, const double* F, int64_t count, int fp32, double* U, double* P, double* smin,
                   uint8_t* routed) {
-  hipLaunchKernelGGL(k_polar, dim3(blocks_for(count)), dim3(kBlock), 0, st, F, count, fp32, U, P, smin, routed);
+  MFS_LAUNCH(k_polar, dim3(blocks_for(count)), dim3(kBlock), 0, st, F, count, fp32, U, P, smin, routed);
 }
 
 void launch_gather_rows(hipStream_t st, const double* src, const int32_t* perm, int count, int width, double* dst) {
-  hipLaunchKernelGGL(k_gather_rows, dim3(blocks_for(count)), dim3(kBlock), 0, st, src, perm, count, width, dst);
+  MFS_LAUNCH(k_gather_rows, dim3(blocks_for(count)), dim3(kBlock), 0, st, src, perm, count, width, dst);
 }
 
 void launch_scatter_rows(hipStream_t st, const double* src, const int32_t* perm, int count, int width, double sign,
                          double* dst) {
-  hipLaunchKernelGGL(k_scatter_rows, dim3(blocks_for(count)), dim3(kBlock), 0, st, src, perm, count, width, sign, dst);
+  MFS_LAUNCH(k_scatter_rows, dim3(blocks_for(count)), dim3(kBlock), 0, st, src, perm, count, width, sign, dst);
 }
 
 void launch_scatter_planes6(hipStream_t st, const double* planes, int m, const int32_t* tperm, double* dst) {
-  hipLaunchKernelGGL(k_scatter_planes6, dim3(blocks_for(m)), dim3(kBlock), 0, st, planes, m, tperm, dst);
+  MFS_LAUNCH(k_scatter_planes6, dim3(blocks_for(m)), dim3(kBlock), 0, st, planes, m, tperm, dst);
 }
 
 }  // namespace mfs

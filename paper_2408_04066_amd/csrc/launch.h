@@ -1,12 +1,36 @@
 // Host-side launchers of the library's kernels (one per kernel family).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "common.h"
 
 namespace mfs {
+
+// Event pair of a sampled profiler scope.  While `stop` is set, launches
+// through MFS_LAUNCH go out as hipExtLaunchKernelGGL with the events in the
+// dispatch itself: `start` takes the first kernel's start time and `stop`
+// each kernel's end time, so the interval is kernel execution without the
+// gaps of separately recorded events.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool started = false;
+};
+LaunchEvents& launch_events();  // this host thread's pair
+
+#define MFS_LAUNCH(kernel, grid, block, shmem, stream, ...)                                            \
+  do {                                                                                               \
+    ::mfs::LaunchEvents& le_ = ::mfs::launch_events();                                               \
+    if (le_.stop) {                                                                                  \
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, le_.started ? nullptr : le_.start, le_.stop, \
+                            0, __VA_ARGS__);                                                         \
+      le_.started = true;                                                                            \
+    } else {                                                                                         \
+      hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                           \
+    }                                                                                                \
+  } while (0)
 
 // setup and helpers
 void launch_rest(hipStream_t st, const int4* tets, const double* X, const double* youngs, const double* poisson,

@@ -1,8 +1,11 @@
-// Context profiler: sampled HIP-event pairs around kernel launch groups on
-// the context's stream, folded into per-family totals at stream syncs.
+// Context profiler: for every stride-th launch group of a kernel family, a
+// HIP event pair carried by the group's kernel dispatches (start of its
+// first kernel, end of its last), folded into per-family totals at stream
+// syncs.
 #include <cstring>
 
 #include "internal.h"
+#include "launch.h"
 
 namespace mfs {
 
@@ -17,24 +20,39 @@ static hipEvent_t get_event(mfs_context* c) {
   return e;
 }
 
+LaunchEvents& launch_events() {
+  static thread_local LaunchEvents ev;
+  return ev;
+}
+
+// A sampled scope hands its event pair to the launches inside it (see
+// MFS_LAUNCH); the pair is kept only if a kernel was launched.
 ProfScope::ProfScope(mfs_context* ctx, int family, double algorithmic_bytes)
     : c(ctx), fam(family), bytes(algorithmic_bytes) {
   const int64_t k = c->prof_launches[fam]++;
   if (c->prof_stride > 0 && k % c->prof_stride == 0) {
     a = get_event(c);
-    if (a && hipEventRecord(a, c->stream) != hipSuccess) {
-      c->ev_pool.push_back(a);
+    b = a ? get_event(c) : nullptr;
+    if (!b) {
+      if (a) c->ev_pool.push_back(a);
       a = nullptr;
+      return;
     }
+    LaunchEvents& le = launch_events();
+    le.start = a;
+    le.stop = b;
+    le.started = false;
   }
 }
 
 ProfScope::~ProfScope() {
   if (!a) return;
-  hipEvent_t b = get_event(c);
-  if (!b || hipEventRecord(b, c->stream) != hipSuccess) {
+  LaunchEvents& le = launch_events();
+  const bool launched = le.started;
+  le = LaunchEvents();
+  if (!launched) {
     c->ev_pool.push_back(a);
-    if (b) c->ev_pool.push_back(b);
+    c->ev_pool.push_back(b);
     return;
   }
   c->pending.push_back(ProfPending{fam, bytes, a, b});

@@ -66,7 +66,11 @@ int solve_systems(mfs_context* ctx, int count, mfs_character* const* chars, cons
   Engine eng(ctx);
   MFS_TRY(eng.configure(opts));
   MFS_TRY(eng.reserve(count));
-  for (int i = 0; i < count; ++i) MFS_TRY(eng.attach(i, chars[i], R[i], t[i]));
+  for (int i = 0; i < count; ++i) {
+    if (!chars[i] || chars[i]->ctx != ctx) return set_error(MFS_E_INVALID, "character %d is null or of another context", i);
+    MFS_TRY(ensure_workspace(chars[i]));
+    MFS_TRY(eng.attach(i, chars[i], R[i], t[i]));
+  }
   while (eng.any_busy()) MFS_TRY(eng.step());
   if (stats) MFS_TRY(eng.finish_energies());
   mfs_solve_opts o;
@@ -112,6 +116,7 @@ extern "C" int mfs_evaluate(mfs_character* ch, const double* handle_R, const dou
   MFS_HIP(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
   MFS_TRY(check_pose(ch, handle_R, handle_t));
+  MFS_TRY(ensure_workspace(ch));
   const bool host = memory_space == MFS_MEM_HOST;
   const size_t n3 = 3 * sizeof(double) * (size_t)ch->n;
   const size_t m6 = 6 * sizeof(double) * (size_t)ch->m;
@@ -147,13 +152,13 @@ extern "C" int mfs_evaluate(mfs_character* ch, const double* handle_R, const dou
   const Ctrl* dctrl = ctx->ctrl.as<Ctrl>();
   launch_element(st, dsd, dctrl, ts.dt, ts.nt, 0);
   launch_assemble(st, dsd, ts.ds, ts.ns, 0);
-  MFS_HIP(hipMemsetAsync(ch->dx.p, 0, n3, st));
+  MFS_HIP(hipMemsetAsync(ch->desc.dx, 0, n3, st));
   launch_linesearch(st, dsd, dctrl, ts.dt, ts.nt, ts.dv, ts.nv);
   launch_finalize(st, dsd, ctx->sys_ids.as<int32_t>(), 1);
   MFS_HIP(hipGetLastError());
   if (grad_out) {
     double* dst = host ? tmp : grad_out;
-    launch_scatter_rows(st, ch->b.as<double>(), ch->perm_d.as<int32_t>(), ch->n, 3, -1.0, dst);
+    launch_scatter_rows(st, ch->desc.b, ch->perm_d.as<int32_t>(), ch->n, 3, -1.0, dst);
     if (host) MFS_HIP(hipMemcpyAsync(grad_out, tmp, n3, hipMemcpyDeviceToHost, st));
   }
   if (stretch_out) {
@@ -167,11 +172,11 @@ extern "C" int mfs_evaluate(mfs_character* ch, const double* handle_R, const dou
       MFS_HIP(hipMemcpyAsync(tmp, v, n3, hipMemcpyHostToDevice, st));
       vs = tmp;
     }
-    launch_gather_rows(st, vs, ch->perm_d.as<int32_t>(), ch->n, 3, ch->p0.as<double>());
-    launch_spmv_plain(st, ch->rowptr.as<int32_t>(), ch->colidx.as<int32_t>(), ch->vals.as<double>(), ch->nnzb, ch->n,
-                      ch->p0.as<double>(), ch->q.as<double>());
+    launch_gather_rows(st, vs, ch->perm_d.as<int32_t>(), ch->n, 3, static_cast<double*>(ch->desc.p0));
+    launch_spmv_plain(st, ch->rowptr.as<int32_t>(), ch->colidx.as<int32_t>(), static_cast<const double*>(ch->desc.vals), ch->nnzb,
+                      ch->n, static_cast<const double*>(ch->desc.p0), static_cast<double*>(ch->desc.q));
     double* dst = host ? tmp : Kv_out;
-    launch_scatter_rows(st, ch->q.as<double>(), ch->perm_d.as<int32_t>(), ch->n, 3, 1.0, dst);
+    launch_scatter_rows(st, static_cast<const double*>(ch->desc.q), ch->perm_d.as<int32_t>(), ch->n, 3, 1.0, dst);
     if (host) MFS_HIP(hipMemcpyAsync(Kv_out, tmp, n3, hipMemcpyDeviceToHost, st));
   }
   MFS_HIP(hipGetLastError());

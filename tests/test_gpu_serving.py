@@ -1,0 +1,144 @@
+"""GPU tests of the serving loop (``mfs_server_*`` through the C ABI).
+
+A request's result is the same alone and in the mix: frames solved by the
+server while other requests join and leave the batch, some with workspaces
+lent from the server's arena, equal bitwise the same frames solved one at a
+time with ``mfs_solve_frame`` (the batch kernels keep per-character scalars
+and fixed-order reductions, so the tolerance of the claim is zero).
+"""
+
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from workloads import NH, COROT, humanoid, random_pose, animation_pose
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+OPTS = dict(precision=1, cg_tol=1e-5, step_tol=1e-9, cg_adaptive=1)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture()
+def mfs_ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2408_04066_amd as mfs
+    c = mfs.Context(0)
+    yield mfs, c
+    c.close()
+
+
+def _chars(mfs, ctx, specs, seed0):
+    probs = [humanoid(seed0 + i, target_tets=t, n_bones=b, models=(NH, COROT))
+             for i, (t, b) in enumerate(specs)]
+    return probs, [mfs.Character(ctx, p) for p in probs]
+
+
+def test_served_equals_alone_with_arena_admission(mfs_ctx):
+    mfs, ctx = mfs_ctx
+    probs, chars = _chars(mfs, ctx, [(1500, 8), (3000, 12), (800, 10), (2200, 9), (1200, 14)], 300)
+    poses = [random_pose(p, 400 + i) for i, p in enumerate(probs)]
+    alone = []
+    for ch, pose in zip(chars, poses):
+        _say(f"alone: n={ch.n}")
+        x, st, rc = ch.solve(*pose, **OPTS)
+        alone.append((x, st))
+    # three characters borrow workspaces; the arena holds the largest of
+    # them but not all three at once, so admission must wait for memory
+    ws = [ch.footprint()[1] for ch in chars[:3]]
+    budget = max(ws) + min(ws) + 4096
+    assert budget < sum(ws) + 3 * 256
+    for ch in chars[:3]:
+        ch.release_workspace()
+    _say(f"server: slots 3, arena {budget} bytes (workspaces {ws})")
+    srv = mfs.Server(ctx, slots=3, workspace_budget_bytes=budget, **OPTS)
+    order = [0, 1, 2, 0]
+    tickets = [(k, srv.submit(chars[k], *poses[k])) for k in order]
+    t0 = time.time()
+    while srv.info()["running"] == 0 and time.time() - t0 < 30:
+        time.sleep(0.001)
+    for k in (3, 4, 1):  # arrive while others are on the GPU
+        tickets.append((k, srv.submit(chars[k], *poses[k])))
+    got = []
+    for k, tk in tickets:
+        x, st, times, rc = srv.wait(tk)
+        got.append((k, x, st, times))
+    info = srv.info()
+    srv.close()
+    _say(f"server info {info}")
+    assert info["completed"] == len(tickets) and info["queued"] == 0 and info["running"] == 0
+    assert 0 < info["arena_peak"] <= budget and info["arena_in_use"] == 0
+    assert info["slot_steps"] / info["steps"] > 1.0  # requests overlapped in the batch
+    for k, x, st, times in got:
+        ref_x, ref_st = alone[k]
+        assert np.array_equal(x, ref_x), f"request for character {k} differs from its solve alone"
+        assert st["iterations"] == ref_st["iterations"] and st["cg_iterations"] == ref_st["cg_iterations"]
+        assert st["status"] == ref_st["status"]
+        assert times["submit_s"] <= times["admit_s"] <= times["done_s"]
+    # frames of one character ran in submission order
+    done0 = [t["done_s"] for k, _, _, t in got if k == 0]
+    admit0 = [t["admit_s"] for k, _, _, t in got if k == 0]
+    assert admit0[1] >= done0[0]
+    # a released character solves standalone again (own workspace re-made)
+    x, _, _ = chars[0].solve(*poses[0], **OPTS)
+    assert np.array_equal(x, alone[0][0])
+    for ch in chars:
+        ch.close()
+
+
+def test_served_warm_start_sequence_equals_standalone(mfs_ctx):
+    """Animation frames with warm start from the previous frame: served in
+    order per character, interleaved across characters, equal to the same
+    sequence solved standalone on fresh copies of the characters."""
+    mfs, ctx = mfs_ctx
+    specs = [(1500, 10), (2500, 12)]
+    probs, ref_chars = _chars(mfs, ctx, specs, 500)
+    frames = [[animation_pose(p, 600 + i, f / 24.0) for f in range(3)] for i, p in enumerate(probs)]
+    opts = dict(OPTS, warm_start=mfs.WARM_PREVIOUS)
+    ref = []
+    for ch, fr in zip(ref_chars, frames):
+        seq = []
+        for pose in fr:
+            x, st, rc = ch.solve(*pose, **opts)
+            seq.append(x)
+        ref.append(seq)
+        ch.close()
+    _, chars = _chars(mfs, ctx, specs, 500)
+    _say("server: warm-started animation, 2 characters x 3 frames")
+    srv = mfs.Server(ctx, slots=4, **opts)
+    tickets = [(i, f, srv.submit(chars[i], *frames[i][f])) for f in range(3) for i in range(2)]
+    out = {(i, f): srv.wait(tk)[0] for i, f, tk in tickets}
+    srv.close()
+    for i in range(2):
+        for f in range(3):
+            assert np.array_equal(out[(i, f)], ref[i][f])
+    for ch in chars:
+        ch.close()
+
+
+def test_server_rejects_bad_requests(mfs_ctx):
+    mfs, ctx = mfs_ctx
+    probs, chars = _chars(mfs, ctx, [(800, 8)], 700)
+    ch = chars[0]
+    srv = mfs.Server(ctx, slots=2, queue_capacity=1, **OPTS)
+    R, t = random_pose(probs[0], 701)
+    bad = R.copy()
+    bad[0] *= 2.0
+    with pytest.raises(mfs.MfsError) as e:
+        srv.submit(ch, bad, t)
+    assert e.value.code == -1
+    ch.release_workspace()  # no arena: its workspace can never be lent
+    with pytest.raises(mfs.MfsError) as e:
+        srv.submit(ch, R, t)
+    assert e.value.code == -6
+    srv.close()
+    ch.close()

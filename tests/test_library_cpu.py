@@ -39,11 +39,36 @@ def test_host_only_calls():
         mfs.default_opts(no_such_option=1)
 
 
-def test_struct_layouts_match_header():
-    # offsets implied by the C declarations (natural alignment, LP64)
-    assert ctypes.sizeof(mfs.MeshDesc) == 112
-    assert mfs.MeshDesc.pin_stiffness.offset == 96
-    assert ctypes.sizeof(mfs.SolveOpts) == 56
-    assert mfs.SolveOpts.step_tol.offset == 16 and mfs.SolveOpts.cg_max.offset == 32
-    assert ctypes.sizeof(mfs.SolveStats) == 64
-    assert mfs.SolveStats.energy.offset == 32
+STRUCTS = {"mfs_mesh_desc": "MeshDesc", "mfs_solve_opts": "SolveOpts", "mfs_solve_stats": "SolveStats",
+           "mfs_character_info": "CharacterInfo", "mfs_tuning": "Tuning", "mfs_profile": "Profile",
+           "mfs_server_opts": "ServerOpts", "mfs_request_times": "RequestTimes",
+           "mfs_server_info": "ServerInfo"}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes mirror has the size and field offsets that gcc gives the
+    header's declarations."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mfs.h"', "int main(void) {"]
+    for cname, pyname in STRUCTS.items():
+        lines.append(f'  printf("{pyname} size %zu\\n", sizeof({cname}));')
+        for field, _ in getattr(mfs, pyname)._fields_:
+            lines.append(f'  printf("{pyname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    seen = 0
+    for line in filter(None, out):
+        pyname, field, value = line.split()
+        cls = getattr(mfs, pyname)
+        got = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert got == int(value), f"{pyname}.{field}: ctypes {got}, C {value}"
+        seen += 1
+    assert seen == sum(len(getattr(mfs, p)._fields_) + 1 for p in STRUCTS.values())

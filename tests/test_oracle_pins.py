@@ -351,3 +351,40 @@ def test_clusters_match_bruteforce():
     cb = oracle.cluster_by_segments(bm["X"], bm["T"], bm["seg_a"], bm["seg_b"], bm["seg_handle"])
     bx = bm["X"][bm["T"]].mean(axis=1)[:, 0]
     assert np.array_equal(cb, (bx > 8).astype(np.int32))
+
+
+def test_interpolate_pose_is_the_matrix_exponential_screw():
+    """Load-stepping poses: T(tau) = T0 expm(tau logm(T0^-1 T1)) on 4x4
+    homogeneous matrices (scipy's general matrix exp/log), the one-parameter
+    subgroup property (T0^-1 T(1/2))^2 = T0^-1 T1, and a handle rotated
+    about a fixed point keeps that point fixed at every tau."""
+    import scipy.linalg as sla
+    from workloads.common import euler_xyz
+    rng = np.random.default_rng(11)
+    nh = 5
+    R0 = np.stack([euler_xyz(*rng.uniform(-1.0, 1.0, 3)) for _ in range(nh)])
+    t0 = rng.normal(size=(nh, 3))
+    R1 = np.stack([euler_xyz(*rng.uniform(-1.2, 1.2, 3)) for _ in range(nh)])
+    t1 = rng.normal(size=(nh, 3))
+    # handle 0: relative motion is a pure rotation about the point c
+    c = np.array([0.3, -0.7, 1.1])
+    Rrel = R1[0] @ R0[0].T
+    t1[0] = Rrel @ (t0[0] - c) + c  # T1 = Rot_c o T0  =>  T1 (T0^-1 c) = c
+    def hom(R, t):
+        M = np.eye(4)
+        M[:3, :3], M[:3, 3] = R, t
+        return M
+    for tau in (0.0, 0.25, 0.5, 0.8125, 1.0):
+        R, t = oracle.interpolate_pose((R0, t0), (R1, t1), tau)
+        for h in range(nh):
+            T0, T1 = hom(R0[h], t0[h]), hom(R1[h], t1[h])
+            ref = T0 @ np.real(sla.expm(tau * sla.logm(np.linalg.solve(T0, T1))))
+            assert np.abs(hom(R[h], t[h]) - ref).max() < 1e-10
+        # the rotation centre of handle 0 stays where T0 put its preimage
+        p = np.linalg.solve(R0[0], c - t0[0])
+        assert np.abs(R[0] @ p + t[0] - c).max() < 1e-10
+    Rh, th = oracle.interpolate_pose((R0, t0), (R1, t1), 0.5)
+    for h in range(nh):
+        A = np.linalg.solve(hom(R0[h], t0[h]), hom(Rh[h], th[h]))
+        B = np.linalg.solve(hom(R0[h], t0[h]), hom(R1[h], t1[h]))
+        assert np.abs(A @ A - B).max() < 1e-10
