@@ -1,27 +1,42 @@
 """Benchmark of the mixed-FEM skinning frame solve on one MI355X.
 
-Default workload (``--workload c2``): a seeded procedural humanoid of ~50k
-tets / ~10k vertices with 20 bone handles, neo-Hookean or ARAP per limb
-(E log-uniform in [1e4, 1e6], nu uniform in [0.3, 0.49]); each step solves
-one frame at a fresh random pose (joint Euler angles uniform in +-45 degrees)
-from the rest shape.  ``c1`` is the 16x4x4 neo-Hookean beam, ``c3`` the same
-humanoid generator at ~500k tets / 30 handles, ``c4`` a batch of 64 humanoids
-of 5k-200k tets (log-uniform), 8-30 handles, neo-Hookean / co-rotated per
-limb, solved together in one batched run per step.
+Workloads (``--workload``; seeded synthetic inputs, resident in HBM before
+timing):
 
-The timed path is the FP32 + FP64-refinement form (FP32 Hessian values and
-PCG; FP64 residual, energies and updates), inexact Newton (Eisenstat-Walker
-forcing over a 1e-5 PCG floor), stopped at a 1e-8 * bbox Newton step.  The
-FP64 form of the same solve (identical options, FP64 Hessian and PCG) runs
-beside it on the first poses and the two results are compared.  Characters
-are resident in HBM before timing; a step uploads only handle transforms
-and writes positions to device tensors.
+* ``c2`` (default): a procedural humanoid of ~50k tets / ~10k vertices with
+  20 bone handles, neo-Hookean or ARAP per limb (E log-uniform in [1e4,
+  1e6], nu uniform in [0.3, 0.49]); each step solves one frame at a fresh
+  random pose (joint Euler angles uniform in +-45 degrees) from the rest
+  shape.
+* ``c1``: the 16x4x4 neo-Hookean beam (1536 tets), FP64, exactly 10 Newton
+  iterations with PCG tolerance 1e-10 per step.
+* ``c3``: the same generator at ~500k tets / 30 handles; an animation of
+  seeded sinusoidal joint angles (60 degrees, periods 2-5 s, 30 fps), each
+  frame warm-started from the previous one (a step is one frame).
+* ``c4``: 64 humanoids of 5k-200k tets (log-uniform), 8-30 handles,
+  neo-Hookean / co-rotated per limb, solved together in one batched run per
+  step.
+
+Before timing, the autotuner picks the PCG schedule (two-kernel or
+pipelined form, lanes per row, graph length, run sizing) on the first
+step's frames (``--no-autotune`` keeps the default).
+* ``c5``: serving: a pool of characters of 2k-300k tets and a Poisson stream
+  of frame requests (fresh random pose of a uniformly chosen character)
+  through the continuous-batching server; reports p50/p99 latency.
+
+The timed path (c2-c5) is the FP32 + FP64-refinement form (FP32 Hessian
+values and PCG; FP64 residual, energies and updates), inexact Newton
+(Eisenstat-Walker forcing over a 1e-5 PCG floor), stopped at a 1e-8 * bbox
+Newton step.  The FP64 form of the same solve runs beside it on the first
+poses and the two results are compared.  A step uploads only handle
+transforms and writes positions to device tensors.
 
 Prints one JSON line: throughput in tet * Newton-iterations / s, frames/s,
 p50/p99 frame latency, the roofline entry of the dominant kernel (the PCG
-block-sparse matrix-vector product; algorithmic bytes over HIP-event time,
-measured in a second pass over the same frames with the event profiler on)
-and the FP64 CPU oracle timed on this host on a bounded sample.
+block-sparse matrix-vector product; algorithmic bytes over its average
+kernel duration, from HIP events carried by the sampled dispatches in a
+second pass over the same kind of frames) and the FP64 CPU oracle timed on
+this host on a bounded sample.
 """
 
 import argparse
@@ -38,23 +53,35 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def make_workload(name):
-    """(problems, pose_of(step) -> list of poses, workload name)."""
-    from workloads import NH, COROT, humanoid, random_pose, beam, beam_pose, character_pool
+    """(problems, poses_of(step) -> list of poses, workload name, options)."""
+    from workloads import (NH, COROT, humanoid, random_pose, animation_pose, beam, beam_pose,
+                           character_pool)
+    fp32 = dict(precision=1, cg_tol=1e-5, step_tol=1e-8, max_newton=60, cg_adaptive=1)
     if name == "c1":
         p = beam()
-        return [p], (lambda i: [beam_pose(p)]), "beam_16x4x4_neohookean_twist30_stretch2"
+        return [p], (lambda i: [beam_pose(p)]), "beam_16x4x4_neohookean_twist30_stretch2", \
+            dict(precision=0, cg_tol=1e-10, max_newton=10, fixed_newton=1)
     if name == "c2":
         p = humanoid(2001, target_tets=50000, n_bones=20)
-        return [p], (lambda i: [random_pose(p, 2002 + i)]), "humanoid_50k_tets_20_handles_random_pose"
+        return [p], (lambda i: [random_pose(p, 2002 + i)]), "humanoid_50k_tets_20_handles_random_pose", fp32
     if name == "c3":
         p = humanoid(3001, target_tets=500000, n_bones=30)
-        return [p], (lambda i: [random_pose(p, 3002 + i)]), "humanoid_500k_tets_30_handles_random_pose"
+        return [p], (lambda i: [animation_pose(p, 3002, i)]), \
+            "humanoid_500k_tets_30_handles_animation_30fps_warm_started", dict(fp32, warm_start=1)
     if name == "c4":
-        ps = character_pool(64, 4001, (5000, 200000), (8, 30), (NH, COROT))
+        ps = character_pool(64, 4001, (5000, 200000), (8, 30), (NH, COROT), workers=_workers())
         return ps, (lambda i: [random_pose(p, 41000 + 100 * i + k) for k, p in enumerate(ps)]), \
-            "batch_64_humanoids_5k_200k_tets_8_30_handles"
+            "batch_64_humanoids_5k_200k_tets_8_30_handles", fp32
     raise SystemExit(f"unknown workload {name}")
+
+
+def _workers():
+    return max(1, min(16, os.cpu_count() or 1))
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_spmv_humanoid50k.md")
@@ -70,10 +97,11 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def counted_traffic(workload):
-    """HBM bytes per SpMV launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary (copy-kernel scaled), or None when that summary is
-    for another workload or the kernel sources changed since it was taken."""
+def counted_traffic(workload, kernel):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (copy-kernel scaled), or None
+    when that summary is for another workload or kernel, or the kernel
+    sources changed since it was taken."""
     try:
         lines = open(TRAFFIC_SUMMARY).read().splitlines()
     except OSError:
@@ -83,7 +111,8 @@ def counted_traffic(workload):
         if line.startswith("- ") and ": " in line:
             k, v = line[2:].split(": ", 1)
             kv[k.strip("`")] = v.strip().strip("`")
-    if kv.get("workload") != workload or kv.get("kernel_sources_sha256") != kernel_source_hash():
+    if (kv.get("workload") != workload or kv.get("kernel") != kernel
+            or kv.get("kernel_sources_sha256") != kernel_source_hash()):
         return None
     try:
         return float(kv["traffic_bytes_per_launch"])
@@ -119,6 +148,233 @@ def cpu_baseline(prob, pose, iterations=2):
     }
 
 
+def frame_bench(args, mfs, torch):
+    probs, pose_of, wname, opts = make_workload(args.workload)
+    ctx = mfs.Context(0)
+    chars = [mfs.Character(ctx, p) for p in probs]
+    infos = [c.info() for c in chars]
+    m_tot = sum(i["n_tets"] for i in infos)
+    outs = [torch.empty((i["n_vertices"], 3), dtype=torch.float64, device="cuda") for i in infos]
+    steps = [pose_of(i) for i in range(args.warmup + args.steps + max(args.roofline_steps, args.fp64_steps))]
+    fp64_opts = dict(opts, precision=mfs.FP64)
+    warm = opts.get("warm_start", 0) == mfs.WARM_PREVIOUS
+    _progress(f"{wname}: {len(chars)} characters resident, {m_tot} tets")
+    tuned = None
+    if not args.no_autotune:
+        tuned, tms = mfs.autotune(ctx, chars, steps[0], newton_iterations=4, **opts)
+        _progress(f"autotuned PCG schedule {tuned} ({tms:.1f} ms per 4 Newton iterations)")
+
+    def frame(poses, o):
+        if len(chars) == 1:
+            _, st, rc = chars[0].solve(*poses[0], out=outs[0], **o)
+            return [st], rc
+        _, sts, rc = mfs.solve_batch(ctx, chars, poses, outs=outs, **o)
+        return sts, rc
+
+    for i in range(args.warmup):
+        frame(steps[i], opts)
+    torch.cuda.synchronize()
+    _progress("warmup done")
+
+    # ---- timed region ----
+    lat, tet_iters, iters, cgs, rcs, conv = [], 0, [], [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        sts, rc = frame(steps[args.warmup + i], opts)
+        lat.append(time.perf_counter() - ts)
+        tet_iters += sum(inf["n_tets"] * st["iterations"] for inf, st in zip(infos, sts))
+        iters.append(np.mean([st["iterations"] for st in sts]))
+        cgs.append(np.mean([st["cg_iterations"] for st in sts]))
+        rcs.append(rc)
+        conv += [st["status"] == 0 for st in sts]
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    _progress(f"timed {args.steps} steps in {total:.2f} s")
+
+    # ---- roofline pass: frames of the same kind (the next poses of the
+    # sequence), kernels launched directly, every stride-th launch of each
+    # family timed by HIP events carried in its dispatches ----
+    nxt = args.warmup + args.steps
+    ctx.profile_enable(args.profile_stride)
+    ctx.profile_read(reset=True)
+    for i in range(args.roofline_steps):
+        frame(steps[nxt + i], opts)
+    prof = ctx.profile_read(reset=True)
+    ctx.profile_enable(0)
+    _progress("roofline pass done")
+
+    # ---- FP32 + refinement against the FP64 form of the same solve, both
+    # from the rest shape ----
+    lat64, tet_iters64, err = [], 0, []
+    rest_opts = dict(opts, warm_start=mfs.WARM_REST)
+    for i in range(args.fp64_steps):
+        poses = steps[nxt + i]
+        s32, _ = frame(poses, rest_opts)
+        x32 = [o.cpu().numpy().copy() for o in outs]
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        s64, _ = frame(poses, dict(fp64_opts, warm_start=mfs.WARM_REST))
+        torch.cuda.synchronize()
+        lat64.append(time.perf_counter() - ts)
+        tet_iters64 += sum(inf["n_tets"] * st["iterations"] for inf, st in zip(infos, s64))
+        # compared where both forms converged (a frame stopped by the Newton
+        # cap is an unconverged iterate in either precision)
+        for o, a, st32, st64, inf in zip(outs, x32, s32, s64, infos):
+            if st32["status"] == 0 and st64["status"] == 0:
+                err.append(float(np.max(np.linalg.norm(a - o.cpu().numpy(), axis=1))) / inf["bbox_diag"])
+
+    spmv_ms, spmv_timed, spmv_launches, spmv_bytes = prof["spmv"]
+    achieved = spmv_bytes / (spmv_ms * 1e-3) / 1e9 if spmv_ms > 0 else None
+    nchar = len(chars)
+    fp32 = opts["precision"] == mfs.FP32_REFINED
+    pipelined = fp32 and ctx.tuning()["pcg_pipelined"] == 1
+    kernel = ("k_pcg_iter<float>" if pipelined else "k_cg_spmv<float>") if fp32 else "k_cg_spmv<double>"
+    result = {
+        "metric": "tet*Newton-iter/s (frames/s at 1e-7 rel err; p50/p99 frame latency)",
+        "value": tet_iters / total,
+        "unit": "tet*Newton-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if opts["precision"] == mfs.FP32_REFINED else "f64",
+        "data": "synthetic",
+        "frames_per_s": nchar * args.steps / total,
+        "latency_ms_p50": 1e3 * float(np.percentile(lat, 50)),
+        "latency_ms_p99": 1e3 * float(np.percentile(lat, 99)),
+        "newton_iters_per_frame": float(np.mean(iters)),
+        "cg_iters_per_frame": float(np.mean(cgs)),
+        "status_codes": sorted(set(int(r) for r in rcs)),
+        "converged_fraction": float(np.mean(conv)),
+        "fp64": {
+            "frames_per_s": nchar * len(lat64) / sum(lat64) if lat64 else None,
+            "tet_newton_iter_per_s": tet_iters64 / sum(lat64) if lat64 else None,
+            "max_rel_diff_fp32_vs_fp64": (max(err) if err else None) if opts["precision"] else None,
+        },
+        "config": {"workload": wname, "characters": nchar, "tets": m_tot,
+                   "vertices": sum(i["n_vertices"] for i in infos),
+                   "blocks": sum(i["n_blocks"] for i in infos),
+                   "handles": [i["n_handles"] for i in infos] if nchar > 1 else infos[0]["n_handles"],
+                   "precision": "fp32 pcg + fp64 refinement" if opts["precision"] else "fp64",
+                   "cg_tol_floor": opts["cg_tol"],
+                   "cg_forcing": "eisenstat-walker" if opts.get("cg_adaptive") else "fixed",
+                   "step_tol_bbox": opts.get("step_tol"),
+                   "newton": "fixed 10" if opts.get("fixed_newton") else f"max {opts['max_newton']}",
+                   "warm_start": "previous frame" if warm else "rest",
+                   "pcg_schedule": tuned or ctx.tuning()},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": kernel,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": counted_traffic(wname, kernel),
+            "bytes_per_launch": spmv_bytes / max(spmv_timed, 1),
+            "avg_launch_us": 1e3 * spmv_ms / max(spmv_timed, 1),
+            "timed_launches": spmv_timed,
+            "launches": spmv_launches,
+        },
+        "kernel_ms_sampled": {k: v[0] for k, v in prof.items()},
+        "kernel_timed": {k: v[1] for k, v in prof.items()},
+        "kernel_launches": {k: v[2] for k, v in prof.items()},
+    }
+    if not args.no_cpu_baseline:
+        k = int(np.argmin([len(p["T"]) for p in probs]))
+        result["cpu_baseline"] = cpu_baseline(probs[k], steps[args.warmup][k])
+    for c in chars:
+        c.close()
+    ctx.close()
+    return result
+
+
+def serve_bench(args, mfs, torch):
+    """Poisson stream of frame requests through the serving loop."""
+    from workloads import NH, COROT, ARAP, character_pool, random_pose
+    probs = character_pool(args.pool, 5001, (2000, 300000), (8, 30), (NH, COROT, ARAP),
+                           workers=_workers())
+    ctx = mfs.Context(0)
+    chars = [mfs.Character(ctx, p) for p in probs]
+    infos = [c.info() for c in chars]
+    ws = sorted((c.footprint()[1] for c in chars), reverse=True)
+    for c in chars:
+        c.release_workspace()
+    budget = 2 * sum(ws[:args.slots])
+    opts = dict(precision=1, cg_tol=1e-5, step_tol=1e-8, max_newton=60, cg_adaptive=1)
+    rng = np.random.default_rng(5002)
+    n_req = int(args.rate * args.duration)
+    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, size=n_req))
+    who = rng.integers(0, len(chars), size=n_req)
+    poses = [random_pose(probs[k], 50000 + j) for j, k in enumerate(who)]
+    srv = mfs.Server(ctx, slots=args.slots, queue_capacity=args.queue, workspace_budget_bytes=budget, **opts)
+    for j in range(min(args.warmup, n_req)):  # warm the kernels and graphs
+        srv.wait(srv.submit(chars[who[j]], *poses[j]))
+    info0 = srv.info()
+    tickets, rejected = [], 0
+    t0 = time.perf_counter()
+    _progress(f"pool of {len(chars)} characters resident; streaming {n_req} requests")
+    for j in range(n_req):
+        if j % 1000 == 0 and j:
+            _progress(f"submitted {j} requests, {srv.info()['completed']} completed")
+        delay = arrivals[j] - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        try:
+            tickets.append((who[j], srv.submit(chars[who[j]], *poses[j])))
+        except mfs.MfsError as e:
+            if e.code != -6:
+                raise
+            rejected += 1
+    lat, tet_iters, done_t, conv, first_submit = [], 0, [], [], None
+    for k, tk in tickets:
+        _, st, tm, _ = srv.wait(tk)
+        lat.append(tm["done_s"] - tm["submit_s"])
+        first_submit = tm["submit_s"] if first_submit is None else min(first_submit, tm["submit_s"])
+        done_t.append(tm["done_s"])
+        tet_iters += infos[k]["n_tets"] * st["iterations"]
+        conv.append(st["status"] == 0)
+    info = srv.info()
+    srv.close()
+    span = max(done_t) - first_submit
+    steps = info["steps"] - info0["steps"]
+    result = {
+        "metric": "tet*Newton-iter/s (frames/s at 1e-7 rel err; p50/p99 frame latency)",
+        "value": tet_iters / span,
+        "unit": "tet*Newton-iter/s",
+        "n_gpus": 1,
+        "steps": len(tickets),
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * span / max(len(tickets), 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "frames_per_s": len(tickets) / span,
+        "latency_ms_p50": 1e3 * float(np.percentile(lat, 50)),
+        "latency_ms_p99": 1e3 * float(np.percentile(lat, 99)),
+        "offered_rate_per_s": args.rate,
+        "requests": n_req,
+        "rejected_queue_full": rejected,
+        "converged_fraction": float(np.mean(conv)),
+        "mean_batch_width": (info["slot_steps"] - info0["slot_steps"]) / max(steps, 1),
+        "arena_peak_bytes": info["arena_peak"],
+        "config": {"workload": f"serving_pool_{args.pool}_humanoids_2k_300k_tets_poisson_{args.rate:g}_per_s",
+                   "characters": len(chars), "tets": sum(i["n_tets"] for i in infos),
+                   "slots": args.slots, "queue_capacity": args.queue, "arena_bytes": budget,
+                   "duration_s": args.duration, "precision": "fp32 pcg + fp64 refinement"},
+    }
+    for c in chars:
+        c.close()
+    ctx.close()
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,13 +385,19 @@ def main():
     ap.add_argument("--profile-stride", type=int, default=8)
     ap.add_argument("--roofline-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default PCG schedule")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (the reference kernel "
                          "that scales HBM byte counters)")
+    ap.add_argument("--pool", type=int, default=200, help="c5: resident characters")
+    ap.add_argument("--rate", type=float, default=300.0, help="c5: Poisson arrivals per second")
+    ap.add_argument("--duration", type=float, default=60.0, help="c5: seconds of arrivals")
+    ap.add_argument("--slots", type=int, default=16, help="c5: requests in flight at once")
+    ap.add_argument("--queue", type=int, default=512, help="c5: queued requests before rejection")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: one character's frame solve is not split across "
-              "GPUs in this build (DESIGN.md describes how it would shard)", file=sys.stderr)
+        print("bench.py measures one GPU: each frame solve runs on a single device and "
+              "multi-GPU sharding is not implemented", file=sys.stderr)
         return 2
     if int(os.environ.get("RANK", "0")) != 0:
         return 0
@@ -151,129 +413,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    probs, pose_of, wname = make_workload(args.workload)
-    ctx = mfs.Context(0)
-    chars = [mfs.Character(ctx, p) for p in probs]
-    infos = [c.info() for c in chars]
-    m_tot = sum(i["n_tets"] for i in infos)
-    outs = [torch.empty((i["n_vertices"], 3), dtype=torch.float64, device="cuda") for i in infos]
-    steps = [pose_of(i) for i in range(args.warmup + args.steps)]
-    common = dict(cg_tol=1e-5, step_tol=1e-8, max_newton=60, cg_adaptive=1)
-    fp32_opts = dict(precision=mfs.FP32_REFINED, **common)
-    fp64_opts = dict(precision=mfs.FP64, **common)
-
-    def frame(poses, opts):
-        if len(chars) == 1:
-            _, st, rc = chars[0].solve(*poses[0], out=outs[0], **opts)
-            return [st], rc
-        _, sts, rc = mfs.solve_batch(ctx, chars, poses, outs=outs, **opts)
-        return sts, rc
-
-    for i in range(args.warmup):
-        frame(steps[i], fp32_opts)
-    torch.cuda.synchronize()
-
-    # ---- timed region: FP32 + FP64 refinement (PCG runs replayed as graphs) ----
-    lat, tet_iters, iters, cgs, rcs, conv = [], 0, [], [], [], []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ts = time.perf_counter()
-        sts, rc = frame(steps[args.warmup + i], fp32_opts)
-        lat.append(time.perf_counter() - ts)
-        tet_iters += sum(inf["n_tets"] * st["iterations"] for inf, st in zip(infos, sts))
-        iters.append(np.mean([st["iterations"] for st in sts]))
-        cgs.append(np.mean([st["cg_iterations"] for st in sts]))
-        rcs.append(rc)
-        conv += [st["status"] == 0 for st in sts]
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-
-    # ---- roofline pass: the same frames with sampled HIP-event timing of
-    # every kernel family (direct launches; one event pair per timed launch) ----
-    x32 = []
-    ctx.profile_enable(args.profile_stride)
-    ctx.profile_read(reset=True)
-    for i in range(max(min(args.steps, args.roofline_steps), min(args.steps, args.fp64_steps))):
-        sts32, _ = frame(steps[args.warmup + i], fp32_opts)
-        if i < args.fp64_steps:
-            x32.append(([o.cpu().numpy().copy() for o in outs], [st["status"] for st in sts32]))
-    prof = ctx.profile_read(reset=True)
-    ctx.profile_enable(0)
-
-    # ---- the FP64 form of the same solve on the first poses ----
-    lat64, tet_iters64, err = [], 0, []
-    for i in range(min(args.fp64_steps, args.steps)):
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        sts, rc = frame(steps[args.warmup + i], fp64_opts)
-        torch.cuda.synchronize()
-        lat64.append(time.perf_counter() - ts)
-        tet_iters64 += sum(inf["n_tets"] * st["iterations"] for inf, st in zip(infos, sts))
-        # compared where both forms converged (a frame stopped by the Newton
-        # cap is an unconverged iterate in either precision)
-        for o, a, s32, st, inf in zip(outs, x32[i][0], x32[i][1], sts, infos):
-            if s32 == 0 and st["status"] == 0:
-                err.append(float(np.max(np.linalg.norm(a - o.cpu().numpy(), axis=1))) / inf["bbox_diag"])
-
-    spmv_ms, spmv_timed, spmv_launches, spmv_bytes = prof["spmv"]
-    achieved = spmv_bytes / (spmv_ms * 1e-3) / 1e9 if spmv_ms > 0 else None
-    nchar = len(chars)
-    result = {
-        "metric": "tet*Newton-iter/s (frames/s at 1e-7 rel err; p50/p99 frame latency)",
-        "value": tet_iters / total,
-        "unit": "tet*Newton-iter/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * total / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "frames_per_s": nchar * args.steps / total,
-        "latency_ms_p50": 1e3 * float(np.percentile(lat, 50)),
-        "latency_ms_p99": 1e3 * float(np.percentile(lat, 99)),
-        "newton_iters_per_frame": float(np.mean(iters)),
-        "cg_iters_per_frame": float(np.mean(cgs)),
-        "status_codes": sorted(set(int(r) for r in rcs)),
-        "converged_fraction": float(np.mean(conv)),
-        "fp64": {
-            "frames_per_s": nchar * len(lat64) / sum(lat64) if lat64 else None,
-            "tet_newton_iter_per_s": tet_iters64 / sum(lat64) if lat64 else None,
-            "max_rel_diff_fp32_vs_fp64": max(err) if err else None,
-        },
-        "config": {"workload": wname, "characters": nchar, "tets": m_tot,
-                   "vertices": sum(i["n_vertices"] for i in infos),
-                   "blocks": sum(i["n_blocks"] for i in infos),
-                   "handles": [i["n_handles"] for i in infos] if nchar > 1 else infos[0]["n_handles"],
-                   "precision": "fp32 pcg + fp64 refinement", "cg_tol_floor": common["cg_tol"],
-                   "cg_forcing": "eisenstat-walker", "step_tol_bbox": common["step_tol"]},
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_cg_spmv<float>",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS if achieved else None,
-            "traffic": counted_traffic(wname),
-            "bytes_per_launch": spmv_bytes / max(spmv_timed, 1),
-            "avg_launch_us": 1e3 * spmv_ms / max(spmv_timed, 1),
-            "timed_launches": spmv_timed,
-            "launches": spmv_launches,
-        },
-        "kernel_ms_sampled": {k: v[0] for k, v in prof.items()},
-        "kernel_timed": {k: v[1] for k, v in prof.items()},
-        "kernel_launches": {k: v[2] for k, v in prof.items()},
-    }
-    if not args.no_cpu_baseline:
-        k = int(np.argmin([len(p["T"]) for p in probs]))
-        result["cpu_baseline"] = cpu_baseline(probs[k], steps[args.warmup][k])
+    result = serve_bench(args, mfs, torch) if args.workload == "c5" else frame_bench(args, mfs, torch)
     print(json.dumps(result), flush=True)
-    for c in chars:
-        c.close()
-    ctx.close()
     return 0
 
 

@@ -157,6 +157,9 @@ typedef struct mfs_tuning {
   int32_t graph_iterations;   /* PCG iterations per captured graph, 1..64 */
   int32_t first_check;        /* PCG iterations before the first convergence check */
   int32_t min_run, max_run;   /* bounds of later runs between checks */
+  int32_t pcg_pipelined;      /* 1: FP32_REFINED solves run the pipelined PCG of Ghysels and
+                                 Vanroose (one kernel per iteration, dot products overlapped
+                                 with the SpMV); FP64 solves always run the two-kernel form */
 } mfs_tuning;
 
 int mfs_context_get_tuning(const mfs_context* ctx, mfs_tuning* out);
@@ -224,6 +227,26 @@ int mfs_solve_batch(mfs_context* ctx, int32_t count, mfs_character* const* chars
                     const double* const* handle_R, const double* const* handle_t,
                     const mfs_solve_opts* opts, double* const* x_out,
                     mfs_solve_stats* stats);
+
+/* ---- autotuning --------------------------------------------------------- */
+
+#define MFS_AUTOTUNE_FORCE 1  /* time the candidates even when a cached choice exists */
+
+/* Choose the PCG launch schedule (SpMV lanes per row, PCG iterations per
+ * graph, first convergence check, shortest run between checks) for a batch
+ * like this one and apply it to the context.  Each candidate solves the
+ * given frames (as mfs_solve_batch with `opts`, but from the rest shape and
+ * for exactly `newton_iterations` iterations, into scratch device memory)
+ * twice, timing the second; the fastest wins.  Choices are kept per
+ * (GPU architecture, size class = bit length of the total vertex count):
+ * in the context, and in the text file `cache_path` when it is not NULL
+ * (read first, rewritten after tuning).  A cached choice is applied without
+ * timing unless flags has MFS_AUTOTUNE_FORCE.  The characters end up holding
+ * the solution of the last timed run.  best and best_ms may be NULL. */
+int mfs_autotune(mfs_context* ctx, int32_t count, mfs_character* const* chars,
+                 const double* const* handle_R, const double* const* handle_t,
+                 const mfs_solve_opts* opts, int32_t newton_iterations, const char* cache_path,
+                 int32_t flags, mfs_tuning* best, double* best_ms);
 
 /* ---- serving ------------------------------------------------------------ */
 

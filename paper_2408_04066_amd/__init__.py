@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 __all__ = ["MfsError", "MfsUnavailable", "Context", "Character", "SolveOpts", "SolveStats",
-           "solve_batch", "Server", "lib", "EXPORTED", "ARAP", "COROT", "NEOHOOKEAN", "FP64", "FP32_REFINED",
+           "solve_batch", "autotune", "Server", "lib", "EXPORTED", "ARAP", "COROT", "NEOHOOKEAN", "FP64", "FP32_REFINED",
            "MEM_HOST", "MEM_DEVICE", "WARM_REST", "WARM_PREVIOUS"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmfs.so")
@@ -32,7 +32,7 @@ EXPORTED = ("mfs_default_opts", "mfs_status_string", "mfs_last_error", "mfs_cont
             "mfs_profile_enable", "mfs_profile_read", "mfs_context_get_tuning",
             "mfs_context_set_tuning", "mfs_character_release_workspace", "mfs_default_server_opts",
             "mfs_server_create", "mfs_server_destroy", "mfs_server_submit", "mfs_server_poll",
-            "mfs_server_wait", "mfs_server_get_info")
+            "mfs_server_wait", "mfs_server_get_info", "mfs_autotune")
 
 KERNEL_FAMILIES = ("warm_start", "element", "assemble", "spmv", "cg_update", "linesearch", "update",
                    "other")
@@ -83,7 +83,7 @@ class CharacterInfo(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("pcg_lanes_per_row", c_i32), ("use_graphs", c_i32), ("graph_iterations", c_i32),
-                ("first_check", c_i32), ("min_run", c_i32), ("max_run", c_i32)]
+                ("first_check", c_i32), ("min_run", c_i32), ("max_run", c_i32), ("pcg_pipelined", c_i32)]
 
 
 class Profile(ctypes.Structure):
@@ -148,6 +148,8 @@ def lib():
                                            P(c_i32)]),
         "mfs_server_wait": (ctypes.c_int, [c_vp, ctypes.c_uint64, c_vp, P(SolveStats), P(RequestTimes)]),
         "mfs_server_get_info": (ctypes.c_int, [c_vp, P(ServerInfo)]),
+        "mfs_autotune": (ctypes.c_int, [c_vp, c_i32, c_vp, c_vp, c_vp, P(SolveOpts), c_i32, ctypes.c_char_p,
+                                        c_i32, P(Tuning), P(c_dbl)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -259,6 +261,21 @@ class Context:
         _check(lib().mfs_polar(self.handle, _ptr(F), c, precision, _ptr(U), _ptr(P), _ptr(s),
                                _ptr(routed), MEM_HOST))
         return U.reshape(c, 3, 3), P, s, routed
+
+
+def autotune(ctx, chars, poses, newton_iterations=4, cache_path=None, force=False, **opts):
+    """Pick and apply the PCG launch schedule for a batch like ``chars``
+    (``mfs_autotune``).  Returns (tuning dict, best milliseconds)."""
+    k = len(chars)
+    Rs, ts = zip(*[ch._pose(R, t) for ch, (R, t) in zip(chars, poses)])
+    arr = lambda vals: (c_vp * k)(*vals)
+    o = default_opts(**opts)
+    best, ms = Tuning(), c_dbl()
+    path = cache_path.encode() if cache_path else None
+    _check(lib().mfs_autotune(ctx.handle, k, arr([c.handle.value for c in chars]), arr([_ptr(R) for R in Rs]),
+                              arr([_ptr(t) for t in ts]), ctypes.byref(o), newton_iterations, path,
+                              1 if force else 0, ctypes.byref(best), ctypes.byref(ms)))
+    return {name: getattr(best, name) for name, _ in best._fields_}, ms.value
 
 
 class Character:

@@ -165,6 +165,7 @@ extern "C" int mfs_context_get_tuning(const mfs_context* ctx, mfs_tuning* out) {
   out->first_check = ctx->cg_first_run;
   out->min_run = ctx->cg_min_run;
   out->max_run = ctx->cg_max_run;
+  out->pcg_pipelined = ctx->pipelined ? 1 : 0;
   return MFS_OK;
 }
 
@@ -177,6 +178,7 @@ extern "C" int mfs_context_set_tuning(mfs_context* ctx, const mfs_tuning* t) {
     return set_error(MFS_E_INVALID, "graph_iterations must be in [1, 64]");
   if (t->first_check < 1 || t->min_run < 1 || t->max_run < t->min_run)
     return set_error(MFS_E_INVALID, "invalid PCG run bounds");
+  if (t->pcg_pipelined != 0 && t->pcg_pipelined != 1) return set_error(MFS_E_INVALID, "pcg_pipelined must be 0 or 1");
   MFS_HIP(hipSetDevice(ctx->device));
   MFS_HIP(hipStreamSynchronize(ctx->stream));
   for (const CgGraph& g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
@@ -187,5 +189,6 @@ extern "C" int mfs_context_set_tuning(mfs_context* ctx, const mfs_tuning* t) {
   ctx->cg_first_run = t->first_check;
   ctx->cg_min_run = t->min_run;
   ctx->cg_max_run = t->max_run;
+  ctx->pipelined = t->pcg_pipelined != 0;
   return MFS_OK;
 }

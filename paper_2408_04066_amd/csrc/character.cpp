@@ -184,7 +184,7 @@ int workspace_pieces(const mfs_character* ch, size_t* sz) {
   sz[k++] = n3;                                               // dx
   sz[k++] = 9 * sizeof(double) * (size_t)ch->nnzb;            // vals
   sz[k++] = 6 * sizeof(double) * (size_t)ch->n;               // minv
-  for (int v = 0; v < 6; ++v) sz[k++] = n3;                   // r z p0 p1 q xc
+  for (int v = 0; v < 10; ++v) sz[k++] = n3;                  // r z p0 p1 q xc v0 v1 v2 v3
   sz[k++] = sizeof(double) * P_COUNT * (size_t)ch->ptile;     // part
   sz[k++] = sizeof(double) * P_COUNT;                         // red
   return k;
@@ -194,7 +194,7 @@ size_t align_up(size_t v) { return (v + kWsAlign - 1) / kWsAlign * kWsAlign; }
 }  // namespace
 
 size_t workspace_layout(const mfs_character* ch) {
-  size_t sz[16];
+  size_t sz[24];
   const int k = workspace_pieces(ch, sz);
   size_t total = 0;
   for (int i = 0; i < k; ++i) total += align_up(sz[i]);
@@ -202,9 +202,9 @@ size_t workspace_layout(const mfs_character* ch) {
 }
 
 void bind_workspace(const mfs_character* ch, char* base, SysDesc* d) {
-  size_t sz[16];
+  size_t sz[24];
   const int k = workspace_pieces(ch, sz);
-  void* ptr[16];
+  void* ptr[24];
   size_t off = 0;
   for (int i = 0; i < k; ++i) {
     ptr[i] = base ? base + off : nullptr;
@@ -222,8 +222,12 @@ void bind_workspace(const mfs_character* ch, char* base, SysDesc* d) {
   d->p1 = ptr[9];
   d->q = ptr[10];
   d->xc = ptr[11];
-  d->part = static_cast<double*>(ptr[12]);
-  d->red = static_cast<double*>(ptr[13]);
+  d->v0 = ptr[12];
+  d->v1 = ptr[13];
+  d->v2 = ptr[14];
+  d->v3 = ptr[15];
+  d->part = static_cast<double*>(ptr[16]);
+  d->red = static_cast<double*>(ptr[17]);
 }
 
 int ensure_workspace(mfs_character* ch) {

@@ -35,7 +35,14 @@ enum PartSlot : int {
   P_PIN0 = 8 + 2 * kNumTrials,  // pin energy per trial
   P_CLAMP = 8 + 3 * kNumTrials, // clamped neo-Hookean elements
   P_ROUTED = 9 + 3 * kNumTrials, // warm-start polar decompositions re-run in FP64
-  P_COUNT = 10 + 3 * kNumTrials
+  // pipelined PCG: gamma = r . u, delta = w . u and r . r of the next
+  // iteration, by iteration parity (P_RR holds parity 0)
+  P_G0 = 10 + 3 * kNumTrials,
+  P_G1 = 11 + 3 * kNumTrials,
+  P_D0 = 12 + 3 * kNumTrials,
+  P_D1 = 13 + 3 * kNumTrials,
+  P_RR1 = 14 + 3 * kNumTrials,
+  P_COUNT = 15 + 3 * kNumTrials
 };
 
 // Per-system PCG scalars.  Every PCG kernel ends with an arrival ticket:
@@ -64,6 +71,12 @@ struct CgState {
   uint32_t arrive_init, arrive_spmv, arrive_update;  // arrival tickets (0 between kernels)
   int32_t it_a;    // all-read mode: iteration index read by the SpMV kernel
   int32_t it_b;    // all-read mode: iteration index read by the update kernel
+  // pipelined PCG (one kernel per iteration)
+  double g, d;          // gamma_i, delta_i folded for the next iteration (ticket mode)
+  double a_prev[2];     // alpha of the iterations of each parity
+  double g_prev[2];     // gamma of the iterations of each parity
+  uint32_t arrive_pipe; // arrival ticket of the pipelined kernels
+  int32_t pad1;
 };
 
 // Per-system control block, written by the host driver each iteration.
@@ -145,6 +158,10 @@ struct SysDesc {
   void* p1;
   void* q;
   void* xc;      // PCG iterate
+  void* v0;      // pipelined PCG: w = K u
+  void* v1;      // pipelined PCG: z = K q (recurrence)
+  void* v2;      // pipelined PCG: q = M^-1 s (recurrence)
+  void* v3;      // pipelined PCG: s = K p (recurrence)
   // reductions
   double* part;  // P_COUNT planes of ptile
   double* red;   // P_COUNT per-system results of the finalize kernel

@@ -85,10 +85,10 @@ int build_tile_list(mfs_context* ctx, const std::vector<mfs_character*>& by_slot
 // kernels take no per-iteration arguments (the iteration index and the
 // per-step tolerance live in device memory).
 static int cg_graph(mfs_context* ctx, const SysDesc* sd, const TileSet& ts, int fp32, int iters,
-                    const SysDesc* one, hipGraphExec_t* out) {
+                    const SysDesc* one, bool pipe, hipGraphExec_t* out) {
   for (CgGraph& g : ctx->graphs) {
     if (g.sd == sd && g.tiles == ts.dv && g.ntv == ts.nv && g.fp32 == fp32 && g.lpr == ctx->lpr &&
-        g.iters == iters && g.has_one == (one != nullptr) &&
+        g.iters == iters && g.pipelined == pipe && g.has_one == (one != nullptr) &&
         (!one || std::memcmp(&g.one, one, sizeof(SysDesc)) == 0)) {
       *out = g.exec;
       return MFS_OK;
@@ -97,8 +97,12 @@ static int cg_graph(mfs_context* ctx, const SysDesc* sd, const TileSet& ts, int 
   hipGraph_t graph = nullptr;
   MFS_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
   for (int j = 0; j < iters; ++j) {
-    launch_cg_spmv(ctx->stream, sd, ts.dv, ts.nv, fp32, ctx->lpr, one);
-    launch_cg_update(ctx->stream, sd, ts.dv, ts.nv, fp32, one);
+    if (pipe) {
+      launch_pcg_iter(ctx->stream, sd, ts.dv, ts.nv, fp32, ctx->lpr, one, j & 1);
+    } else {
+      launch_cg_spmv(ctx->stream, sd, ts.dv, ts.nv, fp32, ctx->lpr, one);
+      launch_cg_update(ctx->stream, sd, ts.dv, ts.nv, fp32, one);
+    }
   }
   MFS_HIP(hipStreamEndCapture(ctx->stream, &graph));
   hipGraphExec_t exec = nullptr;
@@ -109,37 +113,46 @@ static int cg_graph(mfs_context* ctx, const SysDesc* sd, const TileSet& ts, int 
     (void)hipGraphExecDestroy(ctx->graphs.front().exec);
     ctx->graphs.erase(ctx->graphs.begin());
   }
-  CgGraph g{sd, ts.dv, ts.nv, fp32, ctx->lpr, iters, one != nullptr, SysDesc{}, exec};
+  CgGraph g{sd, ts.dv, ts.nv, fp32, ctx->lpr, iters, pipe, one != nullptr, SysDesc{}, exec};
   if (one) g.one = *one;
   ctx->graphs.push_back(g);
   *out = exec;
   return MFS_OK;
 }
 
-// Enqueue `run` PCG iterations: replayed graphs when enabled and the
-// profiler is off, direct launches (each family timed by the profiler)
-// otherwise.
+// Enqueue `run` PCG iterations starting at iteration `start`: replayed
+// graphs when enabled and the profiler is off, direct launches (each family
+// timed by the profiler) otherwise.  A pipelined graph holds an even number
+// of iterations and starts at an even one (the kernels take the parity as
+// an argument).
 static int enqueue_cg(mfs_context* ctx, const SysDesc* sd, const TileSet& ts, int fp32, int run,
-                      const SysDesc* one, double spmv_bytes) {
+                      const SysDesc* one, double spmv_bytes, bool pipe, int start) {
   const int G = ctx->graph_iters;
   int done = 0;
-  if (ctx->use_graphs && ctx->prof_stride == 0 && G > 0) {
-    hipGraphExec_t exec;
-    MFS_TRY(cg_graph(ctx, sd, ts, fp32, G, one, &exec));
-    for (; done + G <= run; done += G) {
-      MFS_HIP(hipGraphLaunch(exec, ctx->stream));
-      ctx->prof_launches[MFS_K_SPMV] += G;
-      ctx->prof_launches[MFS_K_CG_UPDATE] += G;
+  auto direct = [&](int it) {
+    if (pipe) {
+      ProfScope ps(ctx, MFS_K_SPMV, spmv_bytes);
+      launch_pcg_iter(ctx->stream, sd, ts.dv, ts.nv, fp32, ctx->lpr, one, it & 1);
+      return;
     }
-  }
-  for (; done < run; ++done) {
     {
       ProfScope ps(ctx, MFS_K_SPMV, spmv_bytes);
       launch_cg_spmv(ctx->stream, sd, ts.dv, ts.nv, fp32, ctx->lpr, one);
     }
     ProfScope ps(ctx, MFS_K_CG_UPDATE);
     launch_cg_update(ctx->stream, sd, ts.dv, ts.nv, fp32, one);
+  };
+  if (ctx->use_graphs && ctx->prof_stride == 0 && G > 0 && (!pipe || G % 2 == 0)) {
+    if (pipe && (start & 1) && run > 0) direct(start + done++);  // graphs start at even iterations
+    hipGraphExec_t exec;
+    MFS_TRY(cg_graph(ctx, sd, ts, fp32, G, one, pipe, &exec));
+    for (; done + G <= run; done += G) {
+      MFS_HIP(hipGraphLaunch(exec, ctx->stream));
+      ctx->prof_launches[MFS_K_SPMV] += G;
+      if (!pipe) ctx->prof_launches[MFS_K_CG_UPDATE] += G;
+    }
   }
+  for (; done < run; ++done) direct(start + done);
   return MFS_OK;
 }
 
@@ -339,6 +352,7 @@ int Engine::attach(int i, mfs_character* ch, const double* R, const double* t) {
     for (int h = 0; h < nh; ++h) S.R0[9 * h] = S.R0[9 * h + 4] = S.R0[9 * h + 8] = 1.0;
   }
   MFS_TRY(set_pose(i, 1.0));
+  tiles_valid_ = false;  // the slot's occupant changed
   SysDesc& d = hd_[i];
   d = ch->desc;
   d.red = ctx_->red.as<double>() + P_COUNT * i;
@@ -372,12 +386,20 @@ int Engine::upload_desc() {
   return MFS_OK;
 }
 
+// The tile list is cached for the last (slot, character) set; a slot that
+// changed occupant must never reuse its previous occupant's tile ranges.
 int Engine::tiles_for(const std::vector<int>& ids) {
-  if (tiles_valid_ && ids == tile_ids_) return MFS_OK;
+  std::vector<const mfs_character*> chars(ids.size());
+  for (size_t k = 0; k < ids.size(); ++k) chars[k] = slot_[ids[k]].ch;
+  if (tiles_valid_ && ids == tile_ids_ && chars == tile_chars_) return MFS_OK;
   std::vector<mfs_character*> by_slot(slot_.size(), nullptr);
   for (size_t i = 0; i < slot_.size(); ++i) by_slot[i] = slot_[i].ch;
+  for (int i : ids)
+    if (i < 0 || i >= (int)slot_.size() || !slot_[i].used || !slot_[i].ch)
+      return set_error(MFS_E_INVALID, "tile list asked for empty slot %d", i);
   MFS_TRY(build_tile_list(ctx_, by_slot, ids, &ts_));
   tile_ids_ = ids;
+  tile_chars_ = chars;
   tiles_valid_ = true;
   return MFS_OK;
 }
@@ -394,26 +416,39 @@ int Engine::run_cg(const std::vector<int>& act) {
     slot_[i].rho_prev = -1.0;
     slot_[i].it_prev = 0;
   }
-  const SysDesc* one = act.size() == 1 ? &hd_[act[0]] : nullptr;
-  // algorithmic bytes of one SpMV launch over the slots still in PCG
-  // (blocks + column indices + row pointers + 2 gathered inputs and 2
-  // outputs per row), for the profiler's roofline figures
+  // launch set: the slots whose PCG still iterates.  It shrinks at the
+  // host's convergence checks, so the tiles of converged systems leave the
+  // grid, and a single remaining system runs with its descriptor as the
+  // kernel argument.  A slot's arithmetic does not depend on the set.
+  std::vector<int> live = act;
+  const SysDesc* one = live.size() == 1 ? &hd_[live[0]] : nullptr;
+  const bool pipe = ctx->pipelined && fp32_;
+  // algorithmic bytes of one SpMV launch over the slots still in PCG, for
+  // the profiler's roofline figures: blocks + column indices + row pointers,
+  // and per row 2 gathered inputs and 2 outputs (standard form), or the
+  // gathered m, 9 vectors read and 9 written and the 3x3 preconditioner
+  // block (pipelined form, which fuses the vector updates)
   const double word = fp32_ ? 4.0 : 8.0;
+  const double per_row = pipe ? (3.0 + 27.0 + 27.0 + 6.0) * word : 12.0 * word;
   auto spmv_bytes = [&]() {
     double by = 0.0;
     for (int i : act)
       if (cit == 0 || !hg[i].done) {
         const mfs_character* c = slot_[i].ch;
-        by += c->nnzb * (9.0 * word + 4.0) + (c->n + 1) * 4.0 + c->n * 12.0 * word;
+        by += c->nnzb * (9.0 * word + 4.0) + (c->n + 1) * 4.0 + c->n * per_row;
       }
     return by;
   };
+  if (pipe) {
+    ProfScope ps(ctx, MFS_K_OTHER);
+    launch_pcg_start(ctx->stream, dsd, ts_.dv, ts_.nv, fp32_, ctx->lpr, one);
+  }
   // PCG in runs of iterations; after each run the host reads the
   // convergence flags and residuals and sizes the next run from the
   // observed residual decay of the slowest slot.
   while (cit < o_.cg_max) {
     const int run = std::min(chunk, o_.cg_max - cit);
-    MFS_TRY(enqueue_cg(ctx, dsd, ts_, fp32_, run, one, spmv_bytes()));
+    MFS_TRY(enqueue_cg(ctx, dsd, ts_, fp32_, run, one, spmv_bytes(), pipe, cit));
     cit += run;
     MFS_HIP(hipGetLastError());
     MFS_TRY(read_cg(ctx, n));
@@ -438,7 +473,16 @@ int Engine::run_cg(const std::vector<int>& act) {
     }
     if (all) break;
     chunk = std::min(std::max(need, ctx->cg_min_run), ctx->cg_max_run);
+    std::vector<int> still;
+    for (int i : live)
+      if (!hg[i].done) still.push_back(i);
+    if (still.size() < live.size()) {
+      live.swap(still);
+      MFS_TRY(tiles_for(live));  // the stream is idle after read_cg
+      one = live.size() == 1 ? &hd_[live[0]] : nullptr;
+    }
   }
+  if (live.size() != act.size()) MFS_TRY(tiles_for(act));
   for (int i : act) {
     if (hg[i].done) {
       slot_[i].cg += hg[i].iters;

@@ -81,7 +81,11 @@ class Engine {
   // or device; synchronises the stream.
   int output(int slot, double* x_out, int mem);
   void stats(int slot, mfs_solve_stats* s) const;
-  void retire(int slot) { slot_[slot] = SlotState(); desc_dirty_ = true; }
+  void retire(int slot) {
+    slot_[slot] = SlotState();
+    desc_dirty_ = true;
+    tiles_valid_ = false;
+  }
   const SlotState& state(int slot) const { return slot_[slot]; }
 
  private:
@@ -100,6 +104,7 @@ class Engine {
   bool desc_dirty_ = true;
   TileSet ts_;
   std::vector<int> tile_ids_;
+  std::vector<const mfs_character*> tile_chars_;
   bool tiles_valid_ = false;
 };
 

@@ -76,6 +76,7 @@ struct CgGraph {
   const Tile* tiles;
   int ntv;
   int fp32, lpr, iters;
+  bool pipelined;    // pipelined PCG kernels
   bool has_one;      // captured with a single system's descriptor as kernel argument
   SysDesc one;       // that descriptor (compared bytewise on lookup)
   hipGraphExec_t exec;
@@ -91,6 +92,7 @@ struct mfs_context {
   int cg_min_run = 8, cg_max_run = 512;
   bool use_graphs = true;            // replay captured runs of PCG iterations
   int graph_iters = 8;               // PCG iterations per captured graph
+  bool pipelined = false;            // FP32 solves: pipelined PCG, one kernel per iteration
   std::vector<mfs::CgGraph> graphs;
   // batch scratch
   mfs::DevBuf desc, ctrl, red, cg, tiles, sys_ids, tmp;
@@ -103,6 +105,13 @@ struct mfs_context {
   double prof_bytes[MFS_K_FAMILIES] = {};
   std::vector<hipEvent_t> ev_pool;
   std::vector<mfs::ProfPending> pending;
+  // autotuned PCG schedules of this context, per size class
+  struct TuneEntry {
+    int size_class;
+    mfs_tuning tuning;
+    double ms;
+  };
+  std::vector<TuneEntry> tune_cache;
   ~mfs_context();
 };
 

@@ -1,7 +1,7 @@
 // Preconditioned conjugate gradients on the condensed 3x3-block system
 // (the global sparse SPD solve of each Newton step).
 //
-// Two kernels per iteration.  k_cg_spmv forms the search direction
+// Standard form: two kernels per iteration.  k_cg_spmv forms the search direction
 // p_it = z + beta p_{it-1} on the fly (double-buffered p, so the gathers of
 // neighbouring rows read the previous buffer) and q = K p_it, with LPR lanes
 // per block row reading the 9 value planes of consecutive slots (coalesced).
@@ -285,6 +285,249 @@ __global__ __launch_bounds__(64) void k_cg_update(const SysDesc* __restrict__ sd
   }
 }
 
+// ---- pipelined PCG (Ghysels and Vanroose, "Hiding global synchronization
+// latency in the preconditioned conjugate gradient algorithm", 2014) ----
+//
+// One kernel per iteration.  Besides x and r it carries u = M^-1 r (in z),
+// w = K u (v0) and the recurrences p (p0), s = K p (v3), q = M^-1 s (v2) and
+// z = K q (v1); m = M^-1 w is double-buffered by iteration parity (buffer 0
+// in p1, buffer 1 in q) because iteration i gathers neighbouring rows of m_i
+// while writing m_{i+1}.  gamma = r.u, delta = w.u and r.r of the next
+// iteration are per-tile partials double-buffered by parity.  The SpMV of
+// iteration i gathers m_i, which is final when the launch starts, so it does
+// not wait for the fold that gives alpha_i and beta_i.  In exact arithmetic
+// the iterates equal those of the two-kernel PCG.  The parity is a launch
+// argument: a captured run of an even number of iterations replays from any
+// even iteration.
+
+// acc = (K v)_row over this lane's share of the row's blocks, then summed
+// over the LPR lanes of the row (every lane of the row gets the sum).
+template <typename T, int LPR>
+__device__ __forceinline__ void row_product(const SysDesc& S, const T* __restrict__ v, int row, bool valid, int lane,
+                                            T acc[3]) {
+  acc[0] = acc[1] = acc[2] = (T)0;
+  if (valid) {
+    const T* vals = (const T*)S.vals;
+    const size_t nz = S.nnzb;
+    const int e = S.rowptr[row + 1];
+    for (int sl = S.rowptr[row] + lane; sl < e; sl += LPR) {
+      const int c = S.colidx[sl];
+      const T v0 = v[3 * c], v1 = v[3 * c + 1], v2 = v[3 * c + 2];
+      acc[0] += vals[sl] * v0 + vals[nz + sl] * v1 + vals[2 * nz + sl] * v2;
+      acc[1] += vals[3 * nz + sl] * v0 + vals[4 * nz + sl] * v1 + vals[5 * nz + sl] * v2;
+      acc[2] += vals[6 * nz + sl] * v0 + vals[7 * nz + sl] * v1 + vals[8 * nz + sl] * v2;
+    }
+  }
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) {
+    acc[0] += __shfl_xor(acc[0], o, 64);
+    acc[1] += __shfl_xor(acc[1], o, 64);
+    acc[2] += __shfl_xor(acc[2], o, 64);
+  }
+}
+
+// After k_cg_init (r = b, x = 0, u = M^-1 r, partials r.r and b.b):
+// w = K u, m_0 = M^-1 w, recurrences cleared, partials gamma_0 and delta_0.
+template <typename T, int LPR, bool ONE>
+__global__ __launch_bounds__(64 * LPR) void k_pcg_start(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
+                                                        int ntiles, const SysDesc one) {
+  __shared__ double red[2][LPR];
+  __shared__ int conv;
+  __shared__ int last;
+  const Tile t = vertex_tile<ONE>(tiles, ntiles, one);
+  const SysDesc& S = ONE ? one : sd[t.sys];
+  CgState* st = S.cg;
+  if (S.ticket) {
+    if (st->done) return;
+  } else {
+    if (threadIdx.x < 64) {
+      const double rr = sys_sum(S.part + P_RR * S.ptile, S.ntv);
+      const double bb = sys_sum(S.part + P_BB * S.ptile, S.ntv);
+      const bool c = rr <= pcg_tol2(*S.ctrl, bb) * bb;
+      if (threadIdx.x == 0) {
+        conv = c ? 1 : 0;
+        if (t.local == 0) {
+          st->rr = rr;
+          st->bb = bb;
+          if (c) {
+            st->done = 1;
+            st->iters = 0;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (conv) return;
+  }
+  if (t.local == 0 && threadIdx.x == 0) {
+    st->a_prev[1] = 1.0;       // alpha_{-1}: any non-zero value
+    st->g_prev[1] = INFINITY;  // gamma_{-1}: beta_0 = 0
+  }
+  const int lane = threadIdx.x % LPR;
+  const int row = t.begin + threadIdx.x / LPR;
+  const bool valid = row < t.end;
+  const T* u = (const T*)S.z;
+  T w[3];
+  row_product<T, LPR>(S, u, row, valid, lane, w);
+  double g = 0.0, dl = 0.0;
+  if (valid && lane == 0) {
+    T m[3];
+    precondition((const T*)S.minv + 6 * row, w, m);
+    T* wv = (T*)S.v0;
+    T* mv = (T*)S.p1;
+    T* zv = (T*)S.v1;
+    T* qv = (T*)S.v2;
+    T* sv = (T*)S.v3;
+    T* pv = (T*)S.p0;
+    const T* r = (const T*)S.r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int k = 3 * row + i;
+      wv[k] = w[i];
+      mv[k] = m[i];
+      zv[k] = qv[k] = sv[k] = pv[k] = (T)0;
+      const double uk = (double)u[k];
+      g += (double)r[k] * uk;
+      dl += (double)w[i] * uk;
+    }
+  }
+  const double tg = block_sum<LPR>(g, red[0]);
+  const double td = block_sum<LPR>(dl, red[1]);
+  if (threadIdx.x == 0) {
+    S.part[P_G0 * S.ptile + t.local] = tg;
+    S.part[P_D0 * S.ptile + t.local] = td;
+  }
+  if (S.ticket && last_arrival(&st->arrive_pipe, S.ntv, &last) && threadIdx.x < 64) {
+    const double sg = coherent_sum(S.part + P_G0 * S.ptile, S.ntv);
+    const double sdl = coherent_sum(S.part + P_D0 * S.ptile, S.ntv);
+    if (threadIdx.x == 0) {
+      st->g = sg;
+      st->d = sdl;
+      st->arrive_pipe = 0;
+    }
+  }
+}
+
+// Iteration i (parity = i & 1) of the pipelined PCG.
+template <typename T, int LPR, bool ONE>
+__global__ __launch_bounds__(64 * LPR) void k_pcg_iter(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
+                                                       int ntiles, const SysDesc one, int parity) {
+  __shared__ double red[3][LPR];
+  __shared__ double bcast[3];
+  __shared__ int last;
+  const Tile t = vertex_tile<ONE>(tiles, ntiles, one);
+  const SysDesc& S = ONE ? one : sd[t.sys];
+  CgState* st = S.cg;
+  if (S.ticket && st->done) return;
+  const int par = parity & 1;
+  const int lane = threadIdx.x % LPR;
+  const int row = t.begin + threadIdx.x / LPR;
+  const bool valid = row < t.end;
+  const T* mi = (const T*)(par ? S.q : S.p1);
+  T* mn = (T*)(par ? S.p1 : S.q);
+  // n_i = K m_i: needs nothing from the fold below
+  T nv[3];
+  row_product<T, LPR>(S, mi, row, valid, lane, nv);
+  double gam, del;
+  if (S.ticket) {
+    gam = st->g;
+    del = st->d;
+  } else {
+    if (threadIdx.x < 64) {
+      const double rr = sys_sum(S.part + (par ? P_RR1 : P_RR) * S.ptile, S.ntv);
+      const double bb = st->bb;
+      const bool c = rr <= pcg_tol2(*S.ctrl, bb) * bb;
+      const double g = sys_sum(S.part + (P_G0 + par) * S.ptile, S.ntv);
+      const double d = sys_sum(S.part + (P_D0 + par) * S.ptile, S.ntv);
+      if (threadIdx.x == 0) {
+        bcast[0] = c ? 1.0 : 0.0;
+        bcast[1] = g;
+        bcast[2] = d;
+        if (t.local == 0) {
+          st->rr = rr;
+          if (c) st->done = 1;
+        }
+      }
+    }
+    __syncthreads();
+    if (bcast[0] != 0.0) return;
+    gam = bcast[1];
+    del = bcast[2];
+  }
+  const double beta = gam / st->g_prev[par ^ 1];
+  const double den = del - beta * gam / st->a_prev[par ^ 1];
+  if (!(den > 0.0) || !(gam > 0.0)) {  // breakdown (lost positive definiteness in rounding): stop here
+    if (t.local == 0 && threadIdx.x == 0) st->done = 1;
+    return;
+  }
+  const double alpha = gam / den;
+  if (t.local == 0 && threadIdx.x == 0) {
+    st->a_prev[par] = alpha;
+    st->g_prev[par] = gam;
+    if (!S.ticket) st->iters += 1;
+  }
+  const T ta = (T)alpha, tb = (T)beta;
+  double g = 0.0, dl = 0.0, rr = 0.0;
+  if (valid && lane == 0) {
+    T* zv = (T*)S.v1;
+    T* qv = (T*)S.v2;
+    T* sv = (T*)S.v3;
+    T* pv = (T*)S.p0;
+    T* xv = (T*)S.xc;
+    T* rv = (T*)S.r;
+    T* uv = (T*)S.z;
+    T* wv = (T*)S.v0;
+    T w[3], mnew[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int k = 3 * row + i;
+      const T z = nv[i] + tb * zv[k];
+      const T q = mi[k] + tb * qv[k];
+      const T sk = wv[k] + tb * sv[k];
+      const T pk = uv[k] + tb * pv[k];
+      zv[k] = z;
+      qv[k] = q;
+      sv[k] = sk;
+      pv[k] = pk;
+      xv[k] += ta * pk;
+      const T r = rv[k] - ta * sk;
+      const T u = uv[k] - ta * q;
+      w[i] = wv[k] - ta * z;
+      rv[k] = r;
+      uv[k] = u;
+      wv[k] = w[i];
+      g += (double)r * (double)u;
+      dl += (double)w[i] * (double)u;
+      rr += (double)r * (double)r;
+    }
+    precondition((const T*)S.minv + 6 * row, w, mnew);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) mn[3 * row + i] = mnew[i];
+  }
+  const int nx = par ^ 1;
+  const double tg = block_sum<LPR>(g, red[0]);
+  const double td = block_sum<LPR>(dl, red[1]);
+  const double tr = block_sum<LPR>(rr, red[2]);
+  if (threadIdx.x == 0) {
+    S.part[(P_G0 + nx) * S.ptile + t.local] = tg;
+    S.part[(P_D0 + nx) * S.ptile + t.local] = td;
+    S.part[(nx ? P_RR1 : P_RR) * S.ptile + t.local] = tr;
+  }
+  if (S.ticket && last_arrival(&st->arrive_pipe, S.ntv, &last) && threadIdx.x < 64) {
+    const double sg = coherent_sum(S.part + (P_G0 + nx) * S.ptile, S.ntv);
+    const double sdl = coherent_sum(S.part + (P_D0 + nx) * S.ptile, S.ntv);
+    const double srr = coherent_sum(S.part + (nx ? P_RR1 : P_RR) * S.ptile, S.ntv);
+    if (threadIdx.x == 0) {
+      st->g = sg;
+      st->d = sdl;
+      st->rr = srr;
+      st->iters += 1;
+      if (srr <= pcg_tol2(*S.ctrl, st->bb) * st->bb) st->done = 1;
+      st->arrive_pipe = 0;
+    }
+  }
+}
+
 // dx (FP64) <- PCG iterate.
 template <typename T>
 __global__ __launch_bounds__(64) void k_cg_finish(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
@@ -364,6 +607,65 @@ void launch_cg_update(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv
   } else {
     if (one) MFS_LAUNCH((k_cg_update<double, true>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv, o);
     else MFS_LAUNCH((k_cg_update<double, false>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv, o);
+  }
+}
+
+template <typename T, bool ONE>
+static void pcg_start_t(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int lpr, const SysDesc& one) {
+  switch (lpr) {
+    case 2:
+      MFS_LAUNCH((k_pcg_start<T, 2, ONE>), dim3(ntv), dim3(128), 0, st, sd, tv, ntv, one);
+      break;
+    case 8:
+      MFS_LAUNCH((k_pcg_start<T, 8, ONE>), dim3(ntv), dim3(512), 0, st, sd, tv, ntv, one);
+      break;
+    default:
+      MFS_LAUNCH((k_pcg_start<T, 4, ONE>), dim3(ntv), dim3(256), 0, st, sd, tv, ntv, one);
+      break;
+  }
+}
+
+template <typename T, bool ONE>
+static void pcg_iter_t(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int lpr, const SysDesc& one,
+                       int parity) {
+  switch (lpr) {
+    case 2:
+      MFS_LAUNCH((k_pcg_iter<T, 2, ONE>), dim3(ntv), dim3(128), 0, st, sd, tv, ntv, one, parity);
+      break;
+    case 8:
+      MFS_LAUNCH((k_pcg_iter<T, 8, ONE>), dim3(ntv), dim3(512), 0, st, sd, tv, ntv, one, parity);
+      break;
+    default:
+      MFS_LAUNCH((k_pcg_iter<T, 4, ONE>), dim3(ntv), dim3(256), 0, st, sd, tv, ntv, one, parity);
+      break;
+  }
+}
+
+void launch_pcg_start(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, int lpr,
+                      const SysDesc* one) {
+  if (!ntv) return;
+  static const SysDesc none{};
+  const SysDesc& o = one ? *one : none;
+  if (fp32) {
+    if (one) pcg_start_t<float, true>(st, sd, tv, ntv, lpr, o);
+    else pcg_start_t<float, false>(st, sd, tv, ntv, lpr, o);
+  } else {
+    if (one) pcg_start_t<double, true>(st, sd, tv, ntv, lpr, o);
+    else pcg_start_t<double, false>(st, sd, tv, ntv, lpr, o);
+  }
+}
+
+void launch_pcg_iter(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, int lpr,
+                     const SysDesc* one, int parity) {
+  if (!ntv) return;
+  static const SysDesc none{};
+  const SysDesc& o = one ? *one : none;
+  if (fp32) {
+    if (one) pcg_iter_t<float, true>(st, sd, tv, ntv, lpr, o, parity);
+    else pcg_iter_t<float, false>(st, sd, tv, ntv, lpr, o, parity);
+  } else {
+    if (one) pcg_iter_t<double, true>(st, sd, tv, ntv, lpr, o, parity);
+    else pcg_iter_t<double, false>(st, sd, tv, ntv, lpr, o, parity);
   }
 }
 

@@ -392,7 +392,7 @@ __global__ __launch_bounds__(64) void k_update_x(const SysDesc* __restrict__ sd,
 // Fold each system's partial planes over its tiles (fixed order).
 __global__ __launch_bounds__(64) void k_finalize(const SysDesc* __restrict__ sd, const int32_t* __restrict__ sys_ids) {
   const SysDesc& S = sd[sys_ids[blockIdx.x]];
-  for (int p = 0; p < P_COUNT; ++p) {
+  for (int p = 0; p < P_G0; ++p) {  // the pipelined-PCG planes are folded by the PCG kernels
     const bool vert = (p == P_PQ || p == P_RZ0 || p == P_RZ1 || p == P_RR || p == P_BB || p == P_SLOPE ||
                        p == P_DXMAX || (p >= P_PIN0 && p < P_PIN0 + kNumTrials));
     const int cnt = vert ? S.ntv : S.ntt;

@@ -61,6 +61,11 @@ void launch_cg_init(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, 
 void launch_cg_spmv(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, int lpr,
                     const SysDesc* one);
 void launch_cg_update(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, const SysDesc* one);
+// pipelined PCG: start (after launch_cg_init) and one iteration of parity i & 1
+void launch_pcg_start(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, int lpr,
+                      const SysDesc* one);
+void launch_pcg_iter(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, int lpr,
+                     const SysDesc* one, int parity);
 void launch_cg_finish(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32);
 void launch_spmv_plain(hipStream_t st, const int32_t* rowptr, const int32_t* colidx, const double* vals, int nnzb,
                        int n, const double* v, double* y);

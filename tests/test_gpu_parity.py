@@ -269,3 +269,56 @@ def test_full_size_humanoid_matches_golden(ctx):
         _say(f"  stats {st} err/bbox={_err(xa, g['x'], prob):.3e}")
         assert rc == 0 and _err(xa, g["x"], prob) <= 1e-7
     ch.close()
+
+
+def test_pipelined_pcg(ctx):
+    """The pipelined one-kernel PCG (FP32 + refinement): the 4k humanoid and
+    the full-size 50k golden within 1e-7 * bbox of the oracle, graph replay
+    bitwise equal to direct launches (odd and even run starts), and a batch
+    bitwise equal to its members solved alone."""
+    import os
+    mfs = _mfs()
+    base = ctx.tuning()
+    kw = dict(precision=mfs.FP32_REFINED, cg_tol=1e-5, step_tol=1e-9, max_newton=60, cg_adaptive=1)
+    try:
+        prob = _small_humanoid(21, 4000, 15)
+        pose = random_pose(prob, 22)
+        ref = oracle.solve_frame(prob, pose)
+        ch = mfs.Character(ctx, prob)
+        for lpr in (2, 4, 8):
+            ctx.set_tuning(pcg_pipelined=1, pcg_lanes_per_row=lpr, use_graphs=1, graph_iterations=8,
+                           first_check=31, min_run=7)
+            _say(f"pipelined PCG: humanoid m={len(prob['T'])} lanes {lpr}, graphs")
+            xg, st, rc = ch.solve(*pose, **kw)
+            _say(f"  stats {st} err/bbox={_err(xg, ref['x'], prob):.3e}")
+            assert rc == 0 and _err(xg, ref["x"], prob) <= 1e-7
+            ctx.set_tuning(use_graphs=0)
+            xd, _, rc = ch.solve(*pose, **kw)
+            assert rc == 0 and np.array_equal(xg, xd)
+        ch.close()
+        ctx.set_tuning(pcg_pipelined=1, pcg_lanes_per_row=4, use_graphs=1, graph_iterations=8)
+        probs = [humanoid(100 + i, target_tets=t, n_bones=b, models=(NH, COROT))
+                 for i, (t, b) in enumerate([(1500, 8), (3000, 12), (800, 10)])]
+        poses = [random_pose(p, 200 + i) for i, p in enumerate(probs)]
+        chars = [mfs.Character(ctx, p) for p in probs]
+        alone = [c.solve(*q, **kw)[0] for c, q in zip(chars, poses)]
+        _say("pipelined PCG: batch of 3")
+        xs, _, rc = mfs.solve_batch(ctx, chars, poses, **kw)
+        assert rc == 0
+        for a, b in zip(alone, xs):
+            assert np.array_equal(a, b)
+        for c in chars:
+            c.close()
+        here = os.path.dirname(os.path.abspath(__file__))
+        g = np.load(os.path.join(here, "golden", "humanoid50k_pose2002.npz"))
+        prob = humanoid(2001, target_tets=50000, n_bones=20)
+        pose = random_pose(prob, 2002)
+        ch = mfs.Character(ctx, prob)
+        _say("pipelined PCG: humanoid 50k golden")
+        x, st, rc = ch.solve(*pose, precision=mfs.FP32_REFINED, cg_tol=1e-5, step_tol=1e-8, max_newton=60,
+                             cg_adaptive=1)
+        _say(f"  stats {st} err/bbox={_err(x, g['x'], prob):.3e}")
+        assert rc == 0 and _err(x, g["x"], prob) <= 1e-7
+        ch.close()
+    finally:
+        ctx.set_tuning(**base)

@@ -142,3 +142,26 @@ def test_server_rejects_bad_requests(mfs_ctx):
     assert e.value.code == -6
     srv.close()
     ch.close()
+
+
+def test_one_slot_reoccupied_by_other_characters(mfs_ctx):
+    """Regression: with one slot, every request reoccupies slot 0 with the
+    same slot list but another character (larger and smaller by turns, own
+    and lent workspaces); each must run on its own tiles and equal its solve
+    alone."""
+    mfs, ctx = mfs_ctx
+    probs, chars = _chars(mfs, ctx, [(3000, 12), (800, 8), (2000, 10)], 1000)
+    poses = [random_pose(p, 1100 + i) for i, p in enumerate(probs)]
+    alone = [ch.solve(*pose, **OPTS)[0] for ch, pose in zip(chars, poses)]
+    chars[1].release_workspace()
+    budget = chars[1].footprint()[1] + 4096
+    _say("server: one slot, characters 0 1 2 1 0 2")
+    srv = mfs.Server(ctx, slots=1, workspace_budget_bytes=budget, **OPTS)
+    order = [0, 1, 2, 1, 0, 2]
+    tickets = [(k, srv.submit(chars[k], *poses[k])) for k in order]
+    for k, tk in tickets:
+        x, st, _, rc = srv.wait(tk)
+        assert np.array_equal(x, alone[k]), f"character {k} differs from its solve alone"
+    srv.close()
+    for ch in chars:
+        ch.close()

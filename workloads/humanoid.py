@@ -287,17 +287,24 @@ def animation_pose(prob, seed, frame, fps=30.0, amp_deg=60.0, period=(2.0, 5.0))
     return forward_kinematics(prob["handle_parent"], prob["handle_joint"], local)
 
 
-def character_pool(count, seed0, tets_range, handles_range, models, poses_seed=None):
+def _pool_member(args):
+    i, seed0, tets_range, handles_range, models = args
+    rng = np.random.default_rng(seed0 + i)
+    m = float(np.exp(rng.uniform(np.log(tets_range[0]), np.log(tets_range[1]))))
+    nh = int(rng.integers(handles_range[0], handles_range[1] + 1))
+    return humanoid(seed0 + i, target_tets=m, n_bones=nh, models=models, name=f"char{i}_s{seed0 + i}")
+
+
+def character_pool(count, seed0, tets_range, handles_range, models, workers=1):
     """Characters with log-uniform sizes and uniform handle counts.
 
     Character i uses seed ``seed0 + i`` for its size, handle count, mesh and
-    materials.  Returns a list of problems.
+    materials, so the list does not depend on ``workers`` (processes that
+    build members in parallel).  Returns a list of problems.
     """
-    out = []
-    for i in range(count):
-        rng = np.random.default_rng(seed0 + i)
-        m = float(np.exp(rng.uniform(np.log(tets_range[0]), np.log(tets_range[1]))))
-        nh = int(rng.integers(handles_range[0], handles_range[1] + 1))
-        out.append(humanoid(seed0 + i, target_tets=m, n_bones=nh, models=models,
-                            name=f"char{i}_s{seed0 + i}"))
-    return out
+    jobs = [(i, seed0, tets_range, handles_range, tuple(models)) for i in range(count)]
+    if workers <= 1:
+        return [_pool_member(j) for j in jobs]
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_pool_member, jobs))
