@@ -159,7 +159,8 @@ typedef struct mfs_tuning {
   int32_t min_run, max_run;   /* bounds of later runs between checks */
   int32_t pcg_pipelined;      /* 1: FP32_REFINED solves run the pipelined PCG of Ghysels and
                                  Vanroose (one kernel per iteration, dot products overlapped
-                                 with the SpMV); FP64 solves always run the two-kernel form */
+                                 with the SpMV; FP32 matrix values, FP64 vectors and
+                                 recurrences); FP64 solves always run the two-kernel form */
 } mfs_tuning;
 
 int mfs_context_get_tuning(const mfs_context* ctx, mfs_tuning* out);
@@ -237,7 +238,10 @@ int mfs_solve_batch(mfs_context* ctx, int32_t count, mfs_character* const* chars
  * like this one and apply it to the context.  Each candidate solves the
  * given frames (as mfs_solve_batch with `opts`, but from the rest shape and
  * for exactly `newton_iterations` iterations, into scratch device memory)
- * twice, timing the second; the fastest wins.  Choices are kept per
+ * twice, timing the second.  The winner is the fastest candidate whose
+ * solves are as good as the default schedule's: no PCG solve left
+ * unconverged (or stopped by a breakdown) where the default had none, and
+ * every final gradient norm within 10x the default's.  Choices are kept per
  * (GPU architecture, size class = bit length of the total vertex count):
  * in the context, and in the text file `cache_path` when it is not NULL
  * (read first, rewritten after tuning).  A cached choice is applied without

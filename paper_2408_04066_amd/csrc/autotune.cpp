@@ -130,22 +130,43 @@ extern "C" int mfs_autotune(mfs_context* ctx, int32_t count, mfs_character* cons
   mfs_tuning base;
   MFS_TRY(mfs_context_get_tuning(ctx, &base));
 
-  auto time_one = [&](const mfs_tuning& t, double* ms) -> int {
+  // A candidate qualifies only if its solves are as good as the default
+  // schedule's: no PCG solve stopped unconverged (or by breakdown) where the
+  // default had none, and every final gradient within 10x the default's.
+  std::vector<mfs_solve_stats> ref(count), got(count);
+  auto time_one = [&](const mfs_tuning& t, double* ms, std::vector<mfs_solve_stats>& st) -> int {
     MFS_TRY(mfs_context_set_tuning(ctx, &t));
     // first run captures this schedule's graphs; the second is timed
     for (int rep = 0; rep < 2; ++rep) {
       const auto t0 = std::chrono::steady_clock::now();
-      const int rc = solve_systems(ctx, count, chars, handle_R, handle_t, &o, xo.data(), nullptr);
+      const int rc = solve_systems(ctx, count, chars, handle_R, handle_t, &o, xo.data(), st.data());
       if (rc < 0) return rc;
       MFS_HIP(hipStreamSynchronize(ctx->stream));
       *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     return MFS_OK;
   };
+  auto qualifies = [&]() {
+    for (int i = 0; i < count; ++i) {
+      if (got[i].cg_not_converged > ref[i].cg_not_converged) return false;
+      if (!(got[i].grad_norm <= 10.0 * ref[i].grad_norm + 1e-300)) return false;
+    }
+    return true;
+  };
 
   mfs_tuning win = base;
   win.use_graphs = 1;
+  win.pcg_pipelined = 0;
   double win_ms = INFINITY;
+  {
+    double ms;
+    const int rc = time_one(win, &ms, ref);
+    if (rc < 0) {
+      (void)mfs_context_set_tuning(ctx, &base);
+      return rc;
+    }
+    win_ms = ms;
+  }
   // stage 1: PCG form x lanes per row x graph length (the pipelined form
   // only where it applies, FP32 solves)
   const int forms = o.precision == MFS_FP32_REFINED ? 2 : 1;
@@ -157,12 +178,12 @@ extern "C" int mfs_autotune(mfs_context* ctx, int32_t count, mfs_character* cons
       t.pcg_lanes_per_row = lpr;
       t.graph_iterations = gi;
       double ms;
-      const int rc = time_one(t, &ms);
+      const int rc = time_one(t, &ms, got);
       if (rc < 0) {
         (void)mfs_context_set_tuning(ctx, &base);
         return rc;
       }
-      if (ms < win_ms) {
+      if (ms < win_ms && qualifies()) {
         win_ms = ms;
         win = t;
       }
@@ -177,12 +198,12 @@ extern "C" int mfs_autotune(mfs_context* ctx, int32_t count, mfs_character* cons
       t.min_run = minrun;
       if (t.max_run < t.min_run) t.max_run = t.min_run;
       double ms;
-      const int rc = time_one(t, &ms);
+      const int rc = time_one(t, &ms, got);
       if (rc < 0) {
         (void)mfs_context_set_tuning(ctx, &base);
         return rc;
       }
-      if (ms < win_ms) {
+      if (ms < win_ms && qualifies()) {
         win_ms = ms;
         win = t;
       }

@@ -66,7 +66,7 @@ struct CgState {
   double bb;       // b . b (both modes)
   double pq;       // p . K p of the last SpMV (ticket mode)
   int32_t it;      // iterations completed (ticket mode)
-  int32_t done;    // 1 once r . r <= tol^2 b . b
+  int32_t done;    // 1 once r . r <= tol^2 b . b; 2 after a breakdown (stopped, not converged)
   int32_t iters;   // iterations at convergence
   uint32_t arrive_init, arrive_spmv, arrive_update;  // arrival tickets (0 between kernels)
   int32_t it_a;    // all-read mode: iteration index read by the SpMV kernel

@@ -426,10 +426,10 @@ int Engine::run_cg(const std::vector<int>& act) {
   // algorithmic bytes of one SpMV launch over the slots still in PCG, for
   // the profiler's roofline figures: blocks + column indices + row pointers,
   // and per row 2 gathered inputs and 2 outputs (standard form), or the
-  // gathered m, 9 vectors read and 9 written and the 3x3 preconditioner
-  // block (pipelined form, which fuses the vector updates)
+  // gathered m, 9 vectors read and 9 written (FP64) and the 3x3
+  // preconditioner block (pipelined form, which fuses the vector updates)
   const double word = fp32_ ? 4.0 : 8.0;
-  const double per_row = pipe ? (3.0 + 27.0 + 27.0 + 6.0) * word : 12.0 * word;
+  const double per_row = pipe ? (3.0 + 27.0 + 27.0) * 8.0 + 6.0 * word : 12.0 * word;
   auto spmv_bytes = [&]() {
     double by = 0.0;
     for (int i : act)
@@ -486,13 +486,14 @@ int Engine::run_cg(const std::vector<int>& act) {
   for (int i : act) {
     if (hg[i].done) {
       slot_[i].cg += hg[i].iters;
+      if (hg[i].done == 2) slot_[i].cg_fail++;
     } else {
       slot_[i].cg += o_.cg_max;
       slot_[i].cg_fail++;
     }
   }
   ProfScope ps(ctx, MFS_K_OTHER);
-  launch_cg_finish(ctx->stream, dsd, ts_.dv, ts_.nv, fp32_);
+  launch_cg_finish(ctx->stream, dsd, ts_.dv, ts_.nv, pipe ? 0 : fp32_);  // pipelined iterate is FP64
   return MFS_OK;
 }
 
@@ -645,7 +646,10 @@ int Engine::step() {
   }
   {
     ProfScope ps(ctx, MFS_K_OTHER);
-    launch_cg_init(st, dsd, ts_.dv, ts_.nv, fp32_);
+    if (ctx->pipelined && fp32_)
+      launch_pcg_init(st, dsd, ts_.dv, ts_.nv, fp32_);
+    else
+      launch_cg_init(st, dsd, ts_.dv, ts_.nv, fp32_);
   }
   MFS_HIP(hipGetLastError());
   MFS_TRY(run_cg(act));

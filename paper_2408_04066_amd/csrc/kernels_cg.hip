@@ -22,11 +22,14 @@
 
 namespace mfs {
 
-template <typename T>
-__device__ __forceinline__ void precondition(const T* __restrict__ mi, const T rv[3], T zv[3]) {
-  zv[0] = mi[0] * rv[0] + mi[5] * rv[1] + mi[4] * rv[2];
-  zv[1] = mi[5] * rv[0] + mi[1] * rv[1] + mi[3] * rv[2];
-  zv[2] = mi[4] * rv[0] + mi[3] * rv[1] + mi[2] * rv[2];
+// z = M_row^-1 r with the symmetric 3x3 inverse block stored in precision T
+// and the vectors in precision V (the product runs in V).
+template <typename T, typename V>
+__device__ __forceinline__ void precondition(const T* __restrict__ mi, const V rv[3], V zv[3]) {
+  const V m0 = (V)mi[0], m1 = (V)mi[1], m2 = (V)mi[2], m3 = (V)mi[3], m4 = (V)mi[4], m5 = (V)mi[5];
+  zv[0] = m0 * rv[0] + m5 * rv[1] + m4 * rv[2];
+  zv[1] = m5 * rv[0] + m1 * rv[1] + m3 * rv[2];
+  zv[2] = m4 * rv[0] + m3 * rv[1] + m2 * rv[2];
 }
 
 // ONE: a single system whose descriptor is the kernel argument `one` and
@@ -43,7 +46,7 @@ __device__ __forceinline__ Tile vertex_tile(const Tile* __restrict__ tiles, int 
 // workgroup of a system sets its PCG state (and `done` when b is already
 // within tolerance).  All-read mode: tile 0 resets the state; the first SpMV
 // folds the partials and tests convergence.
-template <typename T>
+template <typename T, typename V = T>
 __global__ __launch_bounds__(64) void k_cg_init(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
                                                 int ntiles) {
   __shared__ int last;
@@ -52,17 +55,17 @@ __global__ __launch_bounds__(64) void k_cg_init(const SysDesc* __restrict__ sd, 
   const int row = t.begin + threadIdx.x;
   double rz = 0.0, rr = 0.0, bb = 0.0;
   if (row < t.end) {
-    T* r = (T*)S.r;
-    T* z = (T*)S.z;
-    T* xc = (T*)S.xc;
-    T rv[3], zv[3];
+    V* r = (V*)S.r;
+    V* z = (V*)S.z;
+    V* xc = (V*)S.xc;
+    V rv[3], zv[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const double bv = S.b[3 * row + i];
       bb += bv * bv;
-      rv[i] = (T)bv;
+      rv[i] = (V)bv;
       r[3 * row + i] = rv[i];
-      xc[3 * row + i] = (T)0;
+      xc[3 * row + i] = (V)0;
     }
     precondition((const T*)S.minv + 6 * row, rv, zv);
 #pragma unroll
@@ -296,26 +299,30 @@ __global__ __launch_bounds__(64) void k_cg_update(const SysDesc* __restrict__ sd
 // iteration are per-tile partials double-buffered by parity.  The SpMV of
 // iteration i gathers m_i, which is final when the launch starts, so it does
 // not wait for the fold that gives alpha_i and beta_i.  In exact arithmetic
-// the iterates equal those of the two-kernel PCG.  The parity is a launch
+// the iterates equal those of the two-kernel PCG.  The matrix values and
+// preconditioner blocks are read in precision T, every vector and recurrence
+// is kept in V: with T = float the extra recurrences of the pipelined form
+// lose the residual in FP32 rounding well before 1e-5 (its three-term
+// updates break down), so the FP32 path runs them in FP64.  The parity is a launch
 // argument: a captured run of an even number of iterations replays from any
 // even iteration.
 
 // acc = (K v)_row over this lane's share of the row's blocks, then summed
 // over the LPR lanes of the row (every lane of the row gets the sum).
-template <typename T, int LPR>
-__device__ __forceinline__ void row_product(const SysDesc& S, const T* __restrict__ v, int row, bool valid, int lane,
-                                            T acc[3]) {
-  acc[0] = acc[1] = acc[2] = (T)0;
+template <typename T, typename V, int LPR>
+__device__ __forceinline__ void row_product(const SysDesc& S, const V* __restrict__ v, int row, bool valid, int lane,
+                                            V acc[3]) {
+  acc[0] = acc[1] = acc[2] = (V)0;
   if (valid) {
     const T* vals = (const T*)S.vals;
     const size_t nz = S.nnzb;
     const int e = S.rowptr[row + 1];
     for (int sl = S.rowptr[row] + lane; sl < e; sl += LPR) {
       const int c = S.colidx[sl];
-      const T v0 = v[3 * c], v1 = v[3 * c + 1], v2 = v[3 * c + 2];
-      acc[0] += vals[sl] * v0 + vals[nz + sl] * v1 + vals[2 * nz + sl] * v2;
-      acc[1] += vals[3 * nz + sl] * v0 + vals[4 * nz + sl] * v1 + vals[5 * nz + sl] * v2;
-      acc[2] += vals[6 * nz + sl] * v0 + vals[7 * nz + sl] * v1 + vals[8 * nz + sl] * v2;
+      const V v0 = v[3 * c], v1 = v[3 * c + 1], v2 = v[3 * c + 2];
+      acc[0] += (V)vals[sl] * v0 + (V)vals[nz + sl] * v1 + (V)vals[2 * nz + sl] * v2;
+      acc[1] += (V)vals[3 * nz + sl] * v0 + (V)vals[4 * nz + sl] * v1 + (V)vals[5 * nz + sl] * v2;
+      acc[2] += (V)vals[6 * nz + sl] * v0 + (V)vals[7 * nz + sl] * v1 + (V)vals[8 * nz + sl] * v2;
     }
   }
 #pragma unroll
@@ -328,7 +335,7 @@ __device__ __forceinline__ void row_product(const SysDesc& S, const T* __restric
 
 // After k_cg_init (r = b, x = 0, u = M^-1 r, partials r.r and b.b):
 // w = K u, m_0 = M^-1 w, recurrences cleared, partials gamma_0 and delta_0.
-template <typename T, int LPR, bool ONE>
+template <typename T, typename V, int LPR, bool ONE>
 __global__ __launch_bounds__(64 * LPR) void k_pcg_start(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
                                                         int ntiles, const SysDesc one) {
   __shared__ double red[2][LPR];
@@ -366,26 +373,26 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_start(const SysDesc* __restric
   const int lane = threadIdx.x % LPR;
   const int row = t.begin + threadIdx.x / LPR;
   const bool valid = row < t.end;
-  const T* u = (const T*)S.z;
-  T w[3];
-  row_product<T, LPR>(S, u, row, valid, lane, w);
+  const V* u = (const V*)S.z;
+  V w[3];
+  row_product<T, V, LPR>(S, u, row, valid, lane, w);
   double g = 0.0, dl = 0.0;
   if (valid && lane == 0) {
-    T m[3];
+    V m[3];
     precondition((const T*)S.minv + 6 * row, w, m);
-    T* wv = (T*)S.v0;
-    T* mv = (T*)S.p1;
-    T* zv = (T*)S.v1;
-    T* qv = (T*)S.v2;
-    T* sv = (T*)S.v3;
-    T* pv = (T*)S.p0;
-    const T* r = (const T*)S.r;
+    V* wv = (V*)S.v0;
+    V* mv = (V*)S.p1;
+    V* zv = (V*)S.v1;
+    V* qv = (V*)S.v2;
+    V* sv = (V*)S.v3;
+    V* pv = (V*)S.p0;
+    const V* r = (const V*)S.r;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const int k = 3 * row + i;
       wv[k] = w[i];
       mv[k] = m[i];
-      zv[k] = qv[k] = sv[k] = pv[k] = (T)0;
+      zv[k] = qv[k] = sv[k] = pv[k] = (V)0;
       const double uk = (double)u[k];
       g += (double)r[k] * uk;
       dl += (double)w[i] * uk;
@@ -409,7 +416,7 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_start(const SysDesc* __restric
 }
 
 // Iteration i (parity = i & 1) of the pipelined PCG.
-template <typename T, int LPR, bool ONE>
+template <typename T, typename V, int LPR, bool ONE>
 __global__ __launch_bounds__(64 * LPR) void k_pcg_iter(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
                                                        int ntiles, const SysDesc one, int parity) {
   __shared__ double red[3][LPR];
@@ -418,16 +425,20 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_iter(const SysDesc* __restrict
   const Tile t = vertex_tile<ONE>(tiles, ntiles, one);
   const SysDesc& S = ONE ? one : sd[t.sys];
   CgState* st = S.cg;
-  if (S.ticket && st->done) return;
+  // A run of launches goes on after convergence (or a breakdown) while its
+  // parity argument keeps alternating; the planes of the other parity still
+  // hold the previous iteration's sums, so every later launch must stop here.
+  // (Within the launch that sets `done`, every workgroup stops anyway.)
+  if (st->done) return;
   const int par = parity & 1;
   const int lane = threadIdx.x % LPR;
   const int row = t.begin + threadIdx.x / LPR;
   const bool valid = row < t.end;
-  const T* mi = (const T*)(par ? S.q : S.p1);
-  T* mn = (T*)(par ? S.p1 : S.q);
+  const V* mi = (const V*)(par ? S.q : S.p1);
+  V* mn = (V*)(par ? S.p1 : S.q);
   // n_i = K m_i: needs nothing from the fold below
-  T nv[3];
-  row_product<T, LPR>(S, mi, row, valid, lane, nv);
+  V nv[3];
+  row_product<T, V, LPR>(S, mi, row, valid, lane, nv);
   double gam, del;
   if (S.ticket) {
     gam = st->g;
@@ -457,7 +468,7 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_iter(const SysDesc* __restrict
   const double beta = gam / st->g_prev[par ^ 1];
   const double den = del - beta * gam / st->a_prev[par ^ 1];
   if (!(den > 0.0) || !(gam > 0.0)) {  // breakdown (lost positive definiteness in rounding): stop here
-    if (t.local == 0 && threadIdx.x == 0) st->done = 1;
+    if (t.local == 0 && threadIdx.x == 0) st->done = 2;  // reported as not converged
     return;
   }
   const double alpha = gam / den;
@@ -466,32 +477,32 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_iter(const SysDesc* __restrict
     st->g_prev[par] = gam;
     if (!S.ticket) st->iters += 1;
   }
-  const T ta = (T)alpha, tb = (T)beta;
+  const V ta = (V)alpha, tb = (V)beta;
   double g = 0.0, dl = 0.0, rr = 0.0;
   if (valid && lane == 0) {
-    T* zv = (T*)S.v1;
-    T* qv = (T*)S.v2;
-    T* sv = (T*)S.v3;
-    T* pv = (T*)S.p0;
-    T* xv = (T*)S.xc;
-    T* rv = (T*)S.r;
-    T* uv = (T*)S.z;
-    T* wv = (T*)S.v0;
-    T w[3], mnew[3];
+    V* zv = (V*)S.v1;
+    V* qv = (V*)S.v2;
+    V* sv = (V*)S.v3;
+    V* pv = (V*)S.p0;
+    V* xv = (V*)S.xc;
+    V* rv = (V*)S.r;
+    V* uv = (V*)S.z;
+    V* wv = (V*)S.v0;
+    V w[3], mnew[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const int k = 3 * row + i;
-      const T z = nv[i] + tb * zv[k];
-      const T q = mi[k] + tb * qv[k];
-      const T sk = wv[k] + tb * sv[k];
-      const T pk = uv[k] + tb * pv[k];
+      const V z = nv[i] + tb * zv[k];
+      const V q = mi[k] + tb * qv[k];
+      const V sk = wv[k] + tb * sv[k];
+      const V pk = uv[k] + tb * pv[k];
       zv[k] = z;
       qv[k] = q;
       sv[k] = sk;
       pv[k] = pk;
       xv[k] += ta * pk;
-      const T r = rv[k] - ta * sk;
-      const T u = uv[k] - ta * q;
+      const V r = rv[k] - ta * sk;
+      const V u = uv[k] - ta * q;
       w[i] = wv[k] - ta * z;
       rv[k] = r;
       uv[k] = u;
@@ -610,35 +621,44 @@ void launch_cg_update(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv
   }
 }
 
-template <typename T, bool ONE>
+template <typename T, typename V, bool ONE>
 static void pcg_start_t(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int lpr, const SysDesc& one) {
   switch (lpr) {
     case 2:
-      MFS_LAUNCH((k_pcg_start<T, 2, ONE>), dim3(ntv), dim3(128), 0, st, sd, tv, ntv, one);
+      MFS_LAUNCH((k_pcg_start<T, V, 2, ONE>), dim3(ntv), dim3(128), 0, st, sd, tv, ntv, one);
       break;
     case 8:
-      MFS_LAUNCH((k_pcg_start<T, 8, ONE>), dim3(ntv), dim3(512), 0, st, sd, tv, ntv, one);
+      MFS_LAUNCH((k_pcg_start<T, V, 8, ONE>), dim3(ntv), dim3(512), 0, st, sd, tv, ntv, one);
       break;
     default:
-      MFS_LAUNCH((k_pcg_start<T, 4, ONE>), dim3(ntv), dim3(256), 0, st, sd, tv, ntv, one);
+      MFS_LAUNCH((k_pcg_start<T, V, 4, ONE>), dim3(ntv), dim3(256), 0, st, sd, tv, ntv, one);
       break;
   }
 }
 
-template <typename T, bool ONE>
+template <typename T, typename V, bool ONE>
 static void pcg_iter_t(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int lpr, const SysDesc& one,
                        int parity) {
   switch (lpr) {
     case 2:
-      MFS_LAUNCH((k_pcg_iter<T, 2, ONE>), dim3(ntv), dim3(128), 0, st, sd, tv, ntv, one, parity);
+      MFS_LAUNCH((k_pcg_iter<T, V, 2, ONE>), dim3(ntv), dim3(128), 0, st, sd, tv, ntv, one, parity);
       break;
     case 8:
-      MFS_LAUNCH((k_pcg_iter<T, 8, ONE>), dim3(ntv), dim3(512), 0, st, sd, tv, ntv, one, parity);
+      MFS_LAUNCH((k_pcg_iter<T, V, 8, ONE>), dim3(ntv), dim3(512), 0, st, sd, tv, ntv, one, parity);
       break;
     default:
-      MFS_LAUNCH((k_pcg_iter<T, 4, ONE>), dim3(ntv), dim3(256), 0, st, sd, tv, ntv, one, parity);
+      MFS_LAUNCH((k_pcg_iter<T, V, 4, ONE>), dim3(ntv), dim3(256), 0, st, sd, tv, ntv, one, parity);
       break;
   }
+}
+
+// The pipelined form keeps FP64 vectors; fp32 selects FP32 matrix values.
+void launch_pcg_init(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32) {
+  if (!ntv) return;
+  if (fp32)
+    MFS_LAUNCH((k_cg_init<float, double>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv);
+  else
+    MFS_LAUNCH((k_cg_init<double, double>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv);
 }
 
 void launch_pcg_start(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, int lpr,
@@ -647,11 +667,11 @@ void launch_pcg_start(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv
   static const SysDesc none{};
   const SysDesc& o = one ? *one : none;
   if (fp32) {
-    if (one) pcg_start_t<float, true>(st, sd, tv, ntv, lpr, o);
-    else pcg_start_t<float, false>(st, sd, tv, ntv, lpr, o);
+    if (one) pcg_start_t<float, double, true>(st, sd, tv, ntv, lpr, o);
+    else pcg_start_t<float, double, false>(st, sd, tv, ntv, lpr, o);
   } else {
-    if (one) pcg_start_t<double, true>(st, sd, tv, ntv, lpr, o);
-    else pcg_start_t<double, false>(st, sd, tv, ntv, lpr, o);
+    if (one) pcg_start_t<double, double, true>(st, sd, tv, ntv, lpr, o);
+    else pcg_start_t<double, double, false>(st, sd, tv, ntv, lpr, o);
   }
 }
 
@@ -661,11 +681,11 @@ void launch_pcg_iter(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv,
   static const SysDesc none{};
   const SysDesc& o = one ? *one : none;
   if (fp32) {
-    if (one) pcg_iter_t<float, true>(st, sd, tv, ntv, lpr, o, parity);
-    else pcg_iter_t<float, false>(st, sd, tv, ntv, lpr, o, parity);
+    if (one) pcg_iter_t<float, double, true>(st, sd, tv, ntv, lpr, o, parity);
+    else pcg_iter_t<float, double, false>(st, sd, tv, ntv, lpr, o, parity);
   } else {
-    if (one) pcg_iter_t<double, true>(st, sd, tv, ntv, lpr, o, parity);
-    else pcg_iter_t<double, false>(st, sd, tv, ntv, lpr, o, parity);
+    if (one) pcg_iter_t<double, double, true>(st, sd, tv, ntv, lpr, o, parity);
+    else pcg_iter_t<double, double, false>(st, sd, tv, ntv, lpr, o, parity);
   }
 }
 

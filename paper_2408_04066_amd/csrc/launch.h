@@ -61,7 +61,10 @@ void launch_cg_init(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, 
 void launch_cg_spmv(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, int lpr,
                     const SysDesc* one);
 void launch_cg_update(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, const SysDesc* one);
-// pipelined PCG: start (after launch_cg_init) and one iteration of parity i & 1
+// pipelined PCG (FP64 vectors; fp32 selects FP32 matrix values): init
+// (r = b, x = 0, u = M^-1 r), start (w = K u, m_0) and one iteration of
+// parity i & 1; finish with launch_cg_finish(..., fp32 = 0)
+void launch_pcg_init(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32);
 void launch_pcg_start(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, int lpr,
                       const SysDesc* one);
 void launch_pcg_iter(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, int lpr,

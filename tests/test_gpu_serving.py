@@ -78,9 +78,11 @@ def test_served_equals_alone_with_arena_admission(mfs_ctx):
     assert info["completed"] == len(tickets) and info["queued"] == 0 and info["running"] == 0
     assert 0 < info["arena_peak"] <= budget and info["arena_in_use"] == 0
     assert info["slot_steps"] / info["steps"] > 1.0  # requests overlapped in the batch
-    for k, x, st, times in got:
+    for j, (k, x, st, times) in enumerate(got):
         ref_x, ref_st = alone[k]
-        assert np.array_equal(x, ref_x), f"request for character {k} differs from its solve alone"
+        assert np.array_equal(x, ref_x), (
+            f"request {j} (character {k}) differs from its solve alone: max |dx| "
+            f"{np.max(np.abs(x - ref_x)):.3e}; served {st}; alone {ref_st}; times {times}; info {info}")
         assert st["iterations"] == ref_st["iterations"] and st["cg_iterations"] == ref_st["cg_iterations"]
         assert st["status"] == ref_st["status"]
         assert times["submit_s"] <= times["admit_s"] <= times["done_s"]
