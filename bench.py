@@ -84,7 +84,7 @@ def _workers():
     return max(1, min(16, os.cpu_count() or 1))
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_spmv_humanoid50k.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_pcg_humanoid50k.md")
 TRAFFIC_SOURCES = ("paper_2408_04066_amd/csrc/kernels_cg.hip", "paper_2408_04066_amd/csrc/common.h")
 
 
@@ -161,7 +161,7 @@ def frame_bench(args, mfs, torch):
     _progress(f"{wname}: {len(chars)} characters resident, {m_tot} tets")
     tuned = None
     if not args.no_autotune:
-        tuned, tms = mfs.autotune(ctx, chars, steps[0], newton_iterations=4, **opts)
+        tuned, tms = mfs.autotune(ctx, chars, steps[0], newton_iterations=4, cache_path=args.tune_cache, **opts)
         _progress(f"autotuned PCG schedule {tuned} ({tms:.1f} ms per 4 Newton iterations)")
 
     def frame(poses, o):
@@ -386,6 +386,8 @@ def main():
     ap.add_argument("--roofline-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default PCG schedule")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file: reuse a choice made for this GPU and size class")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (the reference kernel "
                          "that scales HBM byte counters)")

@@ -345,10 +345,15 @@ typedef struct mfs_profile {
   double gpu_ms[MFS_K_FAMILIES];     /* summed HIP-event time of the timed launches */
   int64_t timed[MFS_K_FAMILIES];     /* launches that were timed */
   int64_t launches[MFS_K_FAMILIES];  /* all launches of the family */
-  double bytes[MFS_K_FAMILIES];      /* algorithmic HBM bytes of the timed launches (SpMV:
-                                        every block value and column index, row pointers,
-                                        and per row the two gathered inputs and two outputs;
-                                        0 for families without a byte model) */
+  double bytes[MFS_K_FAMILIES];      /* algorithmic HBM bytes of the timed launches, counted
+                                        for the systems a launch iterates (a system whose PCG
+                                        stopped earlier in the run costs nothing).  SpMV family:
+                                        every block value and column index and the row
+                                        pointers, plus per row the two gathered inputs and
+                                        two outputs (two-kernel PCG) or the gathered m, nine
+                                        FP64 vectors read and written and the 3x3
+                                        preconditioner block (pipelined PCG); 0 for families
+                                        without a byte model */
 } mfs_profile;
 
 /* Time kernel launches of this context with HIP events on its stream:

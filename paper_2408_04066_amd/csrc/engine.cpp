@@ -28,10 +28,10 @@ int upload_ctrl(mfs_context* ctx, int count) {
   return MFS_OK;
 }
 
-int read_cg(mfs_context* ctx, int count) {
+int read_cg(mfs_context* ctx, int count, bool resolve) {
   MFS_HIP(hipMemcpyAsync(ctx->h_cg.p, ctx->cg.p, count * sizeof(CgState), hipMemcpyDeviceToHost, ctx->stream));
   MFS_HIP(hipStreamSynchronize(ctx->stream));
-  prof_resolve(ctx);
+  if (resolve) prof_resolve(ctx);
   return MFS_OK;
 }
 
@@ -126,17 +126,19 @@ static int cg_graph(mfs_context* ctx, const SysDesc* sd, const TileSet& ts, int 
 // of iterations and starts at an even one (the kernels take the parity as
 // an argument).
 static int enqueue_cg(mfs_context* ctx, const SysDesc* sd, const TileSet& ts, int fp32, int run,
-                      const SysDesc* one, double spmv_bytes, bool pipe, int start) {
+                      const SysDesc* one, bool pipe, int start) {
   const int G = ctx->graph_iters;
   int done = 0;
+  // timed SpMV-family launches carry their iteration index; their bytes are
+  // set once the run's convergence counts are known (run_cg)
   auto direct = [&](int it) {
     if (pipe) {
-      ProfScope ps(ctx, MFS_K_SPMV, spmv_bytes);
+      ProfScope ps(ctx, MFS_K_SPMV, 0.0, it);
       launch_pcg_iter(ctx->stream, sd, ts.dv, ts.nv, fp32, ctx->lpr, one, it & 1);
       return;
     }
     {
-      ProfScope ps(ctx, MFS_K_SPMV, spmv_bytes);
+      ProfScope ps(ctx, MFS_K_SPMV, 0.0, it);
       launch_cg_spmv(ctx->stream, sd, ts.dv, ts.nv, fp32, ctx->lpr, one);
     }
     ProfScope ps(ctx, MFS_K_CG_UPDATE);
@@ -430,14 +432,20 @@ int Engine::run_cg(const std::vector<int>& act) {
   // preconditioner block (pipelined form, which fuses the vector updates)
   const double word = fp32_ ? 4.0 : 8.0;
   const double per_row = pipe ? (3.0 + 27.0 + 27.0) * 8.0 + 6.0 * word : 12.0 * word;
-  auto spmv_bytes = [&]() {
-    double by = 0.0;
-    for (int i : act)
-      if (cit == 0 || !hg[i].done) {
-        const mfs_character* c = slot_[i].ch;
-        by += c->nnzb * (9.0 * word + 4.0) + (c->n + 1) * 4.0 + c->n * per_row;
-      }
-    return by;
+  // A launch at iteration index `it` does work for a slot whose PCG had not
+  // stopped before it (a stopped slot's launches return at once).
+  auto attribute_bytes = [&]() {
+    for (ProfPending& p : ctx->pending) {
+      if (p.fam != MFS_K_SPMV || p.tag < 0) continue;
+      double by = 0.0;
+      for (int i : act)
+        if (!hg[i].done || p.tag < hg[i].iters) {
+          const mfs_character* c = slot_[i].ch;
+          by += c->nnzb * (9.0 * word + 4.0) + (c->n + 1) * 4.0 + c->n * per_row;
+        }
+      p.bytes = by;
+      p.tag = -1;
+    }
   };
   if (pipe) {
     ProfScope ps(ctx, MFS_K_OTHER);
@@ -448,10 +456,12 @@ int Engine::run_cg(const std::vector<int>& act) {
   // observed residual decay of the slowest slot.
   while (cit < o_.cg_max) {
     const int run = std::min(chunk, o_.cg_max - cit);
-    MFS_TRY(enqueue_cg(ctx, dsd, ts_, fp32_, run, one, spmv_bytes(), pipe, cit));
+    MFS_TRY(enqueue_cg(ctx, dsd, ts_, fp32_, run, one, pipe, cit));
     cit += run;
     MFS_HIP(hipGetLastError());
-    MFS_TRY(read_cg(ctx, n));
+    MFS_TRY(read_cg(ctx, n, false));
+    attribute_bytes();
+    prof_resolve(ctx);
     bool all = true;
     int need = 0;
     for (int i : act) {

@@ -46,7 +46,7 @@ struct TileSet {
 };
 
 int upload_ctrl(mfs_context* ctx, int count);
-int read_cg(mfs_context* ctx, int count);
+int read_cg(mfs_context* ctx, int count, bool resolve = true);
 int read_red(mfs_context* ctx, int count);
 // Tiles of the listed slots (indices into by_slot), uploaded to the
 // context's tile buffer, plus the slot-id list of the finalize kernel.  The

@@ -70,6 +70,7 @@ struct ProfPending {
   int fam;
   double bytes;
   hipEvent_t a, b;
+  int tag;  // PCG iteration index of an SpMV-family launch whose bytes are set after its run (-1: none)
 };
 struct CgGraph {
   const SysDesc* sd;
@@ -159,7 +160,8 @@ struct ProfScope {
   int fam;
   double bytes;
   hipEvent_t a = nullptr, b = nullptr;
-  ProfScope(mfs_context* ctx, int family, double algorithmic_bytes = 0.0);
+  int tag = -1;
+  ProfScope(mfs_context* ctx, int family, double algorithmic_bytes = 0.0, int iteration_tag = -1);
   ~ProfScope();
 };
 // Fold completed event pairs into the counters (call after a stream sync).

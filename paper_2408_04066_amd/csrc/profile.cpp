@@ -27,8 +27,8 @@ LaunchEvents& launch_events() {
 
 // A sampled scope hands its event pair to the launches inside it (see
 // MFS_LAUNCH); the pair is kept only if a kernel was launched.
-ProfScope::ProfScope(mfs_context* ctx, int family, double algorithmic_bytes)
-    : c(ctx), fam(family), bytes(algorithmic_bytes) {
+ProfScope::ProfScope(mfs_context* ctx, int family, double algorithmic_bytes, int iteration_tag)
+    : c(ctx), fam(family), bytes(algorithmic_bytes), tag(iteration_tag) {
   const int64_t k = c->prof_launches[fam]++;
   if (c->prof_stride > 0 && k % c->prof_stride == 0) {
     a = get_event(c);
@@ -55,7 +55,7 @@ ProfScope::~ProfScope() {
     c->ev_pool.push_back(b);
     return;
   }
-  c->pending.push_back(ProfPending{fam, bytes, a, b});
+  c->pending.push_back(ProfPending{fam, bytes, a, b, tag});
 }
 
 void prof_resolve(mfs_context* c) {
