@@ -161,6 +161,10 @@ typedef struct mfs_tuning {
                                  Vanroose (one kernel per iteration, dot products overlapped
                                  with the SpMV; FP32 matrix values, FP64 vectors and
                                  recurrences); FP64 solves always run the two-kernel form */
+  int32_t allread_max_tiles;  /* PCG dot products of a system with at most this many 64-row
+                                 tiles are folded by every workgroup of the next kernel
+                                 (no fences); larger systems fold them in the last workgroup
+                                 to finish (arrival ticket with a release fence) */
 } mfs_tuning;
 
 int mfs_context_get_tuning(const mfs_context* ctx, mfs_tuning* out);

@@ -166,6 +166,7 @@ extern "C" int mfs_context_get_tuning(const mfs_context* ctx, mfs_tuning* out) {
   out->min_run = ctx->cg_min_run;
   out->max_run = ctx->cg_max_run;
   out->pcg_pipelined = ctx->pipelined ? 1 : 0;
+  out->allread_max_tiles = ctx->allread_tiles;
   return MFS_OK;
 }
 
@@ -179,6 +180,7 @@ extern "C" int mfs_context_set_tuning(mfs_context* ctx, const mfs_tuning* t) {
   if (t->first_check < 1 || t->min_run < 1 || t->max_run < t->min_run)
     return set_error(MFS_E_INVALID, "invalid PCG run bounds");
   if (t->pcg_pipelined != 0 && t->pcg_pipelined != 1) return set_error(MFS_E_INVALID, "pcg_pipelined must be 0 or 1");
+  if (t->allread_max_tiles < 0) return set_error(MFS_E_INVALID, "allread_max_tiles must be >= 0");
   MFS_HIP(hipSetDevice(ctx->device));
   MFS_HIP(hipStreamSynchronize(ctx->stream));
   for (const CgGraph& g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
@@ -190,5 +192,6 @@ extern "C" int mfs_context_set_tuning(mfs_context* ctx, const mfs_tuning* t) {
   ctx->cg_min_run = t->min_run;
   ctx->cg_max_run = t->max_run;
   ctx->pipelined = t->pcg_pipelined != 0;
+  ctx->allread_tiles = t->allread_max_tiles;
   return MFS_OK;
 }

@@ -3,8 +3,9 @@
 // The schedule knobs are the PCG form (two kernels per iteration, or the
 // pipelined one-kernel form for FP32 solves), the SpMV lanes per block row
 // (2, 4 or 8 lanes of a 64-row tile), the number of PCG iterations per
-// captured graph, and the lengths of the first and shortest runs between
-// host convergence checks.  Candidates
+// captured graph, the lengths of the first and shortest runs between host
+// convergence checks, and for large systems the reduction mode (all-read
+// folds or fenced arrival tickets).  Candidates
 // are timed on the caller's own systems: each runs the same fixed number of
 // Newton iterations from the rest shape (the same launches for every
 // candidate, up to summation order), timed on the host clock around the
@@ -15,6 +16,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -49,9 +51,9 @@ std::vector<Entry> read_cache(const char* path) {
   if (!f) return out;
   char arch[128];
   Entry e{};
-  while (std::fscanf(f, "%127s %d %d %d %d %d %d %d %d %lf", arch, &e.size_class, &e.t.pcg_lanes_per_row,
+  while (std::fscanf(f, "%127s %d %d %d %d %d %d %d %d %d %lf", arch, &e.size_class, &e.t.pcg_lanes_per_row,
                      &e.t.use_graphs, &e.t.graph_iterations, &e.t.first_check, &e.t.min_run, &e.t.max_run,
-                     &e.t.pcg_pipelined, &e.ms) == 10) {
+                     &e.t.pcg_pipelined, &e.t.allread_max_tiles, &e.ms) == 11) {
     e.arch = arch;
     out.push_back(e);
   }
@@ -64,9 +66,9 @@ int write_cache(const char* path, const std::vector<Entry>& entries) {
   FILE* f = std::fopen(tmp.c_str(), "w");
   if (!f) return set_error(MFS_E_INVALID, "cannot write tuning cache %s", tmp.c_str());
   for (const Entry& e : entries)
-    std::fprintf(f, "%s %d %d %d %d %d %d %d %d %.6f\n", e.arch.c_str(), e.size_class, e.t.pcg_lanes_per_row,
+    std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %.6f\n", e.arch.c_str(), e.size_class, e.t.pcg_lanes_per_row,
                  e.t.use_graphs, e.t.graph_iterations, e.t.first_check, e.t.min_run, e.t.max_run,
-                 e.t.pcg_pipelined, e.ms);
+                 e.t.pcg_pipelined, e.t.allread_max_tiles, e.ms);
   std::fclose(f);
   if (std::rename(tmp.c_str(), path) != 0) return set_error(MFS_E_INVALID, "cannot replace tuning cache %s", path);
   return MFS_OK;
@@ -208,6 +210,29 @@ extern "C" int mfs_autotune(mfs_context* ctx, int32_t count, mfs_character* cons
         win = t;
       }
     }
+  // stage 3: reduction mode of the large systems (all-read folds instead of
+  // fenced arrival tickets), when the batch has any
+  int max_tiles = 0;
+  for (int i = 0; i < count; ++i) max_tiles = std::max(max_tiles, chars[i]->ntv);
+  if (max_tiles > win.allread_max_tiles) {
+    const mfs_tuning stage2 = win;
+    for (int lim : {1024, 4096, 1 << 20}) {
+      if (lim <= stage2.allread_max_tiles) continue;
+      mfs_tuning t = stage2;
+      t.allread_max_tiles = lim;
+      double ms;
+      const int rc = time_one(t, &ms, got);
+      if (rc < 0) {
+        (void)mfs_context_set_tuning(ctx, &base);
+        return rc;
+      }
+      if (ms < win_ms && qualifies()) {
+        win_ms = ms;
+        win = t;
+      }
+      if (max_tiles <= lim) break;
+    }
+  }
   MFS_TRY(mfs_context_set_tuning(ctx, &win));
   bool replaced = false;
   for (auto& e : ctx->tune_cache)

@@ -52,11 +52,12 @@ enum PartSlot : int {
 // only by that last workgroup, after every workgroup of the system has read
 // the old values.
 //
-// Systems with at most kAllReadTiles vertex tiles skip the tickets (whose
-// release fence costs a few microseconds per workgroup): there every
-// workgroup folds the few partials itself ("all-read" mode) and the
-// iteration index is double-buffered in it_a / it_b (each written only by
-// the other kernel of the PCG pair).
+// Systems with at most a tuned number of vertex tiles (default
+// kAllReadTiles) skip the tickets (whose release fence costs a few
+// microseconds per workgroup): there every workgroup folds the partials
+// itself ("all-read" mode, O(tiles) reads per workgroup) and the iteration
+// index is double-buffered in it_a / it_b (each written only by the other
+// kernel of the PCG pair).
 constexpr int kAllReadTiles = 256;
 
 struct CgState {
@@ -122,7 +123,7 @@ struct Tile {
 struct SysDesc {
   int32_t n, m, nnzb, nh;
   int32_t ntv, ntt, nts, ptile;   // tiles per system: vertex, tet, slot; partial stride
-  int32_t ticket;                 // PCG reductions by arrival ticket (ntv > kAllReadTiles)
+  int32_t ticket;                 // PCG reductions by arrival ticket (ntv above the all-read limit)
   int32_t pad0;
   double ks;                      // pin stiffness
   // resident (reordered) mesh data

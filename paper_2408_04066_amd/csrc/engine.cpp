@@ -357,6 +357,7 @@ int Engine::attach(int i, mfs_character* ch, const double* R, const double* t) {
   tiles_valid_ = false;  // the slot's occupant changed
   SysDesc& d = hd_[i];
   d = ch->desc;
+  d.ticket = ch->ntv > ctx_->allread_tiles ? 1 : 0;
   d.red = ctx_->red.as<double>() + P_COUNT * i;
   d.cg = ctx_->cg.as<CgState>() + i;
   d.ctrl = ctx_->ctrl.as<Ctrl>() + i;

@@ -94,6 +94,7 @@ struct mfs_context {
   bool use_graphs = true;            // replay captured runs of PCG iterations
   int graph_iters = 8;               // PCG iterations per captured graph
   bool pipelined = false;            // FP32 solves: pipelined PCG, one kernel per iteration
+  int allread_tiles = mfs::kAllReadTiles;  // largest system (vertex tiles) with all-read PCG sums
   std::vector<mfs::CgGraph> graphs;
   // batch scratch
   mfs::DevBuf desc, ctrl, red, cg, tiles, sys_ids, tmp;
