@@ -112,7 +112,9 @@ typedef struct mfs_solve_opts {
                                warm-start pose T0 to the target T1 -- halving the increment
                                at most this many times and doubling it after each
                                intermediate pose converges (to a 1e-4 * bbox step) */
-  int32_t reserved;
+  int32_t fp32_cg_max;      /* FP32_REFINED: a Newton step whose FP32 PCG has not converged
+                               after this many iterations is solved again in FP64 (element
+                               records, assembly and PCG); 0 = 100 n^(1/3), at least 2000 */
 } mfs_solve_opts;
 
 typedef struct mfs_solve_stats {
@@ -123,11 +125,13 @@ typedef struct mfs_solve_stats {
   int32_t halvings;         /* line-search halvings summed over the frame */
   int32_t clamped;          /* neo-Hookean elements with clamped Hessian, last iteration */
   int32_t fp64_routed;      /* tets whose polar decomposition ran in FP64 (FP32 path) */
-  int32_t cg_not_converged; /* solves that hit cg_max */
+  int32_t cg_not_converged; /* solves that hit cg_max (or stopped by a breakdown) */
   double energy;            /* E(x) at the returned positions */
   double grad_norm;         /* ||grad E|| at the last Newton-phase assembly */
   double last_step;         /* max_v ||alpha dx_v|| of the last iteration */
   double cg_rel_residual;   /* ||r|| / ||b|| of the last PCG solve */
+  int32_t fp64_resolves;    /* FP32_REFINED: Newton steps re-solved in FP64 (fp32_cg_max) */
+  int32_t reserved;
 } mfs_solve_stats;
 
 /* ---- library and context --------------------------------------------- */

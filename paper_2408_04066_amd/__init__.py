@@ -63,17 +63,18 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("precision", c_i32), ("max_newton", c_i32), ("fixed_newton", c_i32),
                 ("step_tol", c_dbl), ("cg_tol", c_dbl), ("cg_max", c_i32), ("warm_start", c_i32),
                 ("output_memory", c_i32), ("cg_adaptive", c_i32), ("load_bisections", c_i32),
-                ("reserved", c_i32)]
+                ("fp32_cg_max", c_i32)]
 
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("status", c_i32), ("iterations", c_i32), ("mixed_iterations", c_i32),
                 ("cg_iterations", c_i32), ("halvings", c_i32), ("clamped", c_i32),
                 ("fp64_routed", c_i32), ("cg_not_converged", c_i32), ("energy", c_dbl),
-                ("grad_norm", c_dbl), ("last_step", c_dbl), ("cg_rel_residual", c_dbl)]
+                ("grad_norm", c_dbl), ("last_step", c_dbl), ("cg_rel_residual", c_dbl),
+                ("fp64_resolves", c_i32), ("reserved", c_i32)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
 class CharacterInfo(ctypes.Structure):

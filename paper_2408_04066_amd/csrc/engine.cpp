@@ -407,7 +407,12 @@ int Engine::tiles_for(const std::vector<int>& ids) {
   return MFS_OK;
 }
 
-int Engine::run_cg(const std::vector<int>& act) {
+int Engine::fp32_cap(const mfs_character* ch) const {
+  if (o_.fp32_cg_max > 0) return std::min(o_.cg_max, o_.fp32_cg_max);
+  return std::min(o_.cg_max, std::max(2000, (int)(100.0 * std::cbrt((double)ch->n))));
+}
+
+int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* failed) {
   mfs_context* ctx = ctx_;
   const SysDesc* dsd = ctx->desc.as<SysDesc>();
   const int n = (int)slot_.size();
@@ -425,13 +430,21 @@ int Engine::run_cg(const std::vector<int>& act) {
   // kernel argument.  A slot's arithmetic does not depend on the set.
   std::vector<int> live = act;
   const SysDesc* one = live.size() == 1 ? &hd_[live[0]] : nullptr;
-  const bool pipe = ctx->pipelined && fp32_;
+  const bool pipe = ctx->pipelined && fp32;
+  // per-slot iteration caps: the FP32 pass stops early where FP32 stalls
+  std::vector<int> cap(slot_.size(), o_.cg_max);
+  int max_cap = 0;
+  for (int i : act) {
+    cap[i] = failed ? fp32_cap(slot_[i].ch) : o_.cg_max;
+    max_cap = std::max(max_cap, cap[i]);
+  }
+  std::vector<int> stopped_at(slot_.size(), -1);
   // algorithmic bytes of one SpMV launch over the slots still in PCG, for
   // the profiler's roofline figures: blocks + column indices + row pointers,
   // and per row 2 gathered inputs and 2 outputs (standard form), or the
   // gathered m, 9 vectors read and 9 written (FP64) and the 3x3
   // preconditioner block (pipelined form, which fuses the vector updates)
-  const double word = fp32_ ? 4.0 : 8.0;
+  const double word = fp32 ? 4.0 : 8.0;
   const double per_row = pipe ? (3.0 + 27.0 + 27.0) * 8.0 + 6.0 * word : 12.0 * word;
   // A launch at iteration index `it` does work for a slot whose PCG had not
   // stopped before it (a stopped slot's launches return at once).
@@ -450,14 +463,14 @@ int Engine::run_cg(const std::vector<int>& act) {
   };
   if (pipe) {
     ProfScope ps(ctx, MFS_K_OTHER);
-    launch_pcg_start(ctx->stream, dsd, ts_.dv, ts_.nv, fp32_, ctx->lpr, one);
+    launch_pcg_start(ctx->stream, dsd, ts_.dv, ts_.nv, fp32, ctx->lpr, one);
   }
   // PCG in runs of iterations; after each run the host reads the
   // convergence flags and residuals and sizes the next run from the
   // observed residual decay of the slowest slot.
-  while (cit < o_.cg_max) {
-    const int run = std::min(chunk, o_.cg_max - cit);
-    MFS_TRY(enqueue_cg(ctx, dsd, ts_, fp32_, run, one, pipe, cit));
+  while (cit < max_cap) {
+    const int run = std::min(chunk, max_cap - cit);
+    MFS_TRY(enqueue_cg(ctx, dsd, ts_, fp32, run, one, pipe, cit));
     cit += run;
     MFS_HIP(hipGetLastError());
     MFS_TRY(read_cg(ctx, n, false));
@@ -485,8 +498,15 @@ int Engine::run_cg(const std::vector<int>& act) {
     if (all) break;
     chunk = std::min(std::max(need, ctx->cg_min_run), ctx->cg_max_run);
     std::vector<int> still;
-    for (int i : live)
-      if (!hg[i].done) still.push_back(i);
+    for (int i : live) {
+      if (hg[i].done) continue;
+      if (cit >= cap[i]) {  // this slot's cap: stop iterating it
+        stopped_at[i] = cit;
+        continue;
+      }
+      still.push_back(i);
+    }
+    if (still.empty()) break;
     if (still.size() < live.size()) {
       live.swap(still);
       MFS_TRY(tiles_for(live));  // the stream is idle after read_cg
@@ -495,16 +515,16 @@ int Engine::run_cg(const std::vector<int>& act) {
   }
   if (live.size() != act.size()) MFS_TRY(tiles_for(act));
   for (int i : act) {
-    if (hg[i].done) {
-      slot_[i].cg += hg[i].iters;
-      if (hg[i].done == 2) slot_[i].cg_fail++;
-    } else {
-      slot_[i].cg += o_.cg_max;
+    const bool ok = hg[i].done == 1;
+    slot_[i].cg += hg[i].done ? hg[i].iters : (stopped_at[i] >= 0 ? stopped_at[i] : cit);
+    if (ok) continue;
+    if (failed)
+      failed->push_back(i);
+    else
       slot_[i].cg_fail++;
-    }
   }
   ProfScope ps(ctx, MFS_K_OTHER);
-  launch_cg_finish(ctx->stream, dsd, ts_.dv, ts_.nv, pipe ? 0 : fp32_);  // pipelined iterate is FP64
+  launch_cg_finish(ctx->stream, dsd, ts_.dv, ts_.nv, pipe ? 0 : fp32);  // pipelined iterate is FP64
   return MFS_OK;
 }
 
@@ -663,7 +683,28 @@ int Engine::step() {
       launch_cg_init(st, dsd, ts_.dv, ts_.nv, fp32_);
   }
   MFS_HIP(hipGetLastError());
-  MFS_TRY(run_cg(act));
+  std::vector<int> redo;
+  MFS_TRY(run_cg(act, fp32_, fp32_ ? &redo : nullptr));
+  if (!redo.empty()) {
+    // FP32 could not solve these Newton systems (ill-conditioned beyond
+    // single precision): element records, assembly and PCG again in FP64
+    MFS_TRY(tiles_for(redo));
+    {
+      ProfScope ps(ctx, MFS_K_ELEMENT);
+      launch_element(st, dsd, dctrl, ts_.dt, ts_.nt, 0);
+    }
+    {
+      ProfScope ps(ctx, MFS_K_ASSEMBLE);
+      launch_assemble(st, dsd, ts_.ds, ts_.ns, 0);
+    }
+    {
+      ProfScope ps(ctx, MFS_K_OTHER);
+      launch_cg_init(st, dsd, ts_.dv, ts_.nv, 0);
+    }
+    MFS_HIP(hipGetLastError());
+    MFS_TRY(run_cg(redo, false, nullptr));
+    for (int i : redo) slot_[i].resolves++;
+  }
   MFS_TRY(linesearch(act));
 
   // updates
@@ -790,6 +831,7 @@ void Engine::stats(int i, mfs_solve_stats* s) const {
   s->clamped = S.clamped;
   s->fp64_routed = S.routed;
   s->cg_not_converged = S.cg_fail;
+  s->fp64_resolves = S.resolves;
   s->energy = S.E;
   s->grad_norm = S.grad;
   s->last_step = S.step;

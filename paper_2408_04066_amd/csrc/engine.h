@@ -22,7 +22,7 @@ struct SlotState {
   bool used = false, fresh = false, done = false;
   int phase = 0;  // 0 mixed (s != J x), 1 Newton (s = J x)
   int status = MFS_OK;
-  int iters = 0, mixed = 0, cg = 0, halvings = 0, clamped = 0, routed = 0, cg_fail = 0;
+  int iters = 0, mixed = 0, cg = 0, halvings = 0, clamped = 0, routed = 0, cg_fail = 0, resolves = 0;
   double E = INFINITY;
   bool E_known = false;
   double grad = NAN, step = NAN, relres = NAN;
@@ -93,7 +93,11 @@ class Engine {
   int set_pose(int slot, double tau);
   int restart_load_step(int slot);
   int tiles_for(const std::vector<int>& ids);
-  int run_cg(const std::vector<int>& act);
+  // PCG for the listed slots in the given precision; with `failed`, slots
+  // whose solve stops unconverged (cap or breakdown) are listed there instead
+  // of counted as failures (the FP32 pass, re-solved in FP64).
+  int run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* failed);
+  int fp32_cap(const mfs_character* ch) const;
   int linesearch(const std::vector<int>& act);
 
   mfs_context* ctx_;
