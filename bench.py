@@ -311,6 +311,16 @@ def serve_bench(args, mfs, torch):
     arrivals = np.cumsum(rng.exponential(1.0 / args.rate, size=n_req))
     who = rng.integers(0, len(chars), size=n_req)
     poses = [random_pose(probs[k], 50000 + j) for j, k in enumerate(who)]
+    tuned = None
+    if not args.no_autotune:  # schedule for a batch like the served mix: a sample of the pool
+        sample = list(range(0, len(chars), max(1, len(chars) // args.slots)))[:args.slots]
+        for k in sample:
+            chars[k].solve(*random_pose(probs[k], 1), **opts)  # re-creates the released workspace
+        tuned, tms = mfs.autotune(ctx, [chars[k] for k in sample], [random_pose(probs[k], 1) for k in sample],
+                                  newton_iterations=4, cache_path=args.tune_cache, **opts)
+        for k in sample:
+            chars[k].release_workspace()
+        _progress(f"autotuned PCG schedule {tuned} ({tms:.1f} ms per 4 Newton iterations)")
     srv = mfs.Server(ctx, slots=args.slots, queue_capacity=args.queue, workspace_budget_bytes=budget, **opts)
     for j in range(min(args.warmup, n_req)):  # warm the kernels and graphs
         srv.wait(srv.submit(chars[who[j]], *poses[j]))
@@ -367,7 +377,8 @@ def serve_bench(args, mfs, torch):
         "config": {"workload": f"serving_pool_{args.pool}_humanoids_2k_300k_tets_poisson_{args.rate:g}_per_s",
                    "characters": len(chars), "tets": sum(i["n_tets"] for i in infos),
                    "slots": args.slots, "queue_capacity": args.queue, "arena_bytes": budget,
-                   "duration_s": args.duration, "precision": "fp32 pcg + fp64 refinement"},
+                   "duration_s": args.duration, "precision": "fp32 pcg + fp64 refinement",
+                   "pcg_schedule": tuned or ctx.tuning()},
     }
     for c in chars:
         c.close()
