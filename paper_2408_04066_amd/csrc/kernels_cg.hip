@@ -169,18 +169,41 @@ __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict_
   const int row = t.begin + threadIdx.x / LPR;
   T a0 = 0, a1 = 0, a2 = 0;
   if (row < t.end) {
+    // batches of U blocks per lane: indices and values first, then the
+    // gathers (two dependent latencies per batch, not per block)
+    constexpr int U = LPR >= 16 ? 1 : 16 / LPR;
     const int e = S.rowptr[row + 1];
-    for (int sl = S.rowptr[row] + lane; sl < e; sl += LPR) {
-      const int c = S.colidx[sl];
-      T v0 = z[3 * c], v1 = z[3 * c + 1], v2 = z[3 * c + 2];
-      if (it) {
-        v0 += tb * po[3 * c];
-        v1 += tb * po[3 * c + 1];
-        v2 += tb * po[3 * c + 2];
+    for (int base = S.rowptr[row] + lane; base < e; base += U * LPR) {
+      int c[U];
+      T a[U][9];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {  // past the row's end: reload its last block, weight 0
+        const int sl = base + u * LPR;
+        const int sc = sl < e ? sl : e - 1;
+        c[u] = S.colidx[sc];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) a[u][k] = vals[k * nz + sc];
       }
-      a0 += vals[sl] * v0 + vals[nz + sl] * v1 + vals[2 * nz + sl] * v2;
-      a1 += vals[3 * nz + sl] * v0 + vals[4 * nz + sl] * v1 + vals[5 * nz + sl] * v2;
-      a2 += vals[6 * nz + sl] * v0 + vals[7 * nz + sl] * v1 + vals[8 * nz + sl] * v2;
+
+      T g[U][3];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        g[u][0] = z[3 * c[u]];
+        g[u][1] = z[3 * c[u] + 1];
+        g[u][2] = z[3 * c[u] + 2];
+        if (it) {
+          g[u][0] += tb * po[3 * c[u]];
+          g[u][1] += tb * po[3 * c[u] + 1];
+          g[u][2] += tb * po[3 * c[u] + 2];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {  // weight 1 (exact) or 0 for slots past the row's end
+        const T w = base + u * LPR < e ? (T)1 : (T)0;
+        a0 += w * (a[u][0] * g[u][0] + a[u][1] * g[u][1] + a[u][2] * g[u][2]);
+        a1 += w * (a[u][3] * g[u][0] + a[u][4] * g[u][1] + a[u][5] * g[u][2]);
+        a2 += w * (a[u][6] * g[u][0] + a[u][7] * g[u][1] + a[u][8] * g[u][2]);
+      }
     }
   }
 #pragma unroll
@@ -308,21 +331,47 @@ __global__ __launch_bounds__(64) void k_cg_update(const SysDesc* __restrict__ sd
 // even iteration.
 
 // acc = (K v)_row over this lane's share of the row's blocks, then summed
-// over the LPR lanes of the row (every lane of the row gets the sum).
+// over the LPR lanes of the row (every lane of the row gets the sum).  The
+// lane's blocks are taken in batches of U: all column indices and values of a
+// batch are loaded first (unconditionally: slots past the row's end reload its
+// last block and are weighted 0, so no branch splits the loads), then all gathers are
+// issued, so a batch costs two dependent memory latencies instead of two per
+// block.
 template <typename T, typename V, int LPR>
 __device__ __forceinline__ void row_product(const SysDesc& S, const V* __restrict__ v, int row, bool valid, int lane,
                                             V acc[3]) {
+  constexpr int U = LPR >= 16 ? 1 : 16 / LPR;
   acc[0] = acc[1] = acc[2] = (V)0;
   if (valid) {
     const T* vals = (const T*)S.vals;
     const size_t nz = S.nnzb;
     const int e = S.rowptr[row + 1];
-    for (int sl = S.rowptr[row] + lane; sl < e; sl += LPR) {
-      const int c = S.colidx[sl];
-      const V v0 = v[3 * c], v1 = v[3 * c + 1], v2 = v[3 * c + 2];
-      acc[0] += (V)vals[sl] * v0 + (V)vals[nz + sl] * v1 + (V)vals[2 * nz + sl] * v2;
-      acc[1] += (V)vals[3 * nz + sl] * v0 + (V)vals[4 * nz + sl] * v1 + (V)vals[5 * nz + sl] * v2;
-      acc[2] += (V)vals[6 * nz + sl] * v0 + (V)vals[7 * nz + sl] * v1 + (V)vals[8 * nz + sl] * v2;
+    for (int base = S.rowptr[row] + lane; base < e; base += U * LPR) {
+      int c[U];
+      T a[U][9];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {  // past the row's end: reload its last block, weight 0
+        const int sl = base + u * LPR;
+        const int sc = sl < e ? sl : e - 1;
+        c[u] = S.colidx[sc];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) a[u][k] = vals[k * nz + sc];
+      }
+
+      V g[U][3];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        g[u][0] = v[3 * c[u]];
+        g[u][1] = v[3 * c[u] + 1];
+        g[u][2] = v[3 * c[u] + 2];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {  // weight 1 (exact) or 0 for slots past the row's end
+        const V w = base + u * LPR < e ? (V)1 : (V)0;
+        acc[0] += w * ((V)a[u][0] * g[u][0] + (V)a[u][1] * g[u][1] + (V)a[u][2] * g[u][2]);
+        acc[1] += w * ((V)a[u][3] * g[u][0] + (V)a[u][4] * g[u][1] + (V)a[u][5] * g[u][2]);
+        acc[2] += w * ((V)a[u][6] * g[u][0] + (V)a[u][7] * g[u][1] + (V)a[u][8] * g[u][2]);
+      }
     }
   }
 #pragma unroll
