@@ -194,6 +194,16 @@ int mfs_character_destroy(mfs_character* ch);
 int mfs_character_footprint(const mfs_character* ch, size_t* resident_bytes,
                             size_t* workspace_bytes);
 
+/* External vertex forces (the f_ext term of the next-step extensions: a
+ * load b += f_ext on selected vertices, potential -f . x in E), used by
+ * every later solve and evaluation of this character until changed.
+ * vertices: count indices (repeats add up), forces: count x 3, host or
+ * device per memory_space; count = 0 removes all forces.  Synchronises the
+ * context's stream.  Errors: MFS_E_INVALID (index out of range, non-finite
+ * force), MFS_E_OOM. */
+int mfs_character_set_forces(mfs_character* ch, const int32_t* vertices, const double* forces,
+                             int64_t count, int32_t memory_space);
+
 /* Free the character's own solve workspace (workspace_bytes of device
  * memory), keeping its resident data and last solution.  A server then
  * lends it a workspace from its arena for each admitted frame; a later
@@ -381,8 +391,8 @@ int mfs_profile_read(mfs_context* ctx, mfs_profile* out, int32_t reset);
 /* At positions x (n x 3, caller order, host or device per memory_space) and
  * the given pose, with s = J x (the condensed stretch, sym(R_k^T F_k)):
  *   energy_out (1 double, host): E(x) = sum_k W_k Psi(S_k) + k_s/2 sum_p
- *       ||x_p - (R_h X_p + t_h)||^2 (+inf if a neo-Hookean S_k is not
- *       positive definite);
+ *       ||x_p - (R_h X_p + t_h)||^2 - f_ext . x (+inf if a neo-Hookean S_k
+ *       is not positive definite);
  *   grad_out (n x 3, same memory space as x, or NULL): grad E(x);
  *   stretch_out (m x 6, same space, or NULL): s_k = (S00,S11,S22,S12,S02,S01)
  *       in the caller's tet order;
@@ -391,6 +401,21 @@ int mfs_profile_read(mfs_context* ctx, mfs_profile* out, int32_t reset);
 int mfs_evaluate(mfs_character* ch, const double* handle_R, const double* handle_t,
                  const double* x, const double* v, int32_t memory_space,
                  double* energy_out, double* grad_out, double* stretch_out, double* Kv_out);
+
+/* Stress recovery (back-substitution of the stretch equations of Section 3):
+ * at positions x (n x 3, caller order) and the given pose, per tet k in the
+ * caller's tet order,
+ *   stress_out (m x 6, or NULL): P_k = dPsi/dS at S_k = sym(R_k^T F_k(x)),
+ *       stored (S00, S11, S22, S12, S02, S01);
+ *   multiplier_out (m x 9 row-major, or NULL): lambda_k = W_k R_k P_k, the
+ *       volume-weighted world-frame multiplier of the constraint F_k = R_k S_k
+ *       (the element's force on its vertex a is lambda_k n_a, n_a the rest
+ *       shape-function gradient).
+ * Buffers host or device per memory_space.  A neo-Hookean tet whose S_k is not
+ * positive definite gets NaN.  Uses the character's state buffers (its stored
+ * solution is replaced by x, as in mfs_evaluate). */
+int mfs_stress(mfs_character* ch, const double* handle_R, const double* handle_t, const double* x,
+               int32_t memory_space, double* stress_out, double* multiplier_out);
 
 /* Polar decomposition F = U P (U proper rotation, P symmetric) of `count`
  * 3x3 matrices by Higham's scaled Newton iteration, as the solver's warm

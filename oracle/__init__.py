@@ -22,13 +22,14 @@ from .mfem import (ARAP, COROT, NH, lame, vech, unvech, sym_basis, rest_shape,
                    shape_gradients, deformation_operator, rotation_operator,
                    mixed_operator, psi, dpsi, d2psi, stretch_gradient, stretch_hessian,
                    polar, polar_stretch, cluster_by_segments, pin_targets, Frame,
-                   solve_frame, interpolate_pose, energy, gradient, hessian, DegenerateElement)
+                   solve_frame, interpolate_pose, energy, gradient, hessian, stress,
+                   DegenerateElement)
 
 __all__ = [
     "ARAP", "COROT", "NH", "lame", "vech", "unvech", "sym_basis", "rest_shape",
     "shape_gradients", "deformation_operator", "rotation_operator", "mixed_operator",
     "psi", "dpsi", "d2psi", "stretch_gradient", "stretch_hessian", "polar",
     "polar_stretch", "cluster_by_segments", "pin_targets", "Frame", "solve_frame",
-    "interpolate_pose",
+    "interpolate_pose", "stress",
     "energy", "gradient", "hessian", "DegenerateElement",
 ]

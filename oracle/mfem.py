@@ -50,6 +50,11 @@ Readings taken where the paper is silent, garbled or inconsistent:
   R11 Stop after a fixed iteration count (predictor counts as iteration 1),
       or when max_v ||alpha dx_v|| <= step_tol * bbox_diag.
   R12 Load stepping for poses whose mixed phase stalls (see solve_frame).
+
+Extension beyond the paper's per-frame statement: external vertex forces
+f_ext (the local-perturbation experiment of Section 4) enter as the
+potential -f_ext . x, i.e. b += f_ext in the Newton system; problems carry
+them as ``force_vertex`` (indices, repeats add up) and ``force`` (k x 3).
 """
 
 import numpy as np
@@ -329,6 +334,11 @@ class Frame:
         self.ks = float(prob["pin_stiffness"])
         self.bbox_diag = float(prob["bbox_diag"])
         self.dof = (3 * self.T[:, :, None] + np.arange(3)).reshape(self.m, 12)
+        self.fext = np.zeros((self.n, 3))
+        fv = prob.get("force_vertex")
+        if fv is not None and len(fv):
+            np.add.at(self.fext, np.asarray(fv, dtype=np.int64),
+                      np.asarray(prob["force"], dtype=np.float64).reshape(-1, 3))
 
     def local(self, x):
         return np.asarray(x, dtype=np.float64).reshape(-1)[self.dof]
@@ -348,7 +358,8 @@ class Frame:
 
     def energy(self, x):
         r = self.pin_residual(x)
-        return float(self.element_energy(x).sum() + 0.5 * self.ks * (r * r).sum())
+        return float(self.element_energy(x).sum() + 0.5 * self.ks * (r * r).sum()
+                     - (self.fext * np.asarray(x).reshape(-1, 3)).sum())
 
     def feasible(self, x):
         return bool(np.all(np.isfinite(self.element_energy(x))))
@@ -372,7 +383,7 @@ class Frame:
         f = self._scatter((Jt @ (self.W[:, None] * g)[:, :, None])[:, :, 0])
         pin = np.zeros((self.n, 3))
         np.add.at(pin, self.pin_vertex, self.ks * self.pin_residual(x))
-        return f + pin.reshape(-1)
+        return f + pin.reshape(-1) - self.fext.reshape(-1)
 
     def hessian(self, s, clamp=True):
         """K = H_x + sum_k W_k J_k^T H_k J_k (eq. 12 left-hand side), CSR."""
@@ -387,6 +398,26 @@ class Frame:
         vals = np.concatenate([Kl.reshape(-1), np.full(len(pd), self.ks)])
         n3 = 3 * self.n
         return sp.coo_matrix((vals, (rows, cols)), shape=(n3, n3)).tocsr()
+
+
+def stress(prob, pose, x):
+    """Stress recovery (back-substitution of the stretch equations of
+    Section 3): per tet, P_k = dPsi/dS at S_k = sym(R_k^T F_k(x)) as a
+    6-vector (plain entries) and the volume-weighted world-frame multiplier
+    lambda_k = W_k R_k P_k (3 x 3) of the constraint F_k = R_k S_k; NaN for an
+    infeasible neo-Hookean tet."""
+    fr = Frame(prob, pose)
+    S = unvech(fr.stretch(x))
+    m = fr.m
+    P = np.full((m, 3, 3), np.nan)
+    ok = np.ones(m, dtype=bool)
+    nh = fr.model == NH
+    if np.any(nh):
+        ok[nh] = _spd(S[nh])
+    if np.any(ok):
+        P[ok] = dpsi(S[ok], fr.model[ok], fr.mu[ok], fr.lam[ok])
+    lam = fr.W[:, None, None] * np.einsum("kij,kjl->kil", fr.Rk, P)
+    return vech(P), lam
 
 
 def energy(prob, pose, x):

@@ -32,7 +32,8 @@ EXPORTED = ("mfs_default_opts", "mfs_status_string", "mfs_last_error", "mfs_cont
             "mfs_profile_enable", "mfs_profile_read", "mfs_context_get_tuning",
             "mfs_context_set_tuning", "mfs_character_release_workspace", "mfs_default_server_opts",
             "mfs_server_create", "mfs_server_destroy", "mfs_server_submit", "mfs_server_poll",
-            "mfs_server_wait", "mfs_server_get_info", "mfs_autotune")
+            "mfs_server_wait", "mfs_server_get_info", "mfs_autotune", "mfs_character_set_forces",
+            "mfs_stress")
 
 KERNEL_FAMILIES = ("warm_start", "element", "assemble", "spmv", "cg_update", "linesearch", "update",
                    "other")
@@ -142,6 +143,8 @@ def lib():
         "mfs_context_get_tuning": (ctypes.c_int, [c_vp, P(Tuning)]),
         "mfs_context_set_tuning": (ctypes.c_int, [c_vp, P(Tuning)]),
         "mfs_character_release_workspace": (ctypes.c_int, [c_vp]),
+        "mfs_character_set_forces": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_i32]),
+        "mfs_stress": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp]),
         "mfs_default_server_opts": (None, [P(ServerOpts)]),
         "mfs_server_create": (ctypes.c_int, [c_vp, P(ServerOpts), P(c_vp)]),
         "mfs_server_destroy": (ctypes.c_int, [c_vp]),
@@ -337,6 +340,15 @@ class Character:
         _check(lib().mfs_character_footprint(self.handle, ctypes.byref(r), ctypes.byref(w)))
         return r.value, w.value
 
+    def set_forces(self, vertices=None, forces=None):
+        """External vertex forces (count x 3) for later solves; None clears."""
+        if vertices is None or len(vertices) == 0:
+            _check(lib().mfs_character_set_forces(self.handle, None, None, 0, MEM_HOST))
+            return
+        v = _host(vertices, np.int32).reshape(-1)
+        f = _host(forces, np.float64).reshape(len(v), 3)
+        _check(lib().mfs_character_set_forces(self.handle, _ptr(v), _ptr(f), len(v), MEM_HOST))
+
     def release_workspace(self):
         """Free the solve workspace; a server lends one per admitted frame."""
         _check(lib().mfs_character_release_workspace(self.handle))
@@ -359,6 +371,15 @@ class Character:
         rc = _check(lib().mfs_solve_frame(self.handle, _ptr(R), _ptr(t), ctypes.byref(o), _ptr(out),
                                           ctypes.byref(st)))
         return out, st.as_dict(), rc
+
+    def stress(self, R, t, x):
+        """Per-tet stress P (m, 6) and world multiplier W R P (m, 3, 3) at x."""
+        R, t = self._pose(R, t)
+        x = _host(x, np.float64).reshape(self.n, 3)
+        P = np.empty((self.m, 6))
+        L = np.empty((self.m, 3, 3))
+        _check(lib().mfs_stress(self.handle, _ptr(R), _ptr(t), _ptr(x), MEM_HOST, _ptr(P), _ptr(L)))
+        return P, L
 
     def evaluate(self, R, t, x, v=None, want_grad=True, want_stretch=True):
         """Energy, gradient, stretches and K v at positions x (host arrays)."""

@@ -58,6 +58,30 @@ int PinnedBuf::reserve(size_t nbytes) {
   return MFS_OK;
 }
 
+UploadRing::~UploadRing() {
+  for (int k = 0; k < kChunks; ++k) {
+    if (in_flight[k]) (void)hipEventSynchronize(ev[k]);
+    if (ev[k]) (void)hipEventDestroy(ev[k]);
+  }
+}
+
+int UploadRing::upload(hipStream_t st, void* dst, const void* src, size_t bytes) {
+  if (!bytes) return MFS_OK;
+  const int k = next;
+  next = (next + 1) % kChunks;
+  if (!ev[k]) MFS_HIP(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming));
+  if (in_flight[k]) {
+    MFS_HIP(hipEventSynchronize(ev[k]));
+    in_flight[k] = false;
+  }
+  MFS_TRY(chunk[k].reserve(bytes));
+  std::memcpy(chunk[k].p, src, bytes);
+  MFS_HIP(hipMemcpyAsync(dst, chunk[k].p, bytes, hipMemcpyHostToDevice, st));
+  MFS_HIP(hipEventRecord(ev[k], st));
+  in_flight[k] = true;
+  return MFS_OK;
+}
+
 // Copy `count` elements from host or device memory into a host vector.
 template <class T>
 static int fetch(const T* src, size_t count, int mem, std::vector<T>& dst) {
@@ -541,6 +565,47 @@ extern "C" int mfs_character_destroy(mfs_character* ch) {
   if (!ch) return MFS_OK;
   if (ch->ctx) (void)hipSetDevice(ch->ctx->device);
   delete ch;
+  return MFS_OK;
+}
+
+extern "C" int mfs_character_set_forces(mfs_character* ch, const int32_t* vertices, const double* forces,
+                                        int64_t count, int32_t memory_space) {
+  clear_error();
+  if (!ch) return set_error(MFS_E_INVALID, "null character");
+  if (count < 0) return set_error(MFS_E_INVALID, "negative force count");
+  if (memory_space != MFS_MEM_HOST && memory_space != MFS_MEM_DEVICE)
+    return set_error(MFS_E_INVALID, "invalid memory space");
+  mfs_context* ctx = ch->ctx;
+  MFS_HIP(hipSetDevice(ctx->device));
+  MFS_HIP(hipStreamSynchronize(ctx->stream));  // no solve is reading the old forces
+  if (count == 0) {
+    ch->desc.fext = nullptr;
+    return MFS_OK;
+  }
+  if (!vertices || !forces) return set_error(MFS_E_INVALID, "null vertices or forces");
+  std::vector<int32_t> hv(count);
+  std::vector<double> hf(3 * (size_t)count);
+  if (memory_space == MFS_MEM_DEVICE) {
+    MFS_HIP(hipMemcpy(hv.data(), vertices, sizeof(int32_t) * count, hipMemcpyDeviceToHost));
+    MFS_HIP(hipMemcpy(hf.data(), forces, sizeof(double) * 3 * count, hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(hv.data(), vertices, sizeof(int32_t) * count);
+    std::memcpy(hf.data(), forces, sizeof(double) * 3 * count);
+  }
+  std::vector<int32_t> inv(ch->n);
+  for (int i = 0; i < ch->n; ++i) inv[ch->perm[i]] = i;
+  std::vector<double> f(3 * (size_t)ch->n, 0.0);
+  for (int64_t k = 0; k < count; ++k) {
+    if (hv[k] < 0 || hv[k] >= ch->n) return set_error(MFS_E_INVALID, "force %lld: vertex %d out of range", (long long)k, hv[k]);
+    for (int i = 0; i < 3; ++i) {
+      const double v = hf[3 * k + i];
+      if (!std::isfinite(v)) return set_error(MFS_E_INVALID, "force %lld is not finite", (long long)k);
+      f[3 * (size_t)inv[hv[k]] + i] += v;  // repeated vertices add up
+    }
+  }
+  if (!ch->fext.p) MFS_TRY(ch->fext.alloc(3 * sizeof(double) * (size_t)ch->n));
+  MFS_HIP(hipMemcpy(ch->fext.p, f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice));
+  ch->desc.fext = ch->fext.as<double>();
   return MFS_OK;
 }
 

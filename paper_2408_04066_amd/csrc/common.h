@@ -140,6 +140,7 @@ struct SysDesc {
   const int32_t* diag;     // n: slot of block (r, r)
   const int32_t* vpin_ptr; // n + 1
   const int32_t* vpin_h;   // pins grouped by vertex: their handles
+  const double* fext;      // 3n external vertex forces, or null (none)
   // per-frame rig
   const double* Rh;        // nh x 9
   const double* th;        // nh x 3

@@ -24,8 +24,7 @@
 namespace mfs {
 
 int upload_ctrl(mfs_context* ctx, int count) {
-  MFS_HIP(hipMemcpyAsync(ctx->ctrl.p, ctx->h_ctrl.p, count * sizeof(Ctrl), hipMemcpyHostToDevice, ctx->stream));
-  return MFS_OK;
+  return ctx->up.upload(ctx->stream, ctx->ctrl.p, ctx->h_ctrl.data(), count * sizeof(Ctrl));
 }
 
 int read_cg(mfs_context* ctx, int count, bool resolve) {
@@ -47,9 +46,9 @@ int build_tile_list(mfs_context* ctx, const std::vector<mfs_character*>& by_slot
                     TileSet* ts) {
   size_t total = 0;
   for (int i : ids) total += by_slot[i]->ntv + by_slot[i]->ntt + by_slot[i]->nts;
-  MFS_TRY(ctx->h_tiles.reserve(std::max<size_t>(total, 1) * sizeof(Tile)));
+  ctx->h_tiles.resize(std::max<size_t>(total, 1));
   MFS_TRY(ctx->tiles.reserve(std::max<size_t>(total, 1) * sizeof(Tile)));
-  Tile* h = ctx->h_tiles.as<Tile>();
+  Tile* h = ctx->h_tiles.data();
   size_t pos = 0;
   int counts[3] = {0, 0, 0};
   for (int kind = 0; kind < 3; ++kind) {
@@ -64,7 +63,7 @@ int build_tile_list(mfs_context* ctx, const std::vector<mfs_character*>& by_slot
       }
     }
   }
-  MFS_HIP(hipMemcpyAsync(ctx->tiles.p, h, pos * sizeof(Tile), hipMemcpyHostToDevice, ctx->stream));
+  MFS_TRY(ctx->up.upload(ctx->stream, ctx->tiles.p, h, pos * sizeof(Tile)));
   Tile* d = ctx->tiles.as<Tile>();
   ts->nv = counts[0];
   ts->nt = counts[1];
@@ -73,11 +72,7 @@ int build_tile_list(mfs_context* ctx, const std::vector<mfs_character*>& by_slot
   ts->dt = d + counts[0];
   ts->ds = d + counts[0] + counts[1];
   MFS_TRY(ctx->sys_ids.reserve(std::max<size_t>(ids.size(), 1) * sizeof(int32_t)));
-  MFS_TRY(ctx->h_stage.reserve(std::max<size_t>(ids.size(), 1) * sizeof(int32_t)));
-  std::memcpy(ctx->h_stage.p, ids.data(), ids.size() * sizeof(int32_t));
-  MFS_HIP(hipMemcpyAsync(ctx->sys_ids.p, ctx->h_stage.p, ids.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                         ctx->stream));
-  return MFS_OK;
+  return ctx->up.upload(ctx->stream, ctx->sys_ids.p, ids.data(), ids.size() * sizeof(int32_t));
 }
 
 // A run of PCG iterations captured once as a HIP graph per (tiles, sizes,
@@ -277,7 +272,7 @@ int Engine::restart_load_step(int i) {
   S.fresh = true;
   S.load_mixed = 0;
   S.E_known = false;
-  Ctrl& c = ctx_->h_ctrl.as<Ctrl>()[i];
+  Ctrl& c = ctx_->h_ctrl.data()[i];
   c.cg_g2prev = 0.0;
   c.cg_eta_min = 0.0;
   return MFS_OK;
@@ -306,13 +301,11 @@ int Engine::reserve(int n) {
   MFS_TRY(ctx_->ctrl.reserve(n * sizeof(Ctrl)));
   MFS_TRY(ctx_->red.reserve(n * P_COUNT * sizeof(double)));
   MFS_TRY(ctx_->cg.reserve(n * sizeof(CgState)));
-  MFS_TRY(ctx_->h_ctrl.reserve(n * sizeof(Ctrl)));
+  ctx_->h_ctrl.assign(n, Ctrl{});
   MFS_TRY(ctx_->h_red.reserve(n * P_COUNT * sizeof(double)));
   MFS_TRY(ctx_->h_cg.reserve(n * sizeof(CgState)));
   // arrival tickets start at zero (each kernel's last workgroup resets its own)
   MFS_HIP(hipMemsetAsync(ctx_->cg.p, 0, n * sizeof(CgState), ctx_->stream));
-  MFS_TRY(ctx_->h_desc.reserve(n * sizeof(SysDesc)));
-  std::memset(ctx_->h_ctrl.p, 0, n * sizeof(Ctrl));
   slot_.assign(n, SlotState());
   hd_.assign(n, SysDesc{});
   desc_dirty_ = true;
@@ -361,7 +354,7 @@ int Engine::attach(int i, mfs_character* ch, const double* R, const double* t) {
   d.red = ctx_->red.as<double>() + P_COUNT * i;
   d.cg = ctx_->cg.as<CgState>() + i;
   d.ctrl = ctx_->ctrl.as<Ctrl>() + i;
-  Ctrl& c = ctx_->h_ctrl.as<Ctrl>()[i];
+  Ctrl& c = ctx_->h_ctrl.data()[i];
   std::memset(&c, 0, sizeof c);
   c.cg_tol2 = o_.cg_tol * o_.cg_tol;
   c.cg_adaptive = o_.cg_adaptive ? 1 : 0;
@@ -383,8 +376,7 @@ int Engine::bind_workspace(int i, char* base) {
 int Engine::upload_desc() {
   if (!desc_dirty_) return MFS_OK;
   const int n = (int)slot_.size();
-  std::memcpy(ctx_->h_desc.p, hd_.data(), n * sizeof(SysDesc));
-  MFS_HIP(hipMemcpyAsync(ctx_->desc.p, ctx_->h_desc.p, n * sizeof(SysDesc), hipMemcpyHostToDevice, ctx_->stream));
+  MFS_TRY(ctx_->up.upload(ctx_->stream, ctx_->desc.p, hd_.data(), n * sizeof(SysDesc)));
   desc_dirty_ = false;
   return MFS_OK;
 }
@@ -417,7 +409,7 @@ int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* fai
   const SysDesc* dsd = ctx->desc.as<SysDesc>();
   const int n = (int)slot_.size();
   const CgState* hg = ctx->h_cg.as<CgState>();
-  const Ctrl* hc = ctx->h_ctrl.as<Ctrl>();
+  const Ctrl* hc = ctx->h_ctrl.data();
   int cit = 0;
   int chunk = ctx->cg_first_run;
   for (int i : act) {
@@ -533,7 +525,7 @@ int Engine::linesearch(const std::vector<int>& act) {
   hipStream_t st = ctx->stream;
   const SysDesc* dsd = ctx->desc.as<SysDesc>();
   const Ctrl* dctrl = ctx->ctrl.as<Ctrl>();
-  Ctrl* hc = ctx->h_ctrl.as<Ctrl>();
+  Ctrl* hc = ctx->h_ctrl.data();
   const double* hr = ctx->h_red.as<double>();
   const int n = (int)slot_.size();
   // first pass: Newton slots evaluate E at {0, 1, 1/2, 1/4, 1/8}; mixed
@@ -623,7 +615,7 @@ int Engine::step() {
   const int n = (int)slot_.size();
   const SysDesc* dsd = ctx->desc.as<SysDesc>();
   const Ctrl* dctrl = ctx->ctrl.as<Ctrl>();
-  Ctrl* hc = ctx->h_ctrl.as<Ctrl>();
+  Ctrl* hc = ctx->h_ctrl.data();
   const double* hr = ctx->h_red.as<double>();
   for (int i = 0; i < n; ++i)
     if (slot_[i].used && !slot_[i].done && !hd_[i].blk)
@@ -781,7 +773,7 @@ int Engine::finish_energies() {
     if (slot_[i].used && slot_[i].done && !slot_[i].E_known) need.push_back(i);
   if (need.empty()) return MFS_OK;
   mfs_context* ctx = ctx_;
-  Ctrl* hc = ctx->h_ctrl.as<Ctrl>();
+  Ctrl* hc = ctx->h_ctrl.data();
   MFS_TRY(upload_desc());
   MFS_TRY(tiles_for(need));
   for (int i : need) {

@@ -63,6 +63,25 @@ struct PinnedBuf {
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Pinned staging for host-to-device uploads on one stream.  A copy from
+// pinned memory reads its source when it executes, not when it is enqueued,
+// so a chunk is rewritten only after the copy that last read it has
+// completed (an event recorded behind that copy).  The caller's source may be
+// reused as soon as upload() returns.  Eight chunks let several uploads be in
+// flight without waiting.
+struct UploadRing {
+  static constexpr int kChunks = 8;
+  PinnedBuf chunk[kChunks];
+  hipEvent_t ev[kChunks] = {};
+  bool in_flight[kChunks] = {};
+  int next = 0;
+  UploadRing() = default;
+  UploadRing(const UploadRing&) = delete;
+  UploadRing& operator=(const UploadRing&) = delete;
+  ~UploadRing();
+  int upload(hipStream_t st, void* dst, const void* src, size_t bytes);
+};
+
 }  // namespace mfs
 
 namespace mfs {
@@ -98,7 +117,10 @@ struct mfs_context {
   std::vector<mfs::CgGraph> graphs;
   // batch scratch
   mfs::DevBuf desc, ctrl, red, cg, tiles, sys_ids, tmp;
-  mfs::PinnedBuf h_ctrl, h_red, h_cg, h_tiles, h_stage, h_desc;
+  mfs::PinnedBuf h_red, h_cg;              // device-to-host reads (synchronised at once)
+  std::vector<mfs::Ctrl> h_ctrl;           // host copies of the per-slot controls
+  std::vector<mfs::Tile> h_tiles;          // host copy of the current tile list
+  mfs::UploadRing up;                      // every host-to-device upload of the stream
   // HIP-event profiler (mfs_profile_enable)
   int prof_stride = 0;
   double prof_ms[MFS_K_FAMILIES] = {};
@@ -130,6 +152,7 @@ struct mfs_character {
       tperm_d;
   // per-frame rig and solver state
   mfs::DevBuf Rh, th, x, xb, s;
+  mfs::DevBuf fext;  // external vertex forces (internal order), allocated on first use
   // per-frame workspace (element records, BSR values, PCG vectors, partials):
   // one allocation carved by workspace_layout; empty after
   // mfs_character_release_workspace until a standalone solve needs it again

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_element(const SysDesc* __restrict__ 
 
 // ---------------------------------------------------------------------------
 // Assembly of the condensed system (eq. 12 read as a Newton increment):
-//   K = k_s P^T P + sum_k W_k J_k^T H_k J_k,  b = -grad C - sum_k W_k J_k^T g_k,
+//   K = k_s P^T P + sum_k W_k J_k^T H_k J_k,  b = -grad C - sum_k W_k J_k^T g_k + f_ext,
 // gathered per 3x3 block slot from the slot's list of (tet, a, b)
 // contributions (no atomics); each contribution is one block of the tet's
 // record (transposed when a > b).  The diagonal slot of vertex r also adds
@@ -200,7 +200,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble(const SysDesc* __restrict__
     acc[4] += kc;
     acc[8] += kc;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) S.b[3 * row + i] = -f[i] - (kc * S.x[3 * row + i] - S.ks * ys[i]);
+    for (int i = 0; i < 3; ++i)
+      S.b[3 * row + i] = -f[i] - (kc * S.x[3 * row + i] - S.ks * ys[i]) + (S.fext ? S.fext[3 * row + i] : 0.0);
     // inverse of the symmetrised diagonal block
     double d6[6] = {acc[0], acc[4], acc[8], 0.5 * (acc[5] + acc[7]), 0.5 * (acc[2] + acc[6]),
                     0.5 * (acc[1] + acc[3])};
@@ -333,6 +334,12 @@ __global__ __launch_bounds__(64) void k_linesearch_verts(const SysDesc* __restri
         pe[j] += 0.5 * S.ks * e2;
       }
     }
+    if (S.fext) {  // potential of the external forces, -f . x
+      const double f0 = S.fext[3 * r], f1 = S.fext[3 * r + 1], f2 = S.fext[3 * r + 2];
+#pragma unroll
+      for (int j = 0; j < kNumTrials; ++j)
+        pe[j] -= f0 * (x[0] + C.trials[j] * d[0]) + f1 * (x[1] + C.trials[j] * d[1]) + f2 * (x[2] + C.trials[j] * d[2]);
+    }
   }
   const double ss = wave_sum(slope);
   const double dm = wave_max(dmax);
@@ -402,6 +409,57 @@ __global__ __launch_bounds__(64) void k_finalize(const SysDesc* __restrict__ sd,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Stress recovery at positions x (FP64): per tet, the stress P = dPsi/dS at
+// S = sym(R^T F(x)) and the volume-weighted world-frame multiplier
+// lambda = W R P of the constraint F = R S (Section 3: at a solution the
+// stretch equations give W dPsi/ds = [R]^T lambda, and the element's vertex
+// forces are lambda n_a).  Written in the caller's tet order; infeasible
+// neo-Hookean elements give NaN.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_stress(const SysDesc* __restrict__ sd, const int32_t* __restrict__ tperm,
+                                                   double* __restrict__ P6, double* __restrict__ L9) {
+  const SysDesc& S = sd[0];
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= S.m) return;
+  const int4 tv = S.tets[k];
+  const int vi[4] = {tv.x, tv.y, tv.z, tv.w};
+  double n[4][3], xv[4][3];
+  load_grads(S.G, S.m, k, n);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) xv[a][i] = S.x[3 * vi[a] + i];
+  double F[9], R[9], sx[6];
+  deformation_gradient(xv, n, F);
+  const int info = S.info[k];
+  const int model = info >> 16;
+  load_rot(S.Rh, info & 0xffff, R);
+  rotated_stretch(R, F, sx);
+  const bool ok = model != kNeoHookean || sym_spd(sx);
+  double WP[6] = {0, 0, 0, 0, 0, 0}, T[6], c[4];
+  if (ok) element_state(model, S.wmu[k], S.wlam[k], sx, sx, WP, T, c);
+  // W = |det Dm| / 6 = 1 / (6 |det G|), G = Dm^-1 with rows n_1..n_3
+  const double Gm[9] = {n[1][0], n[1][1], n[1][2], n[2][0], n[2][1], n[2][2], n[3][0], n[3][1], n[3][2]};
+  const double W = 1.0 / (6.0 * fabs(det3(Gm)));
+  const int o = tperm[k];
+  const double nan = __builtin_nan("");
+  if (P6) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) P6[6 * (size_t)o + i] = ok ? WP[i] / W : nan;
+  }
+  if (L9) {
+    double Pf[9];
+    sym_full(WP, Pf);  // W P
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        L9[9 * (size_t)o + 3 * i + j] =
+            ok ? R[3 * i] * Pf[j] + R[3 * i + 1] * Pf[3 + j] + R[3 * i + 2] * Pf[6 + j] : nan;
+  }
+}
+
 // ---- launchers ----
 void launch_warm_start(hipStream_t st, const SysDesc* sd, const Tile* tiles, int ntiles, int fp32) {
   if (ntiles) MFS_LAUNCH(k_warm_start, dim3(ntiles), dim3(kBlock), 0, st, sd, tiles, ntiles, fp32);
@@ -429,6 +487,9 @@ void launch_update(hipStream_t st, const SysDesc* sd, const Ctrl* ctrl, const Ti
                    int ntv) {
   if (ntt) MFS_LAUNCH(k_update_s, dim3(ntt), dim3(kBlock), 0, st, sd, ctrl, tt, ntt);
   if (ntv) MFS_LAUNCH(k_update_x, dim3(ntv), dim3(64), 0, st, sd, ctrl, tv, ntv);
+}
+void launch_stress(hipStream_t st, const SysDesc* sd, int m, const int32_t* tperm, double* P6, double* L9) {
+  if (m > 0) MFS_LAUNCH(k_stress, dim3((m + kBlock - 1) / kBlock), dim3(kBlock), 0, st, sd, tperm, P6, L9);
 }
 void launch_finalize(hipStream_t st, const SysDesc* sd, const int32_t* sys_ids, int nsys) {
   if (nsys) MFS_LAUNCH(k_finalize, dim3(nsys), dim3(64), 0, st, sd, sys_ids);

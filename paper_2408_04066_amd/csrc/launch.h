@@ -52,6 +52,9 @@ void launch_linesearch(hipStream_t st, const SysDesc* sd, const Ctrl* ctrl, cons
                        int ntv);
 void launch_update(hipStream_t st, const SysDesc* sd, const Ctrl* ctrl, const Tile* tt, int ntt, const Tile* tv,
                    int ntv);
+// per-tet stress and multiplier at the descriptor's positions (system 0), in
+// the caller's tet order (tperm: internal -> caller)
+void launch_stress(hipStream_t st, const SysDesc* sd, int m, const int32_t* tperm, double* P6, double* L9);
 void launch_finalize(hipStream_t st, const SysDesc* sd, const int32_t* sys_ids, int nsys);
 
 // PCG

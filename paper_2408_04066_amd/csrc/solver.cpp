@@ -51,9 +51,8 @@ int check_pose(const mfs_character* ch, const double* R, const double* t) {
 
 int upload_pose(mfs_character* ch, const double* R, const double* t) {
   hipStream_t st = ch->ctx->stream;
-  MFS_HIP(hipMemcpyAsync(ch->Rh.p, R, 9 * sizeof(double) * ch->nh, hipMemcpyHostToDevice, st));
-  MFS_HIP(hipMemcpyAsync(ch->th.p, t, 3 * sizeof(double) * ch->nh, hipMemcpyHostToDevice, st));
-  return MFS_OK;
+  MFS_TRY(ch->ctx->up.upload(st, ch->Rh.p, R, 9 * sizeof(double) * ch->nh));
+  return ch->ctx->up.upload(st, ch->th.p, t, 3 * sizeof(double) * ch->nh);
 }
 
 int solve_systems(mfs_context* ctx, int count, mfs_character* const* chars, const double* const* R,
@@ -125,14 +124,14 @@ extern "C" int mfs_evaluate(mfs_character* ch, const double* handle_R, const dou
   MFS_TRY(ctx->ctrl.reserve(sizeof(Ctrl)));
   MFS_TRY(ctx->red.reserve(P_COUNT * sizeof(double)));
   MFS_TRY(ctx->cg.reserve(sizeof(CgState)));
-  MFS_TRY(ctx->h_ctrl.reserve(sizeof(Ctrl)));
+  if (ctx->h_ctrl.empty()) ctx->h_ctrl.resize(1);
   MFS_TRY(ctx->h_red.reserve(P_COUNT * sizeof(double)));
   MFS_HIP(hipStreamSynchronize(st));
   SysDesc hd = ch->desc;
   hd.red = ctx->red.as<double>();
   hd.cg = ctx->cg.as<CgState>();
   hd.ctrl = ctx->ctrl.as<Ctrl>();
-  MFS_HIP(hipMemcpyAsync(ctx->desc.p, &hd, sizeof(SysDesc), hipMemcpyHostToDevice, st));
+  MFS_TRY(ctx->up.upload(st, ctx->desc.p, &hd, sizeof(SysDesc)));
   MFS_TRY(upload_pose(ch, handle_R, handle_t));
   double* tmp = ctx->tmp.as<double>();
   const double* xs = x;
@@ -144,7 +143,7 @@ extern "C" int mfs_evaluate(mfs_character* ch, const double* handle_R, const dou
   ch->has_solution = false;
   TileSet ts;
   MFS_TRY(build_tile_list(ctx, std::vector<mfs_character*>{ch}, std::vector<int>{0}, &ts));
-  Ctrl* hc = ctx->h_ctrl.as<Ctrl>();
+  Ctrl* hc = ctx->h_ctrl.data();
   std::memset(hc, 0, sizeof(Ctrl));
   hc->phase = 1;
   MFS_TRY(upload_ctrl(ctx, 1));
@@ -185,5 +184,44 @@ extern "C" int mfs_evaluate(mfs_character* ch, const double* handle_R, const dou
     const double* rd = ctx->h_red.as<double>();
     *energy_out = rd[P_INF0] > 0.0 ? INFINITY : rd[P_E0] + rd[P_PIN0];
   }
+  return MFS_OK;
+}
+
+extern "C" int mfs_stress(mfs_character* ch, const double* handle_R, const double* handle_t, const double* x,
+                          int32_t memory_space, double* stress_out, double* multiplier_out) {
+  clear_error();
+  if (!ch || !x) return set_error(MFS_E_INVALID, "null character or positions");
+  if (memory_space != MFS_MEM_HOST && memory_space != MFS_MEM_DEVICE)
+    return set_error(MFS_E_INVALID, "invalid memory space");
+  if (!stress_out && !multiplier_out) return MFS_OK;
+  mfs_context* ctx = ch->ctx;
+  MFS_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  MFS_TRY(check_pose(ch, handle_R, handle_t));
+  const bool host = memory_space == MFS_MEM_HOST;
+  const size_t n3 = 3 * sizeof(double) * (size_t)ch->n;
+  const size_t m6 = 6 * sizeof(double) * (size_t)ch->m, m9 = 9 * sizeof(double) * (size_t)ch->m;
+  MFS_TRY(ctx->tmp.reserve(std::max(n3, m6 + m9)));
+  MFS_TRY(ctx->desc.reserve(sizeof(SysDesc)));
+  MFS_HIP(hipStreamSynchronize(st));
+  MFS_TRY(ctx->up.upload(st, ctx->desc.p, &ch->desc, sizeof(SysDesc)));
+  MFS_TRY(upload_pose(ch, handle_R, handle_t));
+  double* tmp = ctx->tmp.as<double>();
+  const double* xs = x;
+  if (host) {
+    MFS_HIP(hipMemcpyAsync(tmp, x, n3, hipMemcpyHostToDevice, st));
+    xs = tmp;
+  }
+  launch_gather_rows(st, xs, ch->perm_d.as<int32_t>(), ch->n, 3, ch->x.as<double>());
+  ch->has_solution = false;
+  double* P6 = stress_out ? (host ? tmp : stress_out) : nullptr;
+  double* L9 = multiplier_out ? (host ? tmp + 6 * (size_t)ch->m : multiplier_out) : nullptr;
+  launch_stress(st, ctx->desc.as<SysDesc>(), ch->m, ch->tperm_d.as<int32_t>(), P6, L9);
+  MFS_HIP(hipGetLastError());
+  if (host) {
+    if (stress_out) MFS_HIP(hipMemcpyAsync(stress_out, P6, m6, hipMemcpyDeviceToHost, st));
+    if (multiplier_out) MFS_HIP(hipMemcpyAsync(multiplier_out, L9, m9, hipMemcpyDeviceToHost, st));
+  }
+  MFS_HIP(hipStreamSynchronize(st));
   return MFS_OK;
 }

@@ -322,3 +322,77 @@ def test_pipelined_pcg(ctx):
         ch.close()
     finally:
         ctx.set_tuning(**base)
+
+
+def test_external_forces(ctx):
+    """External vertex forces (mfs_character_set_forces): E, grad E at a
+    perturbed state within 1e-12 relative of the oracle, FP64 frames within
+    1e-9 * bbox and FP32 + refinement within 1e-7 * bbox of the oracle's
+    solution with the same forces; clearing the forces restores the plain
+    frame."""
+    mfs = _mfs()
+    rng = np.random.default_rng(77)
+    cases = [(beam(), None), (_small_humanoid(21, 4000, 15), 22)]
+    for prob, seed in cases:
+        pose = beam_pose(prob) if seed is None else random_pose(prob, seed)
+        n = len(prob["X"])
+        fv = rng.choice(n, 12, replace=False).astype(np.int32)
+        fv = np.concatenate([fv, fv[:3]])  # repeats add up
+        ff = rng.normal(scale=5e-4 * float(np.max(prob["youngs"])) * prob["bbox_diag"] ** 2 / n, size=(len(fv), 3))
+        pf = dict(prob, force_vertex=fv, force=ff)
+        ch = mfs.Character(ctx, prob)
+        ch.set_forces(fv, ff)
+        _say(f"forces: {prob['name']} ({len(fv)} forces)")
+        fr = oracle.Frame(pf, pose)
+        x = oracle.solve_frame(pf, pose, iterations=1, frame=fr)["x"].reshape(n, 3)
+        x = x + rng.normal(scale=1e-5 * prob["bbox_diag"], size=(n, 3))
+        assert fr.feasible(x.reshape(-1))
+        ev = ch.evaluate(*pose, x)
+        assert abs(ev["energy"] - fr.energy(x)) <= 1e-12 * abs(fr.energy(x))
+        g = fr.gradient(x).reshape(-1, 3)
+        assert np.max(np.abs(ev["grad"] - g)) <= 1e-12 * np.max(np.abs(g))
+        ref = oracle.solve_frame(pf, pose, step_tol=1e-12)
+        assert ref["status"] == "ok"
+        x64, st, rc = ch.solve(*pose, precision=mfs.FP64, step_tol=1e-10, cg_tol=1e-10, max_newton=60)
+        _say(f"  FP64 stats {st} err/bbox={_err(x64, ref['x'], prob):.3e}")
+        assert rc == 0 and _err(x64, ref["x"], prob) <= 1e-9
+        x32, st, rc = ch.solve(*pose, precision=mfs.FP32_REFINED, step_tol=1e-9, cg_tol=1e-5, max_newton=60)
+        assert rc == 0 and _err(x32, ref["x"], prob) <= 1e-7
+        plain = oracle.solve_frame(prob, pose, step_tol=1e-12)
+        assert _err(ref["x"], plain["x"], prob) > 1e-6  # the forces matter
+        ch.set_forces(None)
+        x0, _, rc = ch.solve(*pose, precision=mfs.FP64, step_tol=1e-10, cg_tol=1e-10, max_newton=60)
+        assert rc == 0 and _err(x0, plain["x"], prob) <= 1e-9
+        ch.close()
+
+
+def test_stress_matches_oracle(ctx):
+    """Stress recovery (mfs_stress): P_k and lambda_k = W_k R_k P_k within a
+    relative 1e-12 of the oracle's on a mixed-material humanoid near a solved
+    frame; an inverted neo-Hookean tet gives NaN in both outputs."""
+    mfs = _mfs()
+    prob = _small_humanoid(31, 4000, 12)
+    prob["model"] = np.array([(ARAP, COROT, NH)[k % 3] for k in range(len(prob["T"]))], dtype=np.int32)
+    pose = random_pose(prob, 32, amp_deg=25.0)
+    rng = np.random.default_rng(33)
+    x = oracle.solve_frame(prob, pose, iterations=4)["x"].reshape(-1, 3)
+    x = x + 1e-4 * prob["bbox_diag"] * rng.normal(size=x.shape)
+    fr = oracle.Frame(prob, pose)
+    assert fr.feasible(x.reshape(-1))
+    _say(f"stress: n={fr.n} m={fr.m}")
+    ch = mfs.Character(ctx, prob)
+    P, L = ch.stress(*pose, x)
+    Pr, Lr = oracle.stress(prob, pose, x)
+    assert np.max(np.abs(P - Pr)) <= 1e-12 * np.max(np.abs(Pr))
+    assert np.max(np.abs(L - Lr)) <= 1e-12 * np.max(np.abs(Lr))
+    k = int(np.flatnonzero(fr.model == NH)[0])
+    a, b = prob["T"][k][:2]
+    xb = x.copy()
+    xb[[a, b]] = xb[[b, a]]
+    Pb, Lb = ch.stress(*pose, xb)
+    Pbr, _ = oracle.stress(prob, pose, xb)
+    bad = np.isnan(Pbr[:, 0])
+    assert bad[k] and np.array_equal(np.isnan(Pb[:, 0]), bad) and np.all(np.isnan(Lb[bad]))
+    ok = ~bad
+    assert np.max(np.abs(Pb[ok] - Pbr[ok])) <= 1e-12 * np.max(np.abs(Pbr[ok]))
+    ch.close()
