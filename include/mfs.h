@@ -169,6 +169,13 @@ typedef struct mfs_tuning {
                                  tiles are folded by every workgroup of the next kernel
                                  (no fences); larger systems fold them in the last workgroup
                                  to finish (arrival ticket with a release fence) */
+  int32_t pcg_persistent;     /* 1: a pipelined PCG whose workgroups (one per 64-row tile of
+                                 every system in the batch, the tile's matrix rows held in
+                                 LDS) all fit on the device at once runs as one cooperative
+                                 launch with a barrier per iteration instead of one launch
+                                 per iteration; the iterates are the same bitwise.  Default
+                                 0: it pays off for small systems, where the launch per
+                                 iteration dominates (the autotuner tries it) */
 } mfs_tuning;
 
 int mfs_context_get_tuning(const mfs_context* ctx, mfs_tuning* out);
@@ -251,7 +258,8 @@ int mfs_solve_batch(mfs_context* ctx, int32_t count, mfs_character* const* chars
 
 #define MFS_AUTOTUNE_FORCE 1  /* time the candidates even when a cached choice exists */
 
-/* Choose the PCG launch schedule (SpMV lanes per row, PCG iterations per
+/* Choose the PCG launch schedule (PCG form: two-kernel, pipelined, or
+ * pipelined in one persistent launch; SpMV lanes per row, PCG iterations per
  * graph, first convergence check, shortest run between checks) for a batch
  * like this one and apply it to the context.  Each candidate solves the
  * given frames (as mfs_solve_batch with `opts`, but from the rest shape and

@@ -167,6 +167,7 @@ extern "C" int mfs_context_get_tuning(const mfs_context* ctx, mfs_tuning* out) {
   out->max_run = ctx->cg_max_run;
   out->pcg_pipelined = ctx->pipelined ? 1 : 0;
   out->allread_max_tiles = ctx->allread_tiles;
+  out->pcg_persistent = ctx->persistent ? 1 : 0;
   return MFS_OK;
 }
 
@@ -181,6 +182,8 @@ extern "C" int mfs_context_set_tuning(mfs_context* ctx, const mfs_tuning* t) {
     return set_error(MFS_E_INVALID, "invalid PCG run bounds");
   if (t->pcg_pipelined != 0 && t->pcg_pipelined != 1) return set_error(MFS_E_INVALID, "pcg_pipelined must be 0 or 1");
   if (t->allread_max_tiles < 0) return set_error(MFS_E_INVALID, "allread_max_tiles must be >= 0");
+  if (t->pcg_persistent != 0 && t->pcg_persistent != 1)
+    return set_error(MFS_E_INVALID, "pcg_persistent must be 0 or 1");
   MFS_HIP(hipSetDevice(ctx->device));
   MFS_HIP(hipStreamSynchronize(ctx->stream));
   for (const CgGraph& g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
@@ -193,5 +196,6 @@ extern "C" int mfs_context_set_tuning(mfs_context* ctx, const mfs_tuning* t) {
   ctx->cg_max_run = t->max_run;
   ctx->pipelined = t->pcg_pipelined != 0;
   ctx->allread_tiles = t->allread_max_tiles;
+  ctx->persistent = t->pcg_persistent != 0;
   return MFS_OK;
 }

@@ -51,9 +51,9 @@ std::vector<Entry> read_cache(const char* path) {
   if (!f) return out;
   char arch[128];
   Entry e{};
-  while (std::fscanf(f, "%127s %d %d %d %d %d %d %d %d %d %lf", arch, &e.size_class, &e.t.pcg_lanes_per_row,
+  while (std::fscanf(f, "%127s %d %d %d %d %d %d %d %d %d %d %lf", arch, &e.size_class, &e.t.pcg_lanes_per_row,
                      &e.t.use_graphs, &e.t.graph_iterations, &e.t.first_check, &e.t.min_run, &e.t.max_run,
-                     &e.t.pcg_pipelined, &e.t.allread_max_tiles, &e.ms) == 11) {
+                     &e.t.pcg_pipelined, &e.t.allread_max_tiles, &e.t.pcg_persistent, &e.ms) == 12) {
     e.arch = arch;
     out.push_back(e);
   }
@@ -66,9 +66,9 @@ int write_cache(const char* path, const std::vector<Entry>& entries) {
   FILE* f = std::fopen(tmp.c_str(), "w");
   if (!f) return set_error(MFS_E_INVALID, "cannot write tuning cache %s", tmp.c_str());
   for (const Entry& e : entries)
-    std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %.6f\n", e.arch.c_str(), e.size_class, e.t.pcg_lanes_per_row,
+    std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %.6f\n", e.arch.c_str(), e.size_class, e.t.pcg_lanes_per_row,
                  e.t.use_graphs, e.t.graph_iterations, e.t.first_check, e.t.min_run, e.t.max_run,
-                 e.t.pcg_pipelined, e.t.allread_max_tiles, e.ms);
+                 e.t.pcg_pipelined, e.t.allread_max_tiles, e.t.pcg_persistent, e.ms);
   std::fclose(f);
   if (std::rename(tmp.c_str(), path) != 0) return set_error(MFS_E_INVALID, "cannot replace tuning cache %s", path);
   return MFS_OK;
@@ -159,6 +159,7 @@ extern "C" int mfs_autotune(mfs_context* ctx, int32_t count, mfs_character* cons
   mfs_tuning win = base;
   win.use_graphs = 1;
   win.pcg_pipelined = 0;
+  win.pcg_persistent = 0;
   double win_ms = INFINITY;
   {
     double ms;
@@ -170,13 +171,15 @@ extern "C" int mfs_autotune(mfs_context* ctx, int32_t count, mfs_character* cons
     win_ms = ms;
   }
   // stage 1: PCG form x lanes per row x graph length (the pipelined form
-  // only where it applies, FP32 solves)
-  const int forms = o.precision == MFS_FP32_REFINED ? 2 : 1;
-  for (int pipe = 0; pipe < forms; ++pipe)
+  // only where it applies, FP32 solves; its persistent launch has no graphs)
+  const int forms = o.precision == MFS_FP32_REFINED ? 3 : 1;
+  for (int form = 0; form < forms; ++form)
   for (int lpr : {2, 4, 8})
     for (int gi : {4, 8, 16}) {
+      if (form == 2 && gi != 8) continue;
       mfs_tuning t = win;
-      t.pcg_pipelined = pipe;
+      t.pcg_pipelined = form > 0 ? 1 : 0;
+      t.pcg_persistent = form == 2 ? 1 : 0;
       t.pcg_lanes_per_row = lpr;
       t.graph_iterations = gi;
       double ms;

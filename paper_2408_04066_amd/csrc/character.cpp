@@ -478,6 +478,9 @@ extern "C" int mfs_character_create(mfs_context* ctx, const mfs_mesh_desc* d, mf
   MFS_TRY(upload(ch->info, info.data(), (size_t)m));
   MFS_TRY(upload(ch->X, Xn.data(), 3 * (size_t)n));
   MFS_TRY(upload(ch->rowptr, rowptr.data(), (size_t)n + 1));
+  ch->max_tile_blocks = 0;
+  for (int b = 0; b < n; b += kVTile)
+    ch->max_tile_blocks = std::max(ch->max_tile_blocks, rowptr[std::min(n, b + kVTile)] - rowptr[b]);
   MFS_TRY(upload(ch->colidx, colidx.data(), (size_t)nnzb));
   MFS_TRY(upload(ch->slot_ptr, slot_ptr.data(), (size_t)nnzb + 1));
   MFS_TRY(upload(ch->contrib, contrib.data(), 16 * (size_t)m));

@@ -77,6 +77,8 @@ struct CgState {
   double a_prev[2];     // alpha of the iterations of each parity
   double g_prev[2];     // gamma of the iterations of each parity
   uint32_t arrive_pipe; // arrival ticket of the pipelined kernels
+  uint32_t bar;         // persistent form: barrier arrivals of this solve
+  int32_t abort;        // persistent form: set when a barrier wait timed out
   int32_t pad1;
 };
 
@@ -87,7 +89,7 @@ struct Ctrl {
   double alpha;      // accepted step length (0 = no update)
   double cg_tol2;    // squared relative PCG tolerance (floor when adaptive)
   int32_t cg_adaptive;  // 1: Eisenstat-Walker forcing on top of the floor
-  int32_t pad;
+  int32_t cg_cap;       // persistent PCG: iteration cap of this solve
   double cg_g2prev;  // |g|^2 of the previous Newton step (0: first step)
   double cg_eta_min; // safeguard lower bound on the forcing term
   double trials[kNumTrials];  // step lengths evaluated by the energy pass
@@ -221,9 +223,17 @@ __device__ __forceinline__ double block_max(double v, double* lds4) {
 // Sum of one partial plane over a system's tiles in a fixed order: lane l
 // adds tiles l, l + 64, ... in sequence, then the wave butterfly.  Every lane
 // of every wave returns the same value, independent of which workgroup asks.
+// The loads of four terms are issued before their additions.
 __device__ __forceinline__ double sys_sum(const double* plane, int count) {
   double acc = 0.0;
-  for (int i = threadIdx.x & 63; i < count; i += 64) acc += plane[i];
+  for (int i0 = threadIdx.x & 63; i0 < count; i0 += 256) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = plane[i0 + 64 * u < count ? i0 + 64 * u : i0];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + 64 * u < count) acc += v[u];
+  }
   return wave_sum(acc);
 }
 
@@ -256,7 +266,14 @@ __device__ __forceinline__ double coherent_sum(const double* plane, int count) {
 
 __device__ __forceinline__ double sys_max(const double* plane, int count) {
   double acc = 0.0;
-  for (int i = threadIdx.x & 63; i < count; i += 64) acc = fmax(acc, plane[i]);
+  for (int i0 = threadIdx.x & 63; i0 < count; i0 += 256) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = plane[i0 + 64 * u < count ? i0 + 64 * u : i0];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + 64 * u < count) acc = fmax(acc, v[u]);
+  }
   return wave_max(acc);
 }
 

@@ -457,6 +457,55 @@ int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* fai
     ProfScope ps(ctx, MFS_K_OTHER);
     launch_pcg_start(ctx->stream, dsd, ts_.dv, ts_.nv, fp32, ctx->lpr, one);
   }
+  // Persistent form: when the device holds every workgroup of the set at
+  // once, the whole solve is one cooperative launch that stops each system
+  // at its convergence, breakdown or cap (Ctrl::cg_cap) by itself.
+  if (pipe && ctx->persistent) {
+    int maxb = 0;
+    for (int i : act) maxb = std::max(maxb, slot_[i].ch->max_tile_blocks);
+    const size_t lds = pcg_persist_lds(maxb);
+    if (ctx->persist_lpr != ctx->lpr || ctx->persist_lds != lds) {
+      ctx->persist_capacity = pcg_persist_capacity(ctx->lpr, lds);
+      ctx->persist_lpr = ctx->lpr;
+      ctx->persist_lds = lds;
+    }
+    if (ts_.nv <= ctx->persist_capacity) {
+      constexpr int kPersistTag = -2;
+      {
+        ProfScope ps(ctx, MFS_K_SPMV, 0.0, kPersistTag);
+        MFS_HIP(launch_pcg_persist(ctx->stream, dsd, ts_.dv, ts_.nv, ctx->lpr, lds));
+      }
+      MFS_TRY(read_cg(ctx, n, false));
+      // algorithmic bytes: the matrix, the rows' vectors and preconditioner
+      // blocks once; per iteration the gathered m_i and the stored m_i+1
+      for (ProfPending& p : ctx->pending) {
+        if (p.fam != MFS_K_SPMV || p.tag != kPersistTag) continue;
+        double by = 0.0;
+        for (int i : act) {
+          const mfs_character* c = slot_[i].ch;
+          by += c->nnzb * (9.0 * 4.0 + 4.0) + (c->n + 1) * 4.0 + c->n * (9.0 * 24.0 + 24.0 + 24.0) +
+                (double)hg[i].iters * c->n * 48.0;
+        }
+        p.bytes = by;
+        p.tag = -1;
+      }
+      prof_resolve(ctx);
+      for (int i : act) {
+        if (hg[i].abort)
+          return set_error(MFS_E_HIP, "persistent PCG: a barrier wait timed out (slot %d)", i);
+        const bool ok = hg[i].done == 1;
+        slot_[i].cg += hg[i].iters;
+        if (ok) continue;
+        if (failed)
+          failed->push_back(i);
+        else
+          slot_[i].cg_fail++;
+      }
+      ProfScope ps(ctx, MFS_K_OTHER);
+      launch_cg_finish(ctx->stream, dsd, ts_.dv, ts_.nv, 0);
+      return MFS_OK;
+    }
+  }
   // PCG in runs of iterations; after each run the host reads the
   // convergence flags and residuals and sizes the next run from the
   // observed residual decay of the slowest slot.
@@ -657,6 +706,7 @@ int Engine::step() {
     // tolerance (a loose mixed step can leave the positive-definite cone in
     // single tets and stall the mixed line search)
     hc[i].cg_adaptive = (o_.cg_adaptive && slot_[i].phase == 1) ? 1 : 0;
+    hc[i].cg_cap = fp32_ ? fp32_cap(slot_[i].ch) : o_.cg_max;
   }
   MFS_TRY(upload_ctrl(ctx, n));
   {

@@ -113,6 +113,10 @@ struct mfs_context {
   bool use_graphs = true;            // replay captured runs of PCG iterations
   int graph_iters = 8;               // PCG iterations per captured graph
   bool pipelined = false;            // FP32 solves: pipelined PCG, one kernel per iteration
+  bool persistent = false;           // pipelined solves that fit the device: one cooperative launch
+  int persist_lpr = 0;               // launch shape of the cached capacity below
+  size_t persist_lds = 0;
+  int persist_capacity = 0;          // workgroups of the persistent PCG the device holds at once
   int allread_tiles = mfs::kAllReadTiles;  // largest system (vertex tiles) with all-read PCG sums
   std::vector<mfs::CgGraph> graphs;
   // batch scratch
@@ -146,6 +150,7 @@ struct mfs_character {
   std::vector<int32_t> perm;   // internal vertex -> caller vertex
   std::vector<int32_t> tperm;  // internal tet -> caller tet
   int ntv = 0, ntt = 0, nts = 0, ptile = 0;
+  int max_tile_blocks = 0;     // matrix blocks of the densest 64-row vertex tile
   bool has_solution = false;
   // resident mesh data
   mfs::DevBuf tets, G, wmu, wlam, info, X, rowptr, colidx, slot_ptr, contrib, diag, vpin_ptr, vpin_h, perm_d,

@@ -337,16 +337,17 @@ __global__ __launch_bounds__(64) void k_cg_update(const SysDesc* __restrict__ sd
 // last block and are weighted 0, so no branch splits the loads), then all gathers are
 // issued, so a batch costs two dependent memory latencies instead of two per
 // block.
+// The row's block range [rb, re) is passed in (re = rb for no row).
 template <typename T, typename V, int LPR>
-__device__ __forceinline__ void row_product(const SysDesc& S, const V* __restrict__ v, int row, bool valid, int lane,
-                                            V acc[3]) {
+__device__ __forceinline__ void row_range_product(const SysDesc& S, const V* __restrict__ v, int rb, int re, int lane,
+                                                  V acc[3]) {
   constexpr int U = LPR >= 16 ? 1 : 16 / LPR;
   acc[0] = acc[1] = acc[2] = (V)0;
-  if (valid) {
+  {
     const T* vals = (const T*)S.vals;
     const size_t nz = S.nnzb;
-    const int e = S.rowptr[row + 1];
-    for (int base = S.rowptr[row] + lane; base < e; base += U * LPR) {
+    const int e = re;
+    for (int base = rb + lane; base < e; base += U * LPR) {
       int c[U];
       T a[U][9];
 #pragma unroll
@@ -379,6 +380,40 @@ __device__ __forceinline__ void row_product(const SysDesc& S, const V* __restric
     acc[0] += __shfl_xor(acc[0], o, 64);
     acc[1] += __shfl_xor(acc[1], o, 64);
     acc[2] += __shfl_xor(acc[2], o, 64);
+  }
+}
+
+template <typename T, typename V, int LPR>
+__device__ __forceinline__ void row_product(const SysDesc& S, const V* __restrict__ v, int row, bool valid, int lane,
+                                            V acc[3]) {
+  const int rb = valid ? S.rowptr[row] : 0;
+  const int re = valid ? S.rowptr[row + 1] : 0;
+  row_range_product<T, V, LPR>(S, v, rb, re, lane, acc);
+}
+
+// This lane's terms of the fixed-order sums of three partial planes (lane l
+// adds tiles l, l + 64, ... in sequence, as sys_sum does), with the loads of
+// four terms per plane issued before their additions.
+__device__ __forceinline__ void lane_sums3(const double* a, const double* b, const double* c, int count,
+                                           double& sa, double& sb, double& sc) {
+  sa = sb = sc = 0.0;
+  for (int i0 = threadIdx.x & 63; i0 < count; i0 += 256) {
+    double va[4], vb[4], vc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + 64 * u < count ? i0 + 64 * u : i0;
+      va[u] = a[i];
+      vb[u] = b[i];
+      vc[u] = c[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (i0 + 64 * u < count) {
+        sa += va[u];
+        sb += vb[u];
+        sc += vc[u];
+      }
+    }
   }
 }
 
@@ -418,6 +453,8 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_start(const SysDesc* __restric
   if (t.local == 0 && threadIdx.x == 0) {
     st->a_prev[1] = 1.0;       // alpha_{-1}: any non-zero value
     st->g_prev[1] = INFINITY;  // gamma_{-1}: beta_0 = 0
+    st->bar = 0;               // persistent form: no barrier passed yet
+    st->abort = 0;
   }
   const int lane = threadIdx.x % LPR;
   const int row = t.begin + threadIdx.x / LPR;
@@ -464,58 +501,93 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_start(const SysDesc* __restric
   }
 }
 
-// Iteration i (parity = i & 1) of the pipelined PCG.
+// Iteration i (parity = i & 1) of the pipelined PCG.  Everything the launch
+// reads that no workgroup of it writes (the row's block range, the row's own
+// vector entries, the partial sums of the previous launch, the PCG state) is
+// loaded at its head, before the convergence flag is tested, so the loads
+// overlap instead of forming a chain; a launch for a stopped system reads
+// them and discards them.  Every wave folds the partial sums itself (the
+// same fixed order in each), so no barrier separates the fold from the SpMV.
 template <typename T, typename V, int LPR, bool ONE>
 __global__ __launch_bounds__(64 * LPR) void k_pcg_iter(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
                                                        int ntiles, const SysDesc one, int parity) {
   __shared__ double red[3][LPR];
-  __shared__ double bcast[3];
   __shared__ int last;
   const Tile t = vertex_tile<ONE>(tiles, ntiles, one);
   const SysDesc& S = ONE ? one : sd[t.sys];
   CgState* st = S.cg;
-  // A run of launches goes on after convergence (or a breakdown) while its
-  // parity argument keeps alternating; the planes of the other parity still
-  // hold the previous iteration's sums, so every later launch must stop here.
-  // (Within the launch that sets `done`, every workgroup stops anyway.)
-  if (st->done) return;
   const int par = parity & 1;
   const int lane = threadIdx.x % LPR;
   const int row = t.begin + threadIdx.x / LPR;
   const bool valid = row < t.end;
+  const bool owner = valid && lane == 0;
   const V* mi = (const V*)(par ? S.q : S.p1);
   V* mn = (V*)(par ? S.p1 : S.q);
+  V* zv = (V*)S.v1;
+  V* qv = (V*)S.v2;
+  V* sv = (V*)S.v3;
+  V* pv = (V*)S.p0;
+  V* xv = (V*)S.xc;
+  V* rv = (V*)S.r;
+  V* uv = (V*)S.z;
+  V* wv = (V*)S.v0;
+  const int rb = valid ? S.rowptr[row] : 0;
+  const int re = valid ? S.rowptr[row + 1] : 0;
+  V oz[3], oq[3], os[3], op[3], ox[3], orr[3], ou[3], ow[3], om[3];
+  T mb[6];
+  if (owner) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int k = 3 * row + i;
+      oz[i] = zv[k];
+      oq[i] = qv[k];
+      os[i] = sv[k];
+      op[i] = pv[k];
+      ox[i] = xv[k];
+      orr[i] = rv[k];
+      ou[i] = uv[k];
+      ow[i] = wv[k];
+      om[i] = mi[k];
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) mb[i] = ((const T*)S.minv)[6 * row + i];
+  }
+  double lr = 0.0, lg = 0.0, ld = 0.0;
+  if (!S.ticket)
+    lane_sums3(S.part + (par ? P_RR1 : P_RR) * S.ptile, S.part + (P_G0 + par) * S.ptile,
+               S.part + (P_D0 + par) * S.ptile, S.ntv, lr, lg, ld);
+  const int stopped = st->done;
+  const double g_prev = st->g_prev[par ^ 1], a_prev = st->a_prev[par ^ 1];
+  const double bb = st->bb;
+  const double g_t = st->g, d_t = st->d;
+  const Ctrl ctrl = *S.ctrl;
+  // A run of launches goes on after convergence (or a breakdown) while its
+  // parity argument keeps alternating; the planes of the other parity still
+  // hold the previous iteration's sums, so every later launch must stop here.
+  // (Within the launch that sets `done`, every workgroup stops anyway.)
+  if (stopped) return;
   // n_i = K m_i: needs nothing from the fold below
   V nv[3];
-  row_product<T, V, LPR>(S, mi, row, valid, lane, nv);
+  row_range_product<T, V, LPR>(S, mi, rb, re, lane, nv);
   double gam, del;
   if (S.ticket) {
-    gam = st->g;
-    del = st->d;
+    gam = g_t;
+    del = d_t;
   } else {
-    if (threadIdx.x < 64) {
-      const double rr = sys_sum(S.part + (par ? P_RR1 : P_RR) * S.ptile, S.ntv);
-      const double bb = st->bb;
-      const bool c = rr <= pcg_tol2(*S.ctrl, bb) * bb;
-      const double g = sys_sum(S.part + (P_G0 + par) * S.ptile, S.ntv);
-      const double d = sys_sum(S.part + (P_D0 + par) * S.ptile, S.ntv);
-      if (threadIdx.x == 0) {
-        bcast[0] = c ? 1.0 : 0.0;
-        bcast[1] = g;
-        bcast[2] = d;
-        if (t.local == 0) {
-          st->rr = rr;
-          if (c) st->done = 1;
-        }
+    const double rr = wave_sum(lr);
+    gam = wave_sum(lg);
+    del = wave_sum(ld);
+    if (rr <= pcg_tol2(ctrl, bb) * bb) {
+      if (t.local == 0 && threadIdx.x == 0) {
+        st->rr = rr;
+        st->done = 1;
       }
+      return;
     }
-    __syncthreads();
-    if (bcast[0] != 0.0) return;
-    gam = bcast[1];
-    del = bcast[2];
+    if (t.local == 0 && threadIdx.x == 0) st->rr = rr;
   }
-  const double beta = gam / st->g_prev[par ^ 1];
-  const double den = del - beta * gam / st->a_prev[par ^ 1];
+  const double beta = gam / g_prev;
+  const double den = del - beta * gam / a_prev;
   if (!(den > 0.0) || !(gam > 0.0)) {  // breakdown (lost positive definiteness in rounding): stop here
     if (t.local == 0 && threadIdx.x == 0) st->done = 2;  // reported as not converged
     return;
@@ -528,31 +600,23 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_iter(const SysDesc* __restrict
   }
   const V ta = (V)alpha, tb = (V)beta;
   double g = 0.0, dl = 0.0, rr = 0.0;
-  if (valid && lane == 0) {
-    V* zv = (V*)S.v1;
-    V* qv = (V*)S.v2;
-    V* sv = (V*)S.v3;
-    V* pv = (V*)S.p0;
-    V* xv = (V*)S.xc;
-    V* rv = (V*)S.r;
-    V* uv = (V*)S.z;
-    V* wv = (V*)S.v0;
+  if (owner) {
     V w[3], mnew[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const int k = 3 * row + i;
-      const V z = nv[i] + tb * zv[k];
-      const V q = mi[k] + tb * qv[k];
-      const V sk = wv[k] + tb * sv[k];
-      const V pk = uv[k] + tb * pv[k];
+      const V z = nv[i] + tb * oz[i];
+      const V q = om[i] + tb * oq[i];
+      const V sk = ow[i] + tb * os[i];
+      const V pk = ou[i] + tb * op[i];
       zv[k] = z;
       qv[k] = q;
       sv[k] = sk;
       pv[k] = pk;
-      xv[k] += ta * pk;
-      const V r = rv[k] - ta * sk;
-      const V u = uv[k] - ta * q;
-      w[i] = wv[k] - ta * z;
+      xv[k] = ox[i] + ta * pk;
+      const V r = orr[i] - ta * sk;
+      const V u = ou[i] - ta * q;
+      w[i] = ow[i] - ta * z;
       rv[k] = r;
       uv[k] = u;
       wv[k] = w[i];
@@ -560,7 +624,7 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_iter(const SysDesc* __restrict
       dl += (double)w[i] * (double)u;
       rr += (double)r * (double)r;
     }
-    precondition((const T*)S.minv + 6 * row, w, mnew);
+    precondition(mb, w, mnew);
 #pragma unroll
     for (int i = 0; i < 3; ++i) mn[3 * row + i] = mnew[i];
   }
@@ -585,6 +649,289 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_iter(const SysDesc* __restrict
       if (srr <= pcg_tol2(*S.ctrl, st->bb) * st->bb) st->done = 1;
       st->arrive_pipe = 0;
     }
+  }
+}
+
+// ---- persistent pipelined PCG ----
+//
+// The whole pipelined PCG of a Newton step in one cooperative launch: one
+// workgroup per vertex tile, every workgroup of the launch resident at once
+// (the host launches it only when the device can hold them all).  A
+// workgroup copies its tile's rows of the matrix (values, column indices,
+// row offsets) into LDS once and keeps its rows' vectors and recurrences in
+// registers, so an iteration reads from memory only the gathered
+// neighbours of m_i and the previous iteration's partial sums.  Iterations
+// of a system are separated by a barrier over that system's workgroups (an
+// arrival counter with release/acquire fences); the fold, the convergence
+// test and the breakdown test are computed identically by every
+// workgroup, so all of a system's workgroups leave the loop at the same
+// iteration.  The arithmetic, and its order, is that of k_pcg_iter, so the
+// iterates are bitwise those of the one-kernel-per-iteration form.
+//
+// The values other workgroups read (the rows of m and the partial sums) are
+// stored with device-scope atomic stores; the workgroup barrier orders them
+// before thread 0's release fence, which (with the acquire fence after the
+// wait) makes them visible to the other workgroups of the system.  One fence
+// pair per workgroup and iteration: fences issued by every wave cost several
+// microseconds per iteration more.
+//
+// Every spin on the barrier is bounded: a workgroup that waits longer than
+// kBarrierSpins polls marks the system aborted (CgState::abort), and every
+// workgroup of that system leaves at its next barrier or poll.
+constexpr int kBarrierSpins = 1 << 22;
+
+__device__ __forceinline__ void st_dev(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier over the `count` workgroups of one system; `target` is
+// count x (barriers passed + 1).  Returns false when the system aborted.
+__device__ __forceinline__ bool system_barrier(CgState* st, uint32_t target, int* lds_ok) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();  // release the workgroup's m rows and partial sums
+    atomicAdd(&st->bar, 1u);
+    int ok = 1;
+    for (int spins = 0;; ++spins) {
+      if (__hip_atomic_load(&st->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+      if (spins >= kBarrierSpins || __hip_atomic_load(&st->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        __hip_atomic_store(&st->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __threadfence();  // acquire the other workgroups' stores
+    *lds_ok = ok;
+  }
+  __syncthreads();
+  return *lds_ok != 0;
+}
+
+// Loads of values written by other workgroups of the running launch, at
+// device scope (they do not hit stale lines of this CU's caches).
+__device__ __forceinline__ double ld_dev(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// lane_sums3 with device-scope loads.
+__device__ __forceinline__ void lane_sums3_dev(const double* a, const double* b, const double* c, int count,
+                                               double& sa, double& sb, double& sc) {
+  sa = sb = sc = 0.0;
+  for (int i0 = threadIdx.x & 63; i0 < count; i0 += 256) {
+    double va[4], vb[4], vc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + 64 * u < count ? i0 + 64 * u : i0;
+      va[u] = ld_dev(a + i);
+      vb[u] = ld_dev(b + i);
+      vc[u] = ld_dev(c + i);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (i0 + 64 * u < count) {
+        sa += va[u];
+        sb += vb[u];
+        sc += vc[u];
+      }
+    }
+  }
+}
+
+// LDS bytes of one tile of `blocks` matrix blocks in precision T.
+template <typename T>
+__host__ __device__ constexpr size_t persist_lds_bytes(int blocks) {
+  return ((size_t)(kVTile + 1) * 4 + 15) / 16 * 16 + ((size_t)blocks * 4 + 15) / 16 * 16 + (size_t)9 * blocks * sizeof(T);
+}
+
+template <typename T, typename V, int LPR>
+__global__ __launch_bounds__(64 * LPR) void k_pcg_persist(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
+                                                          int ntiles) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ double red[3][LPR];
+  __shared__ int bar_ok;
+  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
+  const SysDesc& S = sd[t.sys];
+  CgState* st = S.cg;
+  if (st->done) return;  // converged at the start (set by the start kernel)
+  const int cap = S.ctrl->cg_cap;
+  const Ctrl ctrl = *S.ctrl;
+  const double bb = st->bb;
+  // ---- the tile's matrix rows into LDS ----
+  const int rows = t.end - t.begin;
+  const int base = S.rowptr[t.begin];
+  const int nbt = S.rowptr[t.end] - base;
+  int* lrow = (int*)lds_raw;
+  int* lcol = (int*)(lds_raw + ((size_t)(kVTile + 1) * 4 + 15) / 16 * 16);
+  T* lval = (T*)((unsigned char*)lcol + ((size_t)nbt * 4 + 15) / 16 * 16);
+  {
+    const T* vals = (const T*)S.vals;
+    const size_t nz = S.nnzb;
+    for (int i = threadIdx.x; i <= rows; i += blockDim.x) lrow[i] = S.rowptr[t.begin + i] - base;
+    for (int i = threadIdx.x; i < nbt; i += blockDim.x) {
+      lcol[i] = S.colidx[base + i];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) lval[k * nbt + i] = vals[k * nz + base + i];
+    }
+  }
+  const int lane = threadIdx.x % LPR;
+  const int lr = threadIdx.x / LPR;
+  const int row = t.begin + lr;
+  const bool valid = row < t.end;
+  const bool owner = valid && lane == 0;
+  V* xv = (V*)S.xc;
+  // ---- the rows' vectors and recurrences, kept in registers ----
+  V oz[3], oq[3], os[3], op[3], ox[3], orr[3], ou[3], ow[3], om[3];
+  T mb[6];
+  if (owner) {
+    const V* zv = (const V*)S.v1;
+    const V* qv = (const V*)S.v2;
+    const V* sv = (const V*)S.v3;
+    const V* pv = (const V*)S.p0;
+    const V* rv = (const V*)S.r;
+    const V* uv = (const V*)S.z;
+    const V* wv = (const V*)S.v0;
+    const V* m0 = (const V*)S.p1;  // m_0 (iteration 0 has parity 0)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int k = 3 * row + i;
+      oz[i] = zv[k];
+      oq[i] = qv[k];
+      os[i] = sv[k];
+      op[i] = pv[k];
+      ox[i] = xv[k];
+      orr[i] = rv[k];
+      ou[i] = uv[k];
+      ow[i] = wv[k];
+      om[i] = m0[k];
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) mb[i] = ((const T*)S.minv)[6 * row + i];
+  }
+  __syncthreads();
+  const int rb = valid ? lrow[lr] : 0;
+  const int re = valid ? lrow[lr + 1] : 0;
+  double a_prev = 1.0, g_prev = INFINITY;  // alpha_{-1}, gamma_{-1}: beta_0 = 0
+  double rr_last = st->rr;
+  int it = 0;
+  int state = 0;  // 0: running/capped, 1: converged, 2: breakdown, 3: aborted
+  for (;; ++it) {
+    const int par = it & 1;
+    const V* mi = (const V*)(par ? S.q : S.p1);
+    V* mn = (V*)(par ? S.p1 : S.q);
+    // n_i = K m_i: blocks from LDS, m_i gathered (same order as row_range_product)
+    V nv[3] = {(V)0, (V)0, (V)0};
+    {
+      constexpr int U = LPR >= 16 ? 1 : 16 / LPR;
+      for (int b0 = rb + lane; b0 < re; b0 += U * LPR) {
+        int c[U];
+        T a[U][9];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int sl = b0 + u * LPR;
+          const int sc = sl < re ? sl : re - 1;
+          c[u] = lcol[sc];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) a[u][k] = lval[k * nbt + sc];
+        }
+        V g[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          g[u][0] = ld_dev(mi + 3 * c[u]);
+          g[u][1] = ld_dev(mi + 3 * c[u] + 1);
+          g[u][2] = ld_dev(mi + 3 * c[u] + 2);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const V w = b0 + u * LPR < re ? (V)1 : (V)0;
+          nv[0] += w * ((V)a[u][0] * g[u][0] + (V)a[u][1] * g[u][1] + (V)a[u][2] * g[u][2]);
+          nv[1] += w * ((V)a[u][3] * g[u][0] + (V)a[u][4] * g[u][1] + (V)a[u][5] * g[u][2]);
+          nv[2] += w * ((V)a[u][6] * g[u][0] + (V)a[u][7] * g[u][1] + (V)a[u][8] * g[u][2]);
+        }
+      }
+#pragma unroll
+      for (int o = LPR / 2; o > 0; o >>= 1) {
+        nv[0] += __shfl_xor(nv[0], o, 64);
+        nv[1] += __shfl_xor(nv[1], o, 64);
+        nv[2] += __shfl_xor(nv[2], o, 64);
+      }
+    }
+    // fold of the previous iteration's partial sums (every wave, same order)
+    double lsr, lsg, lsd;
+    lane_sums3_dev(S.part + (par ? P_RR1 : P_RR) * S.ptile, S.part + (P_G0 + par) * S.ptile,
+               S.part + (P_D0 + par) * S.ptile, S.ntv, lsr, lsg, lsd);
+    const double rr = wave_sum(lsr);
+    const double gam = wave_sum(lsg);
+    const double del = wave_sum(lsd);
+    rr_last = rr;
+    if (rr <= pcg_tol2(ctrl, bb) * bb) {
+      state = 1;
+      break;
+    }
+    if (it >= cap) break;
+    const double beta = gam / g_prev;
+    const double den = del - beta * gam / a_prev;
+    if (!(den > 0.0) || !(gam > 0.0)) {
+      state = 2;
+      break;
+    }
+    const double alpha = gam / den;
+    a_prev = alpha;
+    g_prev = gam;
+    const V ta = (V)alpha, tb = (V)beta;
+    double g = 0.0, dl = 0.0, r2 = 0.0;
+    if (owner) {
+      V w[3], mnew[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const V z = nv[i] + tb * oz[i];
+        const V q = om[i] + tb * oq[i];
+        const V sk = ow[i] + tb * os[i];
+        const V pk = ou[i] + tb * op[i];
+        oz[i] = z;
+        oq[i] = q;
+        os[i] = sk;
+        op[i] = pk;
+        ox[i] = ox[i] + ta * pk;
+        const V r = orr[i] - ta * sk;
+        const V u = ou[i] - ta * q;
+        w[i] = ow[i] - ta * z;
+        orr[i] = r;
+        ou[i] = u;
+        ow[i] = w[i];
+        g += (double)r * (double)u;
+        dl += (double)w[i] * (double)u;
+        r2 += (double)r * (double)r;
+      }
+      precondition(mb, w, mnew);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        st_dev(mn + 3 * row + i, mnew[i]);
+        om[i] = mnew[i];
+      }
+    }
+    const int nx = par ^ 1;
+    const double tg = block_sum<LPR>(g, red[0]);
+    const double td = block_sum<LPR>(dl, red[1]);
+    const double tr = block_sum<LPR>(r2, red[2]);
+    if (threadIdx.x == 0) {
+      st_dev(S.part + (P_G0 + nx) * S.ptile + t.local, tg);
+      st_dev(S.part + (P_D0 + nx) * S.ptile + t.local, td);
+      st_dev(S.part + (nx ? P_RR1 : P_RR) * S.ptile + t.local, tr);
+    }
+    if (!system_barrier(st, (uint32_t)S.ntv * (uint32_t)(it + 1), &bar_ok)) {
+      state = 3;
+      break;
+    }
+  }
+  if (owner) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) xv[3 * row + i] = ox[i];
+  }
+  if (t.local == 0 && threadIdx.x == 0) {
+    st->iters = it;
+    st->rr = rr_last;
+    st->done = state;
   }
 }
 
@@ -736,6 +1083,46 @@ void launch_pcg_iter(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv,
     if (one) pcg_iter_t<double, double, true>(st, sd, tv, ntv, lpr, o, parity);
     else pcg_iter_t<double, double, false>(st, sd, tv, ntv, lpr, o, parity);
   }
+}
+
+// ---- persistent pipelined PCG launch ----
+template <int LPR>
+static const void* persist_kernel() {
+  return reinterpret_cast<const void*>(&k_pcg_persist<float, double, LPR>);
+}
+static const void* persist_fn(int lpr) {
+  return lpr == 2 ? persist_kernel<2>() : (lpr == 8 ? persist_kernel<8>() : persist_kernel<4>());
+}
+
+size_t pcg_persist_lds(int max_tile_blocks) { return persist_lds_bytes<float>(max_tile_blocks); }
+
+int pcg_persist_capacity(int lpr, size_t lds_bytes) {
+  int dev = 0, per_cu = 0, cus = 0, lds_max = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+  const size_t static_lds = sizeof(double) * 3 * 8 + 16;
+  if (lds_bytes + static_lds > (size_t)lds_max) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_fn(lpr), 64 * (lpr == 2 || lpr == 8 ? lpr : 4),
+                                                   lds_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return per_cu * cus;
+}
+
+hipError_t launch_pcg_persist(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int lpr, size_t lds_bytes) {
+  if (!ntv) return hipSuccess;
+  const int L = (lpr == 2 || lpr == 8) ? lpr : 4;
+  void* args[] = {(void*)&sd, (void*)&tv, (void*)&ntv};
+  LaunchEvents& le = launch_events();
+  if (le.stop && !le.started) (void)hipEventRecord(le.start, st);
+  const hipError_t e = hipLaunchCooperativeKernel(persist_fn(L), dim3(ntv), dim3(64 * L), args, (unsigned)lds_bytes, st);
+  if (le.stop) {
+    (void)hipEventRecord(le.stop, st);
+    le.started = true;
+  }
+  return e;
 }
 
 void launch_cg_finish(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32) {

@@ -396,16 +396,20 @@ __global__ __launch_bounds__(64) void k_update_x(const SysDesc* __restrict__ sd,
   for (int i = 0; i < 3; ++i) S.x[3 * r + i] += a * S.dx[3 * r + i];
 }
 
-// Fold each system's partial planes over its tiles (fixed order).
-__global__ __launch_bounds__(64) void k_finalize(const SysDesc* __restrict__ sd, const int32_t* __restrict__ sys_ids) {
+// Fold each system's partial planes over its tiles (fixed order): one
+// workgroup per system, one wave per plane.
+constexpr int kFinalizeThreads = 512;
+__global__ __launch_bounds__(kFinalizeThreads) void k_finalize(const SysDesc* __restrict__ sd,
+                                                              const int32_t* __restrict__ sys_ids) {
   const SysDesc& S = sd[sys_ids[blockIdx.x]];
-  for (int p = 0; p < P_G0; ++p) {  // the pipelined-PCG planes are folded by the PCG kernels
+  // the pipelined-PCG planes (from P_G0 on) are folded by the PCG kernels
+  for (int p = threadIdx.x >> 6; p < P_G0; p += kFinalizeThreads / 64) {
     const bool vert = (p == P_PQ || p == P_RZ0 || p == P_RZ1 || p == P_RR || p == P_BB || p == P_SLOPE ||
                        p == P_DXMAX || (p >= P_PIN0 && p < P_PIN0 + kNumTrials));
     const int cnt = vert ? S.ntv : S.ntt;
     const double* plane = S.part + (size_t)p * S.ptile;
     const double v = (p == P_DXMAX || p == P_HMAX) ? sys_max(plane, cnt) : sys_sum(plane, cnt);
-    if (threadIdx.x == 0) S.red[p] = v;
+    if ((threadIdx.x & 63) == 0) S.red[p] = v;
   }
 }
 
@@ -492,7 +496,7 @@ void launch_stress(hipStream_t st, const SysDesc* sd, int m, const int32_t* tper
   if (m > 0) MFS_LAUNCH(k_stress, dim3((m + kBlock - 1) / kBlock), dim3(kBlock), 0, st, sd, tperm, P6, L9);
 }
 void launch_finalize(hipStream_t st, const SysDesc* sd, const int32_t* sys_ids, int nsys) {
-  if (nsys) MFS_LAUNCH(k_finalize, dim3(nsys), dim3(64), 0, st, sd, sys_ids);
+  if (nsys) MFS_LAUNCH(k_finalize, dim3(nsys), dim3(kFinalizeThreads), 0, st, sd, sys_ids);
 }
 
 }  // namespace mfs

@@ -72,6 +72,13 @@ void launch_pcg_start(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv
                       const SysDesc* one);
 void launch_pcg_iter(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, int lpr,
                      const SysDesc* one, int parity);
+// Persistent pipelined PCG (FP32 matrix, FP64 vectors): LDS bytes for tiles
+// of at most `max_tile_blocks` blocks, the number of its workgroups the
+// device holds at once (0: cannot run), and the cooperative launch (one
+// workgroup per vertex tile, after launch_pcg_start).
+size_t pcg_persist_lds(int max_tile_blocks);
+int pcg_persist_capacity(int lpr, size_t lds_bytes);
+hipError_t launch_pcg_persist(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int lpr, size_t lds_bytes);
 void launch_cg_finish(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32);
 void launch_spmv_plain(hipStream_t st, const int32_t* rowptr, const int32_t* colidx, const double* vals, int nnzb,
                        int n, const double* v, double* y);

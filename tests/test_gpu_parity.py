@@ -286,8 +286,8 @@ def test_pipelined_pcg(ctx):
         ref = oracle.solve_frame(prob, pose)
         ch = mfs.Character(ctx, prob)
         for lpr in (2, 4, 8):
-            ctx.set_tuning(pcg_pipelined=1, pcg_lanes_per_row=lpr, use_graphs=1, graph_iterations=8,
-                           first_check=31, min_run=7)
+            ctx.set_tuning(pcg_pipelined=1, pcg_persistent=0, pcg_lanes_per_row=lpr, use_graphs=1,
+                           graph_iterations=8, first_check=31, min_run=7)
             _say(f"pipelined PCG: humanoid m={len(prob['T'])} lanes {lpr}, graphs")
             xg, st, rc = ch.solve(*pose, **kw)
             _say(f"  stats {st} err/bbox={_err(xg, ref['x'], prob):.3e}")
@@ -296,7 +296,7 @@ def test_pipelined_pcg(ctx):
             xd, _, rc = ch.solve(*pose, **kw)
             assert rc == 0 and np.array_equal(xg, xd)
         ch.close()
-        ctx.set_tuning(pcg_pipelined=1, pcg_lanes_per_row=4, use_graphs=1, graph_iterations=8)
+        ctx.set_tuning(pcg_pipelined=1, pcg_persistent=0, pcg_lanes_per_row=4, use_graphs=1, graph_iterations=8)
         probs = [humanoid(100 + i, target_tets=t, n_bones=b, models=(NH, COROT))
                  for i, (t, b) in enumerate([(1500, 8), (3000, 12), (800, 10)])]
         poses = [random_pose(p, 200 + i) for i, p in enumerate(probs)]
@@ -396,3 +396,63 @@ def test_stress_matches_oracle(ctx):
     ok = ~bad
     assert np.max(np.abs(Pb[ok] - Pbr[ok])) <= 1e-12 * np.max(np.abs(Pbr[ok]))
     ch.close()
+
+
+def test_persistent_pcg(ctx):
+    """The persistent pipelined PCG (one cooperative launch per Newton step):
+    bitwise the iterates of the one-kernel-per-iteration form for every lane
+    count (same frame, same statistics), one SpMV-family launch per Newton
+    step, a batch bitwise equal to its members solved alone, and the
+    full-size 50k golden within 1e-7 * bbox of the oracle."""
+    import os
+    mfs = _mfs()
+    base = ctx.tuning()
+    kw = dict(precision=mfs.FP32_REFINED, cg_tol=1e-5, step_tol=1e-9, max_newton=60, cg_adaptive=1)
+    try:
+        prob = _small_humanoid(21, 4000, 15)
+        pose = random_pose(prob, 22)
+        ch = mfs.Character(ctx, prob)
+        for lpr in (2, 4, 8):
+            ctx.set_tuning(pcg_pipelined=1, pcg_persistent=0, pcg_lanes_per_row=lpr, use_graphs=1,
+                           graph_iterations=8)
+            x0, st0, rc0 = ch.solve(*pose, **kw)
+            assert rc0 == 0
+            ctx.set_tuning(pcg_persistent=1)
+            _say(f"persistent PCG: humanoid m={len(prob['T'])} lanes {lpr}")
+            ctx.profile_enable(1)
+            ctx.profile_read(reset=True)
+            x1, st1, rc1 = ch.solve(*pose, **kw)
+            prof = ctx.profile_read(reset=True)
+            ctx.profile_enable(0)
+            _say(f"  stats {st1}; spmv launches {prof['spmv'][2]}")
+            assert rc1 == 0 and np.array_equal(x0, x1)
+            for key in ("iterations", "cg_iterations", "status", "fp64_resolves"):
+                assert st0[key] == st1[key], key
+            assert prof["spmv"][2] == st1["iterations"] and prof["spmv"][3] > 0
+        ch.close()
+        ctx.set_tuning(pcg_pipelined=1, pcg_persistent=1, pcg_lanes_per_row=4)
+        probs = [humanoid(100 + i, target_tets=t, n_bones=b, models=(NH, COROT))
+                 for i, (t, b) in enumerate([(1500, 8), (3000, 12), (800, 10)])]
+        poses = [random_pose(p, 200 + i) for i, p in enumerate(probs)]
+        chars = [mfs.Character(ctx, p) for p in probs]
+        alone = [c.solve(*q, **kw)[0] for c, q in zip(chars, poses)]
+        _say("persistent PCG: batch of 3")
+        xs, _, rc = mfs.solve_batch(ctx, chars, poses, **kw)
+        assert rc == 0
+        for a, b in zip(alone, xs):
+            assert np.array_equal(a, b)
+        for c in chars:
+            c.close()
+        here = os.path.dirname(os.path.abspath(__file__))
+        g = np.load(os.path.join(here, "golden", "humanoid50k_pose2002.npz"))
+        prob = humanoid(2001, target_tets=50000, n_bones=20)
+        pose = random_pose(prob, 2002)
+        ch = mfs.Character(ctx, prob)
+        _say("persistent PCG: humanoid 50k golden")
+        x, st, rc = ch.solve(*pose, precision=mfs.FP32_REFINED, cg_tol=1e-5, step_tol=1e-8, max_newton=60,
+                             cg_adaptive=1)
+        _say(f"  stats {st} err/bbox={_err(x, g['x'], prob):.3e}")
+        assert rc == 0 and _err(x, g["x"], prob) <= 1e-7
+        ch.close()
+    finally:
+        ctx.set_tuning(**base)
