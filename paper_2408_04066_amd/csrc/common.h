@@ -183,16 +183,70 @@ __device__ __forceinline__ int xcd_tile(int b, int ntiles) {
   return j * q + (j < rem ? j : rem) + i;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Cross-lane moves through DPP (data-parallel primitives of GFX9): quad
+// permutations, mirrors within 8 and 16 lanes, and the broadcasts of lane 15
+// and lane 31 to the following rows.  A lane whose row is outside ROW_MASK
+// receives 0.  Each move is a VALU operation; a ds_bpermute shuffle goes
+// through the LDS crossbar and costs several times as long.
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppMirror8 = 0x141;    // row_half_mirror: lane j <- lane 7 - j within 8
+constexpr int kDppMirror16 = 0x140;   // row_mirror: lane j <- lane 15 - j within 16
+constexpr int kDppBcast15 = 0x142;    // row_bcast:15
+constexpr int kDppBcast31 = 0x143;    // row_bcast:31
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
+__device__ __forceinline__ double lane63(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
+// Sum over the G consecutive lanes of a group (G = 1, 2, 4 or 8, groups
+// aligned to G); every lane of the group gets the sum.  Called with all 64
+// lanes active.
+template <int G, typename R>
+__device__ __forceinline__ R group_sum(R v) {
+  if (G >= 2) v += dpp<kDppXor1>(v);
+  if (G >= 4) v += dpp<kDppXor2>(v);
+  if (G >= 8) v += dpp<kDppMirror8>(v);
   return v;
 }
 
+// Sum over the 64 lanes in a fixed order (quads, eighths, rows of 16, then
+// the rows in order); every lane gets the sum.  Called with all 64 lanes
+// active.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp<kDppXor1>(v);
+  v += dpp<kDppXor2>(v);
+  v += dpp<kDppMirror8>(v);
+  v += dpp<kDppMirror16>(v);
+  v += dpp<kDppBcast15, 0xA>(v);
+  v += dpp<kDppBcast31, 0xC>(v);
+  return lane63(v);
+}
+
+// Maximum over the 64 lanes of values >= 0 (a masked-off row contributes 0).
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmax(v, dpp<kDppXor1>(v));
+  v = fmax(v, dpp<kDppXor2>(v));
+  v = fmax(v, dpp<kDppMirror8>(v));
+  v = fmax(v, dpp<kDppMirror16>(v));
+  v = fmax(v, dpp<kDppBcast15, 0xA>(v));
+  v = fmax(v, dpp<kDppBcast31, 0xC>(v));
+  return lane63(v);
 }
 
 // Fixed-order workgroup sum: butterfly within each wave, then the wave
@@ -209,6 +263,32 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
 #pragma unroll
   for (int i = 1; i < NW; ++i) acc += lds[i];
   return acc;
+}
+
+// Three fixed-order workgroup sums with one pair of barriers (lds: 3 x NW).
+template <int NW = 4>
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* lds) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  if (NW == 1) return;
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    lds[w] = a;
+    lds[NW + w] = b;
+    lds[2 * NW + w] = c;
+  }
+  __syncthreads();
+  a = lds[0];
+  b = lds[NW];
+  c = lds[2 * NW];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) {
+    a += lds[i];
+    b += lds[NW + i];
+    c += lds[2 * NW + i];
+  }
 }
 
 __device__ __forceinline__ double block_max(double v, double* lds4) {

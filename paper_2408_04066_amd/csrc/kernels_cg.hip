@@ -206,12 +206,9 @@ __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict_
       }
     }
   }
-#pragma unroll
-  for (int o = LPR / 2; o > 0; o >>= 1) {
-    a0 += __shfl_xor(a0, o, 64);
-    a1 += __shfl_xor(a1, o, 64);
-    a2 += __shfl_xor(a2, o, 64);
-  }
+  a0 = group_sum<LPR>(a0);
+  a1 = group_sum<LPR>(a1);
+  a2 = group_sum<LPR>(a2);
   double dot = 0.0;
   if (row < t.end && lane == 0) {
     T p0 = z[3 * row], p1 = z[3 * row + 1], p2 = z[3 * row + 2];
@@ -375,12 +372,9 @@ __device__ __forceinline__ void row_range_product(const SysDesc& S, const V* __r
       }
     }
   }
-#pragma unroll
-  for (int o = LPR / 2; o > 0; o >>= 1) {
-    acc[0] += __shfl_xor(acc[0], o, 64);
-    acc[1] += __shfl_xor(acc[1], o, 64);
-    acc[2] += __shfl_xor(acc[2], o, 64);
-  }
+  acc[0] = group_sum<LPR>(acc[0]);
+  acc[1] = group_sum<LPR>(acc[1]);
+  acc[2] = group_sum<LPR>(acc[2]);
 }
 
 template <typename T, typename V, int LPR>
@@ -422,7 +416,7 @@ __device__ __forceinline__ void lane_sums3(const double* a, const double* b, con
 template <typename T, typename V, int LPR, bool ONE>
 __global__ __launch_bounds__(64 * LPR) void k_pcg_start(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
                                                         int ntiles, const SysDesc one) {
-  __shared__ double red[2][LPR];
+  __shared__ double red[3][LPR];
   __shared__ int conv;
   __shared__ int last;
   const Tile t = vertex_tile<ONE>(tiles, ntiles, one);
@@ -484,8 +478,8 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_start(const SysDesc* __restric
       dl += (double)w[i] * uk;
     }
   }
-  const double tg = block_sum<LPR>(g, red[0]);
-  const double td = block_sum<LPR>(dl, red[1]);
+  double tg = g, td = dl, tz = 0.0;
+  block_sum3<LPR>(tg, td, tz, &red[0][0]);
   if (threadIdx.x == 0) {
     S.part[P_G0 * S.ptile + t.local] = tg;
     S.part[P_D0 * S.ptile + t.local] = td;
@@ -629,9 +623,8 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_iter(const SysDesc* __restrict
     for (int i = 0; i < 3; ++i) mn[3 * row + i] = mnew[i];
   }
   const int nx = par ^ 1;
-  const double tg = block_sum<LPR>(g, red[0]);
-  const double td = block_sum<LPR>(dl, red[1]);
-  const double tr = block_sum<LPR>(rr, red[2]);
+  double tg = g, td = dl, tr = rr;
+  block_sum3<LPR>(tg, td, tr, &red[0][0]);
   if (threadIdx.x == 0) {
     S.part[(P_G0 + nx) * S.ptile + t.local] = tg;
     S.part[(P_D0 + nx) * S.ptile + t.local] = td;
@@ -849,12 +842,9 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_persist(const SysDesc* __restr
           nv[2] += w * ((V)a[u][6] * g[u][0] + (V)a[u][7] * g[u][1] + (V)a[u][8] * g[u][2]);
         }
       }
-#pragma unroll
-      for (int o = LPR / 2; o > 0; o >>= 1) {
-        nv[0] += __shfl_xor(nv[0], o, 64);
-        nv[1] += __shfl_xor(nv[1], o, 64);
-        nv[2] += __shfl_xor(nv[2], o, 64);
-      }
+      nv[0] = group_sum<LPR>(nv[0]);
+      nv[1] = group_sum<LPR>(nv[1]);
+      nv[2] = group_sum<LPR>(nv[2]);
     }
     // fold of the previous iteration's partial sums (every wave, same order)
     double lsr, lsg, lsd;
@@ -911,9 +901,8 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_persist(const SysDesc* __restr
       }
     }
     const int nx = par ^ 1;
-    const double tg = block_sum<LPR>(g, red[0]);
-    const double td = block_sum<LPR>(dl, red[1]);
-    const double tr = block_sum<LPR>(r2, red[2]);
+    double tg = g, td = dl, tr = r2;
+    block_sum3<LPR>(tg, td, tr, &red[0][0]);
     if (threadIdx.x == 0) {
       st_dev(S.part + (P_G0 + nx) * S.ptile + t.local, tg);
       st_dev(S.part + (P_D0 + nx) * S.ptile + t.local, td);
