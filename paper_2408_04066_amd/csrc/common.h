@@ -90,6 +90,8 @@ struct Ctrl {
   double cg_tol2;    // squared relative PCG tolerance (floor when adaptive)
   int32_t cg_adaptive;  // 1: Eisenstat-Walker forcing on top of the floor
   int32_t cg_cap;       // persistent PCG: iteration cap of this solve
+  int32_t cg_epoch;     // number of this PCG solve, stored to SysDesc::stop_flag when it stops
+  int32_t pad2;
   double cg_g2prev;  // |g|^2 of the previous Newton step (0: first step)
   double cg_eta_min; // safeguard lower bound on the forcing term
   double trials[kNumTrials];  // step lengths evaluated by the energy pass
@@ -171,6 +173,7 @@ struct SysDesc {
   double* red;   // P_COUNT per-system results of the finalize kernel
   CgState* cg;   // PCG scalars of this system
   const Ctrl* ctrl;  // this system's control block (per-step PCG tolerance)
+  int32_t* stop_flag;  // host-mapped word set to ctrl->cg_epoch when the PCG stops, or null
 };
 
 // Workgroup -> tile map that keeps consecutive tiles on one XCD: workgroups
@@ -332,6 +335,13 @@ __device__ __forceinline__ bool last_arrival(uint32_t* ticket, uint32_t count, i
   const bool last = *lds_flag != 0;
   if (last) __threadfence();
   return last;
+}
+
+// Tells the host that this system's PCG has stopped (converged, or broke
+// down): the solve's epoch, stored to the host-mapped flag at system scope.
+// Called by the one thread that sets CgState::done.
+__device__ __forceinline__ void signal_stop(const SysDesc& S) {
+  if (S.stop_flag) __hip_atomic_store(S.stop_flag, S.ctrl->cg_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Fixed-order sum of one partial plane with device-coherent loads (the

@@ -16,6 +16,7 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <deque>
 #include <cmath>
 #include <cstring>
 
@@ -25,6 +26,41 @@ namespace mfs {
 
 int upload_ctrl(mfs_context* ctx, int count) {
   return ctx->up.upload(ctx->stream, ctx->ctrl.p, ctx->h_ctrl.data(), count * sizeof(Ctrl));
+}
+
+int ensure_stop_flags(mfs_context* ctx, int slots) {
+  if (slots <= ctx->stop_slots) return MFS_OK;
+  MFS_HIP(hipStreamSynchronize(ctx->stream));
+  if (ctx->h_stop) (void)hipHostFree(ctx->h_stop);
+  ctx->h_stop = nullptr;
+  ctx->d_stop = nullptr;
+  ctx->stop_slots = 0;
+  void* p = nullptr;
+  if (hipHostMalloc(&p, sizeof(int32_t) * slots, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(MFS_E_OOM, "host-mapped PCG flags for %d slots", slots);
+  }
+  std::memset(p, 0, sizeof(int32_t) * slots);
+  void* d = nullptr;
+  if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipHostFree(p);
+    return set_error(MFS_E_HIP, "no device address for the host-mapped PCG flags");
+  }
+  ctx->h_stop = static_cast<int32_t*>(p);
+  ctx->d_stop = static_cast<int32_t*>(d);
+  ctx->stop_slots = slots;
+  return MFS_OK;
+}
+
+int sync_event(mfs_context* ctx, hipEvent_t* out) {
+  if (!ctx->sync_events.empty()) {
+    *out = ctx->sync_events.back();
+    ctx->sync_events.pop_back();
+    return MFS_OK;
+  }
+  MFS_HIP(hipEventCreateWithFlags(out, hipEventDisableTiming));
+  return MFS_OK;
 }
 
 int read_cg(mfs_context* ctx, int count, bool resolve) {
@@ -304,6 +340,7 @@ int Engine::reserve(int n) {
   ctx_->h_ctrl.assign(n, Ctrl{});
   MFS_TRY(ctx_->h_red.reserve(n * P_COUNT * sizeof(double)));
   MFS_TRY(ctx_->h_cg.reserve(n * sizeof(CgState)));
+  MFS_TRY(ensure_stop_flags(ctx_, n));
   // arrival tickets start at zero (each kernel's last workgroup resets its own)
   MFS_HIP(hipMemsetAsync(ctx_->cg.p, 0, n * sizeof(CgState), ctx_->stream));
   slot_.assign(n, SlotState());
@@ -354,6 +391,7 @@ int Engine::attach(int i, mfs_character* ch, const double* R, const double* t) {
   d.red = ctx_->red.as<double>() + P_COUNT * i;
   d.cg = ctx_->cg.as<CgState>() + i;
   d.ctrl = ctx_->ctrl.as<Ctrl>() + i;
+  d.stop_flag = ctx_->d_stop + i;
   Ctrl& c = ctx_->h_ctrl.data()[i];
   std::memset(&c, 0, sizeof c);
   c.cg_tol2 = o_.cg_tol * o_.cg_tol;
@@ -411,15 +449,11 @@ int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* fai
   const CgState* hg = ctx->h_cg.as<CgState>();
   const Ctrl* hc = ctx->h_ctrl.data();
   int cit = 0;
-  int chunk = ctx->cg_first_run;
-  for (int i : act) {
-    slot_[i].rho_prev = -1.0;
-    slot_[i].it_prev = 0;
-  }
-  // launch set: the slots whose PCG still iterates.  It shrinks at the
-  // host's convergence checks, so the tiles of converged systems leave the
-  // grid, and a single remaining system runs with its descriptor as the
-  // kernel argument.  A slot's arithmetic does not depend on the set.
+  // launch set: the slots whose PCG still iterates.  It shrinks when stopped
+  // systems hold a quarter of its tiles (or a system reaches its cap), so
+  // the tiles of converged systems leave the grid, and a single remaining
+  // system runs with its descriptor as the kernel argument.  A slot's
+  // arithmetic does not depend on the set.
   std::vector<int> live = act;
   const SysDesc* one = live.size() == 1 ? &hd_[live[0]] : nullptr;
   const bool pipe = ctx->pipelined && fp32;
@@ -506,54 +540,87 @@ int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* fai
       return MFS_OK;
     }
   }
-  // PCG in runs of iterations; after each run the host reads the
-  // convergence flags and residuals and sizes the next run from the
-  // observed residual decay of the slowest slot.
-  while (cit < max_cap) {
-    const int run = std::min(chunk, max_cap - cit);
+  // PCG in chunks: first_check iterations, then min_run (at most max_run),
+  // one chunk queued ahead of the running one.  The PCG kernels store the
+  // solve's epoch to a system's host-mapped stop flag when it stops; the
+  // host polls the flags and the oldest chunk's completion event, so the
+  // device never idles waiting for the host between chunks, and after the
+  // last stop only the queued launches run (they return at once).  The
+  // stream is synchronised only to shrink the launch set.
+  const int32_t epoch = cg_epoch_;
+  const int32_t* flag = ctx->h_stop;
+  auto stopped = [&](int i) { return __atomic_load_n(flag + i, __ATOMIC_ACQUIRE) == epoch; };
+  const int steady = std::max(1, std::min(ctx->cg_min_run, ctx->cg_max_run));
+  std::deque<std::pair<int, hipEvent_t>> queued;  // (iterations enqueued after the chunk, its completion)
+  auto enqueue = [&](int run) -> int {
     MFS_TRY(enqueue_cg(ctx, dsd, ts_, fp32, run, one, pipe, cit));
     cit += run;
     MFS_HIP(hipGetLastError());
-    MFS_TRY(read_cg(ctx, n, false));
-    attribute_bytes();
-    prof_resolve(ctx);
-    bool all = true;
-    int need = 0;
-    for (int i : act) {
-      if (hg[i].done) continue;
-      all = false;
-      const double rr = hg[i].rr, bb = hg[i].bb;
-      const double rho = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
-      const double tol_i = std::sqrt(pcg_tol2(hc[i], bb));
-      int est = ctx->cg_first_run;
-      SlotState& S = slot_[i];
-      if (S.rho_prev > 0.0 && rho > 0.0 && rho < S.rho_prev && cit > S.it_prev) {
-        const double rate = std::pow(rho / S.rho_prev, 1.0 / (cit - S.it_prev));
-        const double left = std::log(tol_i / rho) / std::log(rate);
-        est = (int)std::ceil(1.1 * left) + 2;
+    hipEvent_t e = nullptr;
+    MFS_TRY(sync_event(ctx, &e));
+    MFS_HIP(hipEventRecord(e, ctx->stream));
+    queued.emplace_back(cit, e);
+    return MFS_OK;
+  };
+  auto drain = [&]() -> int {
+    MFS_HIP(hipStreamSynchronize(ctx->stream));
+    for (auto& qe : queued) ctx->sync_events.push_back(qe.second);
+    queued.clear();
+    return MFS_OK;
+  };
+  int live_tiles = ts_.nv;
+  if (max_cap > 0) MFS_TRY(enqueue(std::min(ctx->cg_first_run, max_cap)));
+  while (!queued.empty()) {
+    if (cit < max_cap && queued.size() < 2) MFS_TRY(enqueue(std::min(steady, max_cap - cit)));
+    bool all = false, shrink = false, front_done = false;
+    for (;;) {
+      all = true;
+      int stopped_tiles = 0;
+      for (int i : live) {
+        if (stopped(i))
+          stopped_tiles += slot_[i].ch->ntv;
+        else
+          all = false;
       }
-      S.rho_prev = rho;
-      S.it_prev = cit;
-      need = std::max(need, est);
+      shrink = live.size() > 1 && 4 * stopped_tiles >= live_tiles;
+      const hipError_t e = hipEventQuery(queued.front().second);
+      if (e != hipSuccess && e != hipErrorNotReady) return set_error(MFS_E_HIP, "PCG chunk: %s", hipGetErrorString(e));
+      front_done = e == hipSuccess;
+      if (all || shrink || front_done) break;
     }
     if (all) break;
-    chunk = std::min(std::max(need, ctx->cg_min_run), ctx->cg_max_run);
-    std::vector<int> still;
-    for (int i : live) {
-      if (hg[i].done) continue;
-      if (cit >= cap[i]) {  // this slot's cap: stop iterating it
-        stopped_at[i] = cit;
-        continue;
-      }
-      still.push_back(i);
+    if (front_done) {
+      ctx->sync_events.push_back(queued.front().second);
+      queued.pop_front();
     }
-    if (still.empty()) break;
-    if (still.size() < live.size()) {
-      live.swap(still);
-      MFS_TRY(tiles_for(live));  // the stream is idle after read_cg
-      one = live.size() == 1 ? &hd_[live[0]] : nullptr;
+    bool capped = false;
+    for (int i : live)
+      if (!stopped(i) && cit >= cap[i]) capped = true;
+    if (shrink || capped) {
+      MFS_TRY(drain());
+      std::vector<int> still;
+      for (int i : live) {
+        if (stopped(i)) continue;
+        if (cit >= cap[i]) {  // this slot's cap: stop iterating it
+          stopped_at[i] = cit;
+          continue;
+        }
+        still.push_back(i);
+      }
+      if (still.empty()) break;
+      if (still.size() < live.size()) {
+        live.swap(still);
+        MFS_TRY(tiles_for(live));  // the stream is idle
+        one = live.size() == 1 ? &hd_[live[0]] : nullptr;
+        live_tiles = ts_.nv;
+      }
+      if (cit < max_cap) MFS_TRY(enqueue(std::min(steady, max_cap - cit)));
     }
   }
+  MFS_TRY(drain());
+  MFS_TRY(read_cg(ctx, n, false));
+  attribute_bytes();
+  prof_resolve(ctx);
   if (live.size() != act.size()) MFS_TRY(tiles_for(act));
   for (int i : act) {
     const bool ok = hg[i].done == 1;
@@ -708,6 +775,8 @@ int Engine::step() {
     hc[i].cg_adaptive = (o_.cg_adaptive && slot_[i].phase == 1) ? 1 : 0;
     hc[i].cg_cap = fp32_ ? fp32_cap(slot_[i].ch) : o_.cg_max;
   }
+  cg_epoch_ = ++ctx->cg_epoch;
+  for (int i : act) hc[i].cg_epoch = cg_epoch_;
   MFS_TRY(upload_ctrl(ctx, n));
   {
     ProfScope ps(ctx, MFS_K_ELEMENT);
@@ -731,6 +800,9 @@ int Engine::step() {
     // FP32 could not solve these Newton systems (ill-conditioned beyond
     // single precision): element records, assembly and PCG again in FP64
     MFS_TRY(tiles_for(redo));
+    cg_epoch_ = ++ctx->cg_epoch;
+    for (int i : redo) hc[i].cg_epoch = cg_epoch_;
+    MFS_TRY(upload_ctrl(ctx, n));
     {
       ProfScope ps(ctx, MFS_K_ELEMENT);
       launch_element(st, dsd, dctrl, ts_.dt, ts_.nt, 0);

@@ -27,8 +27,6 @@ struct SlotState {
   bool E_known = false;
   double grad = NAN, step = NAN, relres = NAN;
   // PCG residual history (run sizing)
-  double rho_prev = -1.0;
-  int it_prev = 0;
   // line search
   double alpha = 0.0;
   // pose homotopy (load stepping): start pose (R0, t0), target (R1, t1),
@@ -46,6 +44,10 @@ struct TileSet {
 };
 
 int upload_ctrl(mfs_context* ctx, int count);
+// Host-mapped PCG stop flags for `slots` slots (grow-only; zeroed when made).
+int ensure_stop_flags(mfs_context* ctx, int slots);
+// An event (no timing) from the context's pool.
+int sync_event(mfs_context* ctx, hipEvent_t* out);
 int read_cg(mfs_context* ctx, int count, bool resolve = true);
 int read_red(mfs_context* ctx, int count);
 // Tiles of the listed slots (indices into by_slot), uploaded to the
@@ -103,6 +105,7 @@ class Engine {
   mfs_context* ctx_;
   mfs_solve_opts o_{};
   int fp32_ = 0;
+  int32_t cg_epoch_ = 0;  // epoch of the PCG solve being run
   std::vector<SlotState> slot_;
   std::vector<SysDesc> hd_;
   bool desc_dirty_ = true;

@@ -125,6 +125,11 @@ struct mfs_context {
   std::vector<mfs::Ctrl> h_ctrl;           // host copies of the per-slot controls
   std::vector<mfs::Tile> h_tiles;          // host copy of the current tile list
   mfs::UploadRing up;                      // every host-to-device upload of the stream
+  int32_t* h_stop = nullptr;               // host-mapped PCG stop flags, one per slot
+  int32_t* d_stop = nullptr;               // their device address
+  int stop_slots = 0;
+  int32_t cg_epoch = 0;                    // last PCG solve number handed out
+  std::vector<hipEvent_t> sync_events;     // completion events of queued PCG chunks
   // HIP-event profiler (mfs_profile_enable)
   int prof_stride = 0;
   double prof_ms[MFS_K_FAMILIES] = {};

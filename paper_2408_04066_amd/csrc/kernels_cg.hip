@@ -107,6 +107,7 @@ __global__ __launch_bounds__(64) void k_cg_init(const SysDesc* __restrict__ sd, 
       st->iters = 0;
       st->done = srr <= pcg_tol2(*S.ctrl, sbb) * sbb ? 1 : 0;
       st->arrive_init = 0;
+      if (st->done) signal_stop(S);
     }
   }
 }
@@ -149,6 +150,7 @@ __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict_
           if (conv && st->done == 0) {
             st->done = 1;
             st->iters = it;
+            signal_stop(S);
           }
           if (!conv) st->it_b = it;
         }
@@ -302,6 +304,7 @@ __global__ __launch_bounds__(64) void k_cg_update(const SysDesc* __restrict__ sd
       if (srr <= pcg_tol2(*S.ctrl, bb) * bb) {
         st->done = 1;
         st->iters = it + 1;
+        signal_stop(S);
       }
       st->arrive_update = 0;
     }
@@ -437,6 +440,7 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_start(const SysDesc* __restric
           if (c) {
             st->done = 1;
             st->iters = 0;
+            signal_stop(S);
           }
         }
       }
@@ -575,6 +579,7 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_iter(const SysDesc* __restrict
       if (t.local == 0 && threadIdx.x == 0) {
         st->rr = rr;
         st->done = 1;
+        signal_stop(S);
       }
       return;
     }
@@ -583,7 +588,10 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_iter(const SysDesc* __restrict
   const double beta = gam / g_prev;
   const double den = del - beta * gam / a_prev;
   if (!(den > 0.0) || !(gam > 0.0)) {  // breakdown (lost positive definiteness in rounding): stop here
-    if (t.local == 0 && threadIdx.x == 0) st->done = 2;  // reported as not converged
+    if (t.local == 0 && threadIdx.x == 0) {
+      st->done = 2;  // reported as not converged
+      signal_stop(S);
+    }
     return;
   }
   const double alpha = gam / den;
@@ -639,7 +647,10 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_iter(const SysDesc* __restrict
       st->d = sdl;
       st->rr = srr;
       st->iters += 1;
-      if (srr <= pcg_tol2(*S.ctrl, st->bb) * st->bb) st->done = 1;
+      if (srr <= pcg_tol2(*S.ctrl, st->bb) * st->bb) {
+        st->done = 1;
+        signal_stop(S);
+      }
       st->arrive_pipe = 0;
     }
   }

@@ -81,6 +81,8 @@ mfs_context::~mfs_context() {
     (void)hipEventDestroy(p.b);
   }
   for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : sync_events) (void)hipEventDestroy(e);
+  if (h_stop) (void)hipHostFree(h_stop);
 }
 
 using namespace mfs;
