@@ -354,6 +354,32 @@ __device__ __forceinline__ double coherent_sum(const double* plane, int count) {
   return wave_sum(acc);
 }
 
+// This lane's terms of the fixed-order sums of three partial planes (lane l
+// adds tiles l, l + 64, ... in sequence, as sys_sum does), with the loads of
+// four terms per plane issued before their additions.
+__device__ __forceinline__ void lane_sums3(const double* a, const double* b, const double* c, int count,
+                                           double& sa, double& sb, double& sc) {
+  sa = sb = sc = 0.0;
+  for (int i0 = threadIdx.x & 63; i0 < count; i0 += 256) {
+    double va[4], vb[4], vc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + 64 * u < count ? i0 + 64 * u : i0;
+      va[u] = a[i];
+      vb[u] = b[i];
+      vc[u] = c[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (i0 + 64 * u < count) {
+        sa += va[u];
+        sb += vb[u];
+        sc += vc[u];
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ double sys_max(const double* plane, int count) {
   double acc = 0.0;
   for (int i0 = threadIdx.x & 63; i0 < count; i0 += 256) {

@@ -113,69 +113,83 @@ __global__ __launch_bounds__(64) void k_cg_init(const SysDesc* __restrict__ sd, 
 }
 
 // Search direction p_it = z + beta p_{it-1} and q = K p_it: one pass of 64
-// rows, LPR lanes per row; partial p.q.
+// rows, LPR lanes per row; partial p.q.  What the launch reads and no
+// workgroup of it writes (the PCG state, the row's block range, the row's z
+// and both p buffers, the partial sums of the previous launches) is loaded
+// at its head, so those loads overlap; in all-read mode every wave folds the
+// sums itself (same order in each), with no barrier before the SpMV.
 template <typename T, int LPR, bool ONE>
 __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
                                                       int ntiles, const SysDesc one) {
   __shared__ double red[LPR];
-  __shared__ double bcast[2];
   __shared__ int last;
   const Tile t = vertex_tile<ONE>(tiles, ntiles, one);
   const SysDesc& S = ONE ? one : sd[t.sys];
   CgState* st = S.cg;
+  const int lane = threadIdx.x % LPR;
+  const int row = t.begin + threadIdx.x / LPR;
+  const bool valid = row < t.end;
+  const T* z = (const T*)S.z;
+  const int rb = valid ? S.rowptr[row] : 0;
+  const int re = valid ? S.rowptr[row + 1] : 0;
+  T oz[3] = {0, 0, 0}, op0[3] = {0, 0, 0}, op1[3] = {0, 0, 0};
+  if (valid && lane == 0) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      oz[i] = z[3 * row + i];
+      op0[i] = ((const T*)S.p0)[3 * row + i];
+      op1[i] = ((const T*)S.p1)[3 * row + i];
+    }
+  }
+  double lrr = 0.0, lbb = 0.0, lz0 = 0.0, lz1 = 0.0, lunused = 0.0;
+  if (!S.ticket) {
+    lane_sums3(S.part + P_RR * S.ptile, S.part + P_BB * S.ptile, S.part + P_RZ0 * S.ptile, S.ntv, lrr, lbb, lz0);
+    lane_sums3(S.part + P_RZ1 * S.ptile, S.part + P_RZ1 * S.ptile, S.part + P_RZ1 * S.ptile, S.ntv, lz1, lunused,
+               lunused);
+  }
+  const int stopped = st->done;
+  const int it_t = st->it, it_all = st->it_a;
+  const double rz_t = st->rz, rzp_t = st->rz_prev;
+  const Ctrl ctrl = *S.ctrl;
   int it;
   double beta;
   if (S.ticket) {
-    if (st->done) return;
-    it = st->it;
-    beta = it == 0 ? 0.0 : st->rz / st->rz_prev;
+    if (stopped) return;
+    it = it_t;
+    beta = it == 0 ? 0.0 : rz_t / rzp_t;
   } else {
-    // all-read: wave 0 folds this system's partials, the workgroup shares them
-    it = st->it_a;
-    if (threadIdx.x < 64) {
-      const double* part = S.part;
-      const double rr = sys_sum(part + P_RR * S.ptile, S.ntv);
-      const double bb = sys_sum(part + P_BB * S.ptile, S.ntv);
-      const bool conv = rr <= pcg_tol2(*S.ctrl, bb) * bb;
-      double b = 0.0;
-      if (!conv && it > 0)
-        b = sys_sum(part + (P_RZ0 + (it & 1)) * S.ptile, S.ntv) /
-            sys_sum(part + (P_RZ0 + ((it + 1) & 1)) * S.ptile, S.ntv);
-      if (threadIdx.x == 0) {
-        bcast[0] = conv ? 1.0 : 0.0;
-        bcast[1] = b;
-        if (t.local == 0) {
-          st->rr = rr;
-          st->bb = bb;
-          if (conv && st->done == 0) {
-            st->done = 1;
-            st->iters = it;
-            signal_stop(S);
-          }
-          if (!conv) st->it_b = it;
-        }
+    it = it_all;
+    const double rr = wave_sum(lrr);
+    const double bb = wave_sum(lbb);
+    const double rz0 = wave_sum(lz0), rz1 = wave_sum(lz1);
+    const bool conv = rr <= pcg_tol2(ctrl, bb) * bb;
+    if (t.local == 0 && threadIdx.x == 0) {
+      st->rr = rr;
+      st->bb = bb;
+      if (conv && st->done == 0) {
+        st->done = 1;
+        st->iters = it;
+        signal_stop(S);
       }
+      if (!conv) st->it_b = it;
     }
-    __syncthreads();
-    if (bcast[0] != 0.0) return;
-    beta = bcast[1];
+    if (conv) return;
+    beta = 0.0;
+    if (it > 0) beta = (it & 1 ? rz1 : rz0) / (it & 1 ? rz0 : rz1);
   }
   const T tb = (T)beta;
   T* pn = (T*)((it & 1) ? S.p1 : S.p0);
   const T* po = (const T*)((it & 1) ? S.p0 : S.p1);
-  const T* z = (const T*)S.z;
   const T* vals = (const T*)S.vals;
   T* q = (T*)S.q;
   const size_t nz = S.nnzb;
-  const int lane = threadIdx.x % LPR;
-  const int row = t.begin + threadIdx.x / LPR;
   T a0 = 0, a1 = 0, a2 = 0;
-  if (row < t.end) {
+  {
     // batches of U blocks per lane: indices and values first, then the
     // gathers (two dependent latencies per batch, not per block)
     constexpr int U = LPR >= 16 ? 1 : 16 / LPR;
-    const int e = S.rowptr[row + 1];
-    for (int base = S.rowptr[row] + lane; base < e; base += U * LPR) {
+    const int e = re;
+    for (int base = rb + lane; base < e; base += U * LPR) {
       int c[U];
       T a[U][9];
 #pragma unroll
@@ -212,12 +226,13 @@ __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict_
   a1 = group_sum<LPR>(a1);
   a2 = group_sum<LPR>(a2);
   double dot = 0.0;
-  if (row < t.end && lane == 0) {
-    T p0 = z[3 * row], p1 = z[3 * row + 1], p2 = z[3 * row + 2];
+  if (valid && lane == 0) {
+    const T* pold = (it & 1) ? op0 : op1;
+    T p0 = oz[0], p1 = oz[1], p2 = oz[2];
     if (it) {
-      p0 += tb * po[3 * row];
-      p1 += tb * po[3 * row + 1];
-      p2 += tb * po[3 * row + 2];
+      p0 += tb * pold[0];
+      p1 += tb * pold[1];
+      p2 += tb * pold[2];
     }
     pn[3 * row] = p0;
     pn[3 * row + 1] = p1;
@@ -240,7 +255,10 @@ __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict_
 
 // alpha = r.z / p.q; x += alpha p; r -= alpha q; z = M^-1 r; partials r.z
 // and r.r.  Ticket mode: the last workgroup folds them, advances the
-// iteration and decides convergence with this Newton step's tolerance.
+// iteration and decides convergence with this Newton step's tolerance.  The
+// row's vectors, its preconditioner block, the PCG state and (all-read) the
+// partial sums are loaded at the head, before the convergence flag is
+// tested.
 template <typename T, bool ONE>
 __global__ __launch_bounds__(64) void k_cg_update(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
                                                   int ntiles, const SysDesc one) {
@@ -248,35 +266,57 @@ __global__ __launch_bounds__(64) void k_cg_update(const SysDesc* __restrict__ sd
   const Tile t = vertex_tile<ONE>(tiles, ntiles, one);
   const SysDesc& S = ONE ? one : sd[t.sys];
   CgState* st = S.cg;
-  if (st->done) return;
-  int it;
-  double rz_old, pq;
-  if (S.ticket) {
-    it = st->it;
-    rz_old = st->rz;
-    pq = st->pq;
-  } else {
-    it = st->it_b;
-    pq = sys_sum(S.part + P_PQ * S.ptile, S.ntv);
-    rz_old = sys_sum(S.part + (P_RZ0 + (it & 1)) * S.ptile, S.ntv);
-  }
-  const T alpha = (T)(rz_old / pq);
-  const T* pn = (const T*)((it & 1) ? S.p1 : S.p0);
-  const T* q = (const T*)S.q;
+  const int row = t.begin + threadIdx.x;
+  const bool valid = row < t.end;
   T* r = (T*)S.r;
   T* z = (T*)S.z;
   T* xc = (T*)S.xc;
-  const int row = t.begin + threadIdx.x;
+  const T* q = (const T*)S.q;
+  T oq[3] = {0, 0, 0}, orr[3] = {0, 0, 0}, ox[3] = {0, 0, 0}, op0[3] = {0, 0, 0}, op1[3] = {0, 0, 0};
+  T mb[6] = {0, 0, 0, 0, 0, 0};
+  if (valid) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      oq[i] = q[3 * row + i];
+      orr[i] = r[3 * row + i];
+      ox[i] = xc[3 * row + i];
+      op0[i] = ((const T*)S.p0)[3 * row + i];
+      op1[i] = ((const T*)S.p1)[3 * row + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) mb[i] = ((const T*)S.minv)[6 * row + i];
+  }
+  double lpq = 0.0, lz0 = 0.0, lz1 = 0.0;
+  if (!S.ticket)
+    lane_sums3(S.part + P_PQ * S.ptile, S.part + P_RZ0 * S.ptile, S.part + P_RZ1 * S.ptile, S.ntv, lpq, lz0, lz1);
+  const int stopped = st->done;
+  const int it_t = st->it, it_all = st->it_b;
+  const double rz_t = st->rz, pq_t = st->pq;
+  if (stopped) return;
+  int it;
+  double rz_old, pq;
+  if (S.ticket) {
+    it = it_t;
+    rz_old = rz_t;
+    pq = pq_t;
+  } else {
+    it = it_all;
+    pq = wave_sum(lpq);
+    const double rz0 = wave_sum(lz0), rz1 = wave_sum(lz1);
+    rz_old = (it & 1) ? rz1 : rz0;
+  }
+  const T alpha = (T)(rz_old / pq);
   double rzn = 0.0, rrn = 0.0;
-  if (row < t.end) {
+  if (valid) {
+    const T* pn = (it & 1) ? op1 : op0;
     T rv[3], zv[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      xc[3 * row + i] += alpha * pn[3 * row + i];
-      rv[i] = r[3 * row + i] - alpha * q[3 * row + i];
+      xc[3 * row + i] = ox[i] + alpha * pn[i];
+      rv[i] = orr[i] - alpha * oq[i];
       r[3 * row + i] = rv[i];
     }
-    precondition((const T*)S.minv + 6 * row, rv, zv);
+    precondition(mb, rv, zv);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       z[3 * row + i] = zv[i];
@@ -388,31 +428,6 @@ __device__ __forceinline__ void row_product(const SysDesc& S, const V* __restric
   row_range_product<T, V, LPR>(S, v, rb, re, lane, acc);
 }
 
-// This lane's terms of the fixed-order sums of three partial planes (lane l
-// adds tiles l, l + 64, ... in sequence, as sys_sum does), with the loads of
-// four terms per plane issued before their additions.
-__device__ __forceinline__ void lane_sums3(const double* a, const double* b, const double* c, int count,
-                                           double& sa, double& sb, double& sc) {
-  sa = sb = sc = 0.0;
-  for (int i0 = threadIdx.x & 63; i0 < count; i0 += 256) {
-    double va[4], vb[4], vc[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = i0 + 64 * u < count ? i0 + 64 * u : i0;
-      va[u] = a[i];
-      vb[u] = b[i];
-      vc[u] = c[i];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (i0 + 64 * u < count) {
-        sa += va[u];
-        sb += vb[u];
-        sc += vc[u];
-      }
-    }
-  }
-}
 
 // After k_cg_init (r = b, x = 0, u = M^-1 r, partials r.r and b.b):
 // w = K u, m_0 = M^-1 w, recurrences cleared, partials gamma_0 and delta_0.
