@@ -21,7 +21,8 @@ invariants, posed-space equivariance and dense-vs-sparse solves.
 from .mfem import (ARAP, COROT, NH, lame, vech, unvech, sym_basis, rest_shape,
                    shape_gradients, deformation_operator, rotation_operator,
                    mixed_operator, psi, dpsi, d2psi, stretch_gradient, stretch_hessian,
-                   polar, polar_stretch, cluster_by_segments, pin_targets, Frame,
+                   polar, polar_stretch, cluster_by_segments, blend_weights, blend_rotations,
+                   pin_targets, Frame,
                    solve_frame, interpolate_pose, energy, gradient, hessian, stress,
                    DegenerateElement)
 
@@ -30,6 +31,6 @@ __all__ = [
     "shape_gradients", "deformation_operator", "rotation_operator", "mixed_operator",
     "psi", "dpsi", "d2psi", "stretch_gradient", "stretch_hessian", "polar",
     "polar_stretch", "cluster_by_segments", "pin_targets", "Frame", "solve_frame",
-    "interpolate_pose", "stress",
+    "interpolate_pose", "stress", "blend_weights", "blend_rotations",
     "energy", "gradient", "hessian", "DegenerateElement",
 ]

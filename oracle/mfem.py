@@ -55,7 +55,18 @@ Extension beyond the paper's per-frame statement: external vertex forces
 f_ext (the local-perturbation experiment of Section 4) enter as the
 potential -f_ext . x, i.e. b += f_ext in the Newton system; problems carry
 them as ``force_vertex`` (indices, repeats add up) and ``force`` (k x 3).
+
+Rotation smoothing (reading R15; the paper names rotation discontinuities at
+cluster boundaries as its main limitation and leaves smoothing to future
+work): with ``blend_handles``/``blend_weights`` (m x K, from blend_weights) a
+tet's rotation is the rotation factor of the polar decomposition of the
+weighted sum of its handles' rotations, instead of its cluster's rotation.
+
+Stress recovery (f2): ``stress`` returns P_k = dPsi/dS at S_k(x) and the
+world-frame multiplier W_k R_k P_k.
 """
+
+import math
 
 import numpy as np
 import scipy.sparse as sp
@@ -300,6 +311,76 @@ def cluster_by_segments(X, T, seg_a, seg_b, seg_handle):
     return np.asarray(seg_handle, dtype=np.int32)[np.argmin(d2, axis=1)]
 
 
+# ----------------------------------------------------------------------------
+# Rotation smoothing across cluster boundaries (the paper's stated limitation
+# and future work; reading R15): a tet blends the rotations of the handles
+# whose bone segments lie within `width` of its nearest one, and the blend is
+# projected back onto the rotations by the polar decomposition.
+# ----------------------------------------------------------------------------
+
+def blend_weights(X, T, seg_a, seg_b, seg_handle, width, kmax):
+    """Per tet, kmax (handle, weight) pairs.  Distances d are from the tet's
+    barycenter to the bone segments (as cluster_by_segments); a handle's
+    distance is that of its nearest segment.  The handle of the nearest
+    segment (the cluster rule, ties to the lowest segment index) comes first
+    with weight 1; every other handle h with d_h - d_min < width follows with
+    weight 1 - (d_h - d_min) / width, in decreasing weight (ties: lower handle
+    index first); the first kmax are kept and divided by their sum (added in
+    that order).  Unused entries: handle -1, weight 0."""
+    X = np.asarray(X, dtype=np.float64)
+    T = np.asarray(T, dtype=np.int64)
+    seg_handle = np.asarray(seg_handle, dtype=np.int64)
+    bary = X[T].mean(axis=1)
+    m = T.shape[0]
+    d2 = np.empty((m, len(seg_a)))
+    for s in range(len(seg_a)):
+        a = np.asarray(seg_a[s], dtype=np.float64)
+        d = np.asarray(seg_b[s], dtype=np.float64) - a
+        dd = float(d @ d)
+        u = np.zeros(m) if dd == 0.0 else np.clip((bary - a) @ d / dd, 0.0, 1.0)
+        q = a + u[:, None] * d
+        d2[:, s] = ((bary - q) ** 2).sum(axis=1)
+    handles = np.full((m, kmax), -1, dtype=np.int32)
+    weights = np.zeros((m, kmax))
+    hs = sorted(set(seg_handle.tolist()))
+    for k in range(m):
+        s0 = int(np.argmin(d2[k]))
+        h0 = int(seg_handle[s0])
+        dmin = math.sqrt(d2[k, s0])
+        cand = []
+        for h in hs:
+            if h == h0:
+                continue
+            dh = math.sqrt(min(d2[k, s] for s in range(len(seg_a)) if seg_handle[s] == h))
+            if width > 0.0 and dh - dmin < width:
+                cand.append((1.0 - (dh - dmin) / width, h))
+        cand.sort(key=lambda c: (-c[0], c[1]))
+        chosen = [(1.0, h0)] + cand[: kmax - 1]
+        total = 0.0
+        for w, _ in chosen:
+            total += w
+        for j, (w, h) in enumerate(chosen):
+            handles[k, j] = h
+            weights[k, j] = w / total
+    return handles, weights
+
+
+def blend_rotations(R, handles, weights):
+    """R_k = polar(sum_j w_kj R_{h_kj}) (the rotation factor).  A tet with a
+    single handle takes that handle's rotation as it is; where the blend has
+    det <= 0 the tet keeps the rotation of its first handle."""
+    R = np.asarray(R, dtype=np.float64)
+    handles = np.asarray(handles)
+    M = np.zeros((handles.shape[0], 3, 3))
+    for j in range(handles.shape[1]):
+        ok = handles[:, j] >= 0
+        M[ok] += weights[ok, j, None, None] * R[handles[ok, j]]
+    U, _ = polar(M)
+    keep = (np.linalg.det(M) <= 0.0) | (np.sum(handles >= 0, axis=1) == 1)
+    U[keep] = R[handles[keep, 0]]
+    return U
+
+
 def pin_targets(X, pin_vertex, pin_handle, R, t):
     """x_p = R_h X_p + t_h for each pin (reading R7)."""
     Xp = np.asarray(X)[pin_vertex]
@@ -326,7 +407,10 @@ class Frame:
             clusters = cluster_by_segments(self.X, self.T, prob["seg_a"], prob["seg_b"],
                                            prob["seg_handle"])
         self.cluster = np.asarray(clusters, dtype=np.int32)
-        self.Rk = np.asarray(R, dtype=np.float64)[self.cluster]
+        if prob.get("blend_handles") is not None:  # rotation smoothing (R15)
+            self.Rk = blend_rotations(R, prob["blend_handles"], prob["blend_weights"])
+        else:
+            self.Rk = np.asarray(R, dtype=np.float64)[self.cluster]
         self.B = deformation_operator(self.G)
         self.J = mixed_operator(self.Rk, self.G)
         self.pin_vertex = np.asarray(prob["pin_vertex"], dtype=np.int64)

@@ -6,6 +6,8 @@ polar decomposition, a dense brute-force KKT solve, rest/rigid invariants,
 posed-space equivariance, dense-vs-sparse solves and brute-force clustering.
 """
 
+import math
+
 import numpy as np
 import pytest
 import scipy.linalg
@@ -466,3 +468,95 @@ def test_stress_recovery_balances_element_forces():
     xb[[a, b]] = xb[[b, a]]
     P6b, _ = oracle.stress(prob, pose, xb)
     assert np.all(np.isnan(P6b[k]))
+
+
+def _axis_rot(axis, ang):
+    axis = np.asarray(axis, dtype=np.float64) / np.linalg.norm(axis)
+    K = np.array([[0, -axis[2], axis[1]], [axis[2], 0, -axis[0]], [-axis[1], axis[0], 0]])
+    return np.eye(3) + math.sin(ang) * K + (1 - math.cos(ang)) * K @ K
+
+
+def test_blend_rotations_closed_form_about_one_axis():
+    """Rotation smoothing (R15): blending rotations about one axis by angles a
+    and b with weights w, 1 - w gives the rotation by arg(w e^{ia} + (1-w) e^{ib})
+    about that axis (the in-plane part is a scaled rotation); one handle
+    reproduces its rotation; the result is a proper rotation."""
+    rng = np.random.default_rng(3)
+    axis = rng.normal(size=3)
+    cases = [(0.3, -0.5, 0.5), (1.1, 0.2, 0.25), (-0.7, 0.9, 0.8), (2.0, 2.6, 0.6)]
+    R = np.stack([_axis_rot(axis, a) for a, _, _ in cases] + [_axis_rot(axis, b) for _, b, _ in cases])
+    nc = len(cases)
+    handles = np.array([[i, nc + i] for i in range(nc)] + [[i, -1] for i in range(nc)], dtype=np.int32)
+    weights = np.array([[w, 1 - w] for _, _, w in cases] + [[1.0, 0.0]] * nc)
+    U = oracle.blend_rotations(R, handles, weights)
+    for i, (a, b, w) in enumerate(cases):
+        ang = np.angle(w * np.exp(1j * a) + (1 - w) * np.exp(1j * b))
+        assert np.allclose(U[i], _axis_rot(axis, ang), atol=1e-13)
+        assert np.allclose(U[nc + i], R[i], atol=1e-15)
+    assert np.allclose(np.einsum("kji,kjl->kil", U, U), np.eye(3), atol=1e-13)
+    assert np.all(np.linalg.det(U) > 0)
+    # a blend with det <= 0 keeps the first handle's rotation
+    Rb = np.stack([np.eye(3), np.diag([1.0, -1.0, -1.0]), np.diag([-1.0, 1.0, -1.0])])
+    Ub = oracle.blend_rotations(Rb, np.array([[0, 1, 2], [1, 0, 2]], dtype=np.int32),
+                                np.array([[0.2, 0.4, 0.4], [0.4, 0.2, 0.4]]))
+    assert np.array_equal(Ub[0], np.eye(3)) and np.array_equal(Ub[1], Rb[1])
+
+
+def test_blend_weights_brute_force_and_cluster_limit():
+    """blend_weights against a per-tet brute force written from its
+    definition on a small mesh with several segments per handle, and the
+    cluster rule in the limit of zero width."""
+    from workloads import humanoid
+    prob = humanoid(61, target_tets=600, n_bones=6)
+    X, T = prob["X"], prob["T"]
+    sa, sb, sh = prob["seg_a"], prob["seg_b"], prob["seg_handle"]
+    width = 0.3
+    H, Wt = oracle.blend_weights(X, T, sa, sb, sh, width, 3)
+    bary = X[T].mean(axis=1)
+    def dist(p, a, b):
+        a, b = np.asarray(a, float), np.asarray(b, float)
+        d = b - a
+        u = 0.0 if d @ d == 0 else min(1.0, max(0.0, (p - a) @ d / (d @ d)))
+        return float(np.linalg.norm(p - (a + u * d)))
+    for k in range(0, len(T), 7):
+        ds = [dist(bary[k], sa[s], sb[s]) for s in range(len(sa))]
+        s0 = int(np.argmin(ds))
+        per_h = {}
+        for s, d in enumerate(ds):
+            per_h[int(sh[s])] = min(per_h.get(int(sh[s]), np.inf), d)
+        h0 = int(sh[s0])
+        others = sorted(((1 - (d - ds[s0]) / width, h) for h, d in per_h.items() if h != h0 and d - ds[s0] < width),
+                        key=lambda c: (-c[0], c[1]))[:2]
+        exp_h = [h0] + [h for _, h in others]
+        exp_w = np.array([1.0] + [w for w, _ in others])
+        exp_w /= exp_w.sum()
+        got_h = [h for h in H[k] if h >= 0]
+        assert got_h == exp_h, (k, got_h, exp_h)
+        assert np.allclose(Wt[k, :len(exp_h)], exp_w, rtol=0, atol=1e-12)
+        assert np.all(Wt[k, len(exp_h):] == 0)
+    H0, W0 = oracle.blend_weights(X, T, sa, sb, sh, 0.0, 3)
+    assert np.array_equal(H0[:, 0], oracle.cluster_by_segments(X, T, sa, sb, sh))
+    assert np.all(W0[:, 0] == 1.0) and np.all(H0[:, 1:] == -1)
+
+
+def test_smoothed_rotations_rigid_pose_and_zero_width():
+    """A frame with smoothed rotations: a rigid pose (every handle at the same
+    transform) still gives the rigidly moved rest shape, and zero blend width
+    gives exactly the cluster frame's solution."""
+    prob = humanoid(63, target_tets=1200, n_bones=8)
+    H, Wt = oracle.blend_weights(prob["X"], prob["T"], prob["seg_a"], prob["seg_b"], prob["seg_handle"], 0.4, 3)
+    assert np.any(H[:, 1] >= 0)  # some tets blend
+    pb = dict(prob, blend_handles=H, blend_weights=Wt)
+    nh = prob["n_handles"]
+    Q = euler_xyz(0.5, -0.3, 1.2)
+    c = np.array([0.2, 1.0, -0.5])
+    r = oracle.solve_frame(pb, (np.stack([Q] * nh), np.stack([c] * nh)), iterations=4)
+    assert r["status"] == "ok"
+    assert np.max(np.abs(r["x"] - (prob["X"] @ Q.T + c))) <= 1e-12 * prob["bbox_diag"]
+    pose = random_pose(prob, 64, amp_deg=20)
+    H0, W0 = oracle.blend_weights(prob["X"], prob["T"], prob["seg_a"], prob["seg_b"], prob["seg_handle"], 0.0, 3)
+    r0 = oracle.solve_frame(dict(prob, blend_handles=H0, blend_weights=W0), pose, iterations=3)
+    rc = oracle.solve_frame(prob, pose, iterations=3)
+    assert np.array_equal(r0["x"], rc["x"])
+    rs = oracle.solve_frame(pb, pose, iterations=3)
+    assert np.max(np.abs(rs["x"] - rc["x"])) > 1e-6 * prob["bbox_diag"]  # smoothing changes the frame
