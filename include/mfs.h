@@ -230,6 +230,37 @@ int mfs_cluster_by_segments(mfs_context* ctx, const double* X, int64_t n,
                             const double* seg_a, const double* seg_b,
                             const int32_t* seg_handle, int32_t* out, int32_t memory_space);
 
+/* Rotation smoothing across cluster boundaries.  The paper names the
+ * rotation discontinuities between clusters as its main limitation and
+ * leaves smoothing to future work (Section 5, Limitations; Section 4,
+ * rotation clustering); this is one reading of it.  Per tet, with d the
+ * distance from the barycenter to a bone segment (as in
+ * mfs_cluster_by_segments) and a handle's distance that of its nearest
+ * segment: the handle of the nearest segment first, weight 1; then the other
+ * handles h with d_h < d_min + width, weight 1 - (d_h - d_min) / width, in
+ * decreasing weight (ties: lower handle index first); at most kmax (1..4) in
+ * all, the weights divided by their sum.  Unused entries: handle -1, weight
+ * 0.  out_handles, out_weights: m x kmax row-major.  width = 0 reproduces
+ * the clusters.  All arrays host or device per memory_space; returns after
+ * the outputs are written. */
+int mfs_blend_weights(mfs_context* ctx, const double* X, int64_t n, const int32_t* tets, int64_t m,
+                      int32_t nseg, const double* seg_a, const double* seg_b, const int32_t* seg_handle,
+                      int32_t n_handles, double width, int32_t kmax, int32_t* out_handles,
+                      double* out_weights, int32_t memory_space);
+
+/* Smoothed tet rotations for later solves, evaluations and stress
+ * recovery: for every pose, R_k = the rotation factor of the polar
+ * decomposition of sum_j w_kj R_{h_kj} (the handle rotation itself for a
+ * tet with one handle, or where the blend has det <= 0) replaces the
+ * rotation of the tet's cluster.  handles, weights: m x kmax row-major in
+ * the caller's tet order (e.g. from mfs_blend_weights); the first handle of
+ * every tet must be valid, -1 marks unused entries, weights finite and >= 0
+ * (their scale does not matter).  handles = NULL returns to cluster
+ * rotations.  Synchronises the context's stream; not while a frame of the
+ * character is in flight.  Pins keep following their handles. */
+int mfs_character_set_rotation_blend(mfs_character* ch, int32_t kmax, const int32_t* handles,
+                                     const double* weights, int32_t memory_space);
+
 /* ---- solving ------------------------------------------------------------ */
 
 /* Solve one frame (Algorithm 1, one pose).  handle_R: n_handles x 9 and

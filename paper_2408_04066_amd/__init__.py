@@ -28,7 +28,8 @@ WARM_REST, WARM_PREVIOUS = 0, 1
 EXPORTED = ("mfs_default_opts", "mfs_status_string", "mfs_last_error", "mfs_context_create",
             "mfs_context_destroy", "mfs_character_create", "mfs_character_destroy",
             "mfs_character_footprint", "mfs_cluster_by_segments", "mfs_solve_frame",
-            "mfs_solve_batch", "mfs_evaluate", "mfs_polar", "mfs_character_get_info",
+            "mfs_solve_batch", "mfs_evaluate", "mfs_polar", "mfs_blend_weights",
+            "mfs_character_set_rotation_blend", "mfs_character_get_info",
             "mfs_profile_enable", "mfs_profile_read", "mfs_context_get_tuning",
             "mfs_context_set_tuning", "mfs_character_release_workspace", "mfs_default_server_opts",
             "mfs_server_create", "mfs_server_destroy", "mfs_server_submit", "mfs_server_poll",
@@ -137,6 +138,9 @@ def lib():
                                            P(SolveStats)]),
         "mfs_evaluate": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),
         "mfs_polar": (ctypes.c_int, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, c_vp, c_i32]),
+        "mfs_blend_weights": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, c_i32,
+                                             c_dbl, c_i32, c_vp, c_vp, c_i32]),
+        "mfs_character_set_rotation_blend": (ctypes.c_int, [c_vp, c_i32, c_vp, c_vp, c_i32]),
         "mfs_character_get_info": (ctypes.c_int, [c_vp, P(CharacterInfo)]),
         "mfs_profile_enable": (ctypes.c_int, [c_vp, c_i32]),
         "mfs_profile_read": (ctypes.c_int, [c_vp, P(Profile), c_i32]),
@@ -256,6 +260,21 @@ class Context:
                                              len(sh), _ptr(sa), _ptr(sb), _ptr(sh), _ptr(out), MEM_HOST))
         return out
 
+    def blend_weights(self, X, T, seg_a, seg_b, seg_handle, n_handles, width, kmax=3):
+        """Rotation-smoothing weights (``mfs_blend_weights``): (handles, weights),
+        each (m, kmax)."""
+        X = _host(X, np.float64)
+        T = _host(T, np.int32)
+        sa, sb = _host(seg_a, np.float64), _host(seg_b, np.float64)
+        sh = _host(seg_handle, np.int32)
+        m = T.shape[0]
+        H = np.empty((m, kmax), dtype=np.int32)
+        W = np.empty((m, kmax))
+        _check(lib().mfs_blend_weights(self.handle, _ptr(X), X.shape[0], _ptr(T), m, len(sh), _ptr(sa), _ptr(sb),
+                                       _ptr(sh), int(n_handles), float(width), int(kmax), _ptr(H), _ptr(W),
+                                       MEM_HOST))
+        return H, W
+
     def polar(self, F, precision=FP64):
         F = _host(F, np.float64).reshape(-1, 9)
         c = F.shape[0]
@@ -318,6 +337,8 @@ class Character:
         _check(lib().mfs_character_create(ctx.handle, ctypes.byref(d), ctypes.byref(h)))
         self.handle = h
         self.n, self.m, self.n_handles = X.shape[0], T.shape[0], d.n_handles
+        if prob.get("blend_handles") is not None:
+            self.set_rotation_blend(prob["blend_handles"], prob["blend_weights"])
 
     def close(self):
         if getattr(self, "handle", None):
@@ -339,6 +360,18 @@ class Character:
         r, w = ctypes.c_size_t(), ctypes.c_size_t()
         _check(lib().mfs_character_footprint(self.handle, ctypes.byref(r), ctypes.byref(w)))
         return r.value, w.value
+
+    def set_rotation_blend(self, handles=None, weights=None):
+        """Smoothed tet rotations (m x kmax handles and weights, caller order)
+        for later solves; None returns to cluster rotations."""
+        if handles is None:
+            _check(lib().mfs_character_set_rotation_blend(self.handle, 0, None, None, MEM_HOST))
+            return
+        H = _host(handles, np.int32)
+        W = _host(weights, np.float64)
+        if H.shape != W.shape or H.ndim != 2 or H.shape[0] != self.m:
+            raise ValueError("handles and weights must both be (m, kmax)")
+        _check(lib().mfs_character_set_rotation_blend(self.handle, H.shape[1], _ptr(H), _ptr(W), MEM_HOST))
 
     def set_forces(self, vertices=None, forces=None):
         """External vertex forces (count x 3) for later solves; None clears."""

@@ -1,3 +1,4 @@
+#include <cmath>
 // C ABI: library-level calls, contexts and the standalone helpers (rotation
 // clusters, polar decomposition).
 #include <cstring>
@@ -113,6 +114,53 @@ extern "C" int mfs_cluster_by_segments(mfs_context* ctx, const double* X, int64_
   MFS_HIP(hipGetLastError());
   if (memory_space == MFS_MEM_HOST)
     MFS_HIP(hipMemcpyAsync(out, dout, sizeof(int32_t) * m, hipMemcpyDeviceToHost, ctx->stream));
+  MFS_HIP(hipStreamSynchronize(ctx->stream));
+  return MFS_OK;
+}
+
+extern "C" int mfs_blend_weights(mfs_context* ctx, const double* X, int64_t n, const int32_t* tets, int64_t m,
+                                 int32_t nseg, const double* seg_a, const double* seg_b, const int32_t* seg_handle,
+                                 int32_t n_handles, double width, int32_t kmax, int32_t* out_handles,
+                                 double* out_weights, int32_t memory_space) {
+  clear_error();
+  if (!ctx || !X || !tets || !seg_a || !seg_b || !seg_handle || !out_handles || !out_weights)
+    return set_error(MFS_E_INVALID, "null argument");
+  if (n < 1 || m < 1 || nseg < 1) return set_error(MFS_E_INVALID, "empty mesh or no segments");
+  if (n_handles < 1 || n_handles > kMaxHandles) return set_error(MFS_E_INVALID, "n_handles out of range");
+  if (kmax < 1 || kmax > 4) return set_error(MFS_E_INVALID, "kmax must be in 1..4");
+  if (!(width >= 0.0) || !std::isfinite(width)) return set_error(MFS_E_INVALID, "width must be finite and >= 0");
+  if (memory_space != MFS_MEM_HOST && memory_space != MFS_MEM_DEVICE)
+    return set_error(MFS_E_INVALID, "invalid memory space");
+  MFS_HIP(hipSetDevice(ctx->device));
+  if (memory_space == MFS_MEM_HOST) {
+    for (int64_t i = 0; i < 4 * m; ++i)
+      if (tets[i] < 0 || tets[i] >= n) return set_error(MFS_E_INVALID, "tet vertex index out of range");
+    for (int32_t i = 0; i < nseg; ++i)
+      if (seg_handle[i] < 0 || seg_handle[i] >= n_handles) return set_error(MFS_E_INVALID, "segment handle out of range");
+  }
+  DevBuf bX, bT, ba, bb, bh, boh, bow;
+  const void *dX, *dT, *da, *db, *dh;
+  MFS_TRY(stage_in(ctx, bX, X, 3 * sizeof(double) * n, memory_space, &dX));
+  MFS_TRY(stage_in(ctx, bT, tets, 4 * sizeof(int32_t) * m, memory_space, &dT));
+  MFS_TRY(stage_in(ctx, ba, seg_a, 3 * sizeof(double) * nseg, memory_space, &da));
+  MFS_TRY(stage_in(ctx, bb, seg_b, 3 * sizeof(double) * nseg, memory_space, &db));
+  MFS_TRY(stage_in(ctx, bh, seg_handle, sizeof(int32_t) * nseg, memory_space, &dh));
+  int32_t* doh = out_handles;
+  double* dow = out_weights;
+  const size_t mk = (size_t)m * kmax;
+  if (memory_space == MFS_MEM_HOST) {
+    MFS_TRY(boh.alloc(sizeof(int32_t) * mk));
+    MFS_TRY(bow.alloc(sizeof(double) * mk));
+    doh = boh.as<int32_t>();
+    dow = bow.as<double>();
+  }
+  launch_blend_weights(ctx->stream, (const double*)dX, (const int32_t*)dT, m, nseg, (const double*)da,
+                       (const double*)db, (const int32_t*)dh, n_handles, width, kmax, doh, dow);
+  MFS_HIP(hipGetLastError());
+  if (memory_space == MFS_MEM_HOST) {
+    MFS_HIP(hipMemcpyAsync(out_handles, doh, sizeof(int32_t) * mk, hipMemcpyDeviceToHost, ctx->stream));
+    MFS_HIP(hipMemcpyAsync(out_weights, dow, sizeof(double) * mk, hipMemcpyDeviceToHost, ctx->stream));
+  }
   MFS_HIP(hipStreamSynchronize(ctx->stream));
   return MFS_OK;
 }

@@ -612,6 +612,59 @@ extern "C" int mfs_character_set_forces(mfs_character* ch, const int32_t* vertic
   return MFS_OK;
 }
 
+extern "C" int mfs_character_set_rotation_blend(mfs_character* ch, int32_t kmax, const int32_t* handles,
+                                                const double* weights, int32_t memory_space) {
+  clear_error();
+  if (!ch) return set_error(MFS_E_INVALID, "null character");
+  if (memory_space != MFS_MEM_HOST && memory_space != MFS_MEM_DEVICE)
+    return set_error(MFS_E_INVALID, "invalid memory space");
+  mfs_context* ctx = ch->ctx;
+  MFS_HIP(hipSetDevice(ctx->device));
+  MFS_HIP(hipStreamSynchronize(ctx->stream));  // no solve is reading the old rotations
+  if (!handles) {
+    ch->blend_k = 0;
+    ch->desc.Rt = nullptr;
+    return MFS_OK;
+  }
+  if (kmax < 1 || kmax > 4) return set_error(MFS_E_INVALID, "kmax must be in 1..4");
+  if (!weights) return set_error(MFS_E_INVALID, "null weights");
+  const size_t mk = (size_t)ch->m * kmax;
+  std::vector<int32_t> hh(mk);
+  std::vector<double> hw(mk);
+  if (memory_space == MFS_MEM_DEVICE) {
+    MFS_HIP(hipMemcpy(hh.data(), handles, sizeof(int32_t) * mk, hipMemcpyDeviceToHost));
+    MFS_HIP(hipMemcpy(hw.data(), weights, sizeof(double) * mk, hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(hh.data(), handles, sizeof(int32_t) * mk);
+    std::memcpy(hw.data(), weights, sizeof(double) * mk);
+  }
+  // caller's tet order, row-major (m x kmax) -> internal order, kmax planes of m
+  std::vector<int32_t> ph(mk);
+  std::vector<double> pw(mk);
+  for (int k = 0; k < ch->m; ++k) {
+    const size_t src = (size_t)ch->tperm[k] * kmax;
+    if (hh[src] < 0 || hh[src] >= ch->nh)
+      return set_error(MFS_E_INVALID, "tet %d: first blend handle %d out of range", ch->tperm[k], hh[src]);
+    for (int j = 0; j < kmax; ++j) {
+      const int32_t h = hh[src + j];
+      const double w = hw[src + j];
+      if (h < -1 || h >= ch->nh) return set_error(MFS_E_INVALID, "tet %d: blend handle %d out of range", ch->tperm[k], h);
+      if (!(w >= 0.0) || !std::isfinite(w))
+        return set_error(MFS_E_INVALID, "tet %d: blend weight must be finite and >= 0", ch->tperm[k]);
+      ph[(size_t)j * ch->m + k] = h;
+      pw[(size_t)j * ch->m + k] = h >= 0 ? w : 0.0;
+    }
+  }
+  MFS_TRY(ch->blend_h.alloc(sizeof(int32_t) * mk));
+  MFS_TRY(ch->blend_w.alloc(sizeof(double) * mk));
+  if (!ch->Rt.p) MFS_TRY(ch->Rt.alloc(9 * sizeof(double) * (size_t)ch->m));
+  MFS_HIP(hipMemcpy(ch->blend_h.p, ph.data(), sizeof(int32_t) * mk, hipMemcpyHostToDevice));
+  MFS_HIP(hipMemcpy(ch->blend_w.p, pw.data(), sizeof(double) * mk, hipMemcpyHostToDevice));
+  ch->blend_k = kmax;
+  ch->desc.Rt = ch->Rt.as<double>();
+  return MFS_OK;
+}
+
 extern "C" int mfs_character_release_workspace(mfs_character* ch) {
   if (!ch) return set_error(MFS_E_INVALID, "null character");
   if (!ch->ws.p) return MFS_OK;

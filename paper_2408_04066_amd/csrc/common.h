@@ -145,6 +145,7 @@ struct SysDesc {
   const int32_t* vpin_ptr; // n + 1
   const int32_t* vpin_h;   // pins grouped by vertex: their handles
   const double* fext;      // 3n external vertex forces, or null (none)
+  const double* Rt;        // 9 planes of m: smoothed tet rotations of the pose, or null (cluster rotations)
   // per-frame rig
   const double* Rh;        // nh x 9
   const double* th;        // nh x 3

@@ -156,6 +156,8 @@ struct mfs_character {
   std::vector<int32_t> tperm;  // internal tet -> caller tet
   int ntv = 0, ntt = 0, nts = 0, ptile = 0;
   int max_tile_blocks = 0;     // matrix blocks of the densest 64-row vertex tile
+  int blend_k = 0;             // rotation smoothing: handles per tet (0: cluster rotations)
+  mfs::DevBuf blend_h, blend_w, Rt;  // blend handles / weights (blend_k planes of m), smoothed rotations (9 planes)
   bool has_solution = false;
   // resident mesh data
   mfs::DevBuf tets, G, wmu, wlam, info, X, rowptr, colidx, slot_ptr, contrib, diag, vpin_ptr, vpin_h, perm_d,

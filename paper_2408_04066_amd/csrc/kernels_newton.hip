@@ -13,6 +13,17 @@ __device__ __forceinline__ void load_rot(const double* __restrict__ Rh, int h, d
   for (int i = 0; i < 9; ++i) R[i] = Rh[9 * h + i];
 }
 
+// The rotation of tet k: its smoothed rotation when the character blends
+// rotations across cluster boundaries, else its cluster handle's rotation.
+__device__ __forceinline__ void tet_rot(const SysDesc& S, int k, int info, double R[9]) {
+  if (S.Rt) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) R[i] = S.Rt[(size_t)i * S.m + k];
+  } else {
+    load_rot(S.Rh, info & 0xffff, R);
+  }
+}
+
 __device__ __forceinline__ void gather4(const double* __restrict__ x, int4 t, double out[4][3]) {
   const int v[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
@@ -86,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_element(const SysDesc* __restrict__ 
     const int info = S.info[k];
     const int model = info >> 16;
     double R[9], x[4][3], n[4][3], F[9], sx[6], sl[6];
-    load_rot(S.Rh, info & 0xffff, R);
+    tet_rot(S, k, info, R);
     gather4(S.x, S.tets[k], x);
     load_grads(S.G, S.m, k, n);
     deformation_gradient(x, n, F);
@@ -243,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_linesearch_tets(const SysDesc* __res
     wlam = S.wlam[k];
     double R[9], x[4][3], d[4][3], n[4][3], F[9];
     const int4 tv = S.tets[k];
-    load_rot(S.Rh, info & 0xffff, R);
+    tet_rot(S, k, info, R);
     load_grads(S.G, S.m, k, n);
     gather4(S.x, tv, x);
     gather4(S.dx, tv, d);
@@ -366,7 +377,7 @@ __global__ __launch_bounds__(kBlock) void k_update_s(const SysDesc* __restrict__
   const int info = S.info[k];
   double R[9], x[4][3], n[4][3], F[9], sx[6];
   const int4 tv = S.tets[k];
-  load_rot(S.Rh, info & 0xffff, R);
+  tet_rot(S, k, info, R);
   load_grads(S.G, S.m, k, n);
   gather4(S.x, tv, x);
   double d[4][3];
@@ -438,7 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_stress(const SysDesc* __restrict__ s
   deformation_gradient(xv, n, F);
   const int info = S.info[k];
   const int model = info >> 16;
-  load_rot(S.Rh, info & 0xffff, R);
+  tet_rot(S, k, info, R);
   rotated_stretch(R, F, sx);
   const bool ok = model != kNeoHookean || sym_spd(sx);
   double WP[6] = {0, 0, 0, 0, 0, 0}, T[6], c[4];

@@ -37,6 +37,13 @@ void launch_rest(hipStream_t st, const int4* tets, const double* X, const double
                  int m, double det_tol, double* G, double* wmu, double* wlam, uint8_t* bad);
 void launch_cluster(hipStream_t st, const double* X, const int32_t* tets, int64_t m, int nseg, const double* sa,
                     const double* sb, const int32_t* sh, int32_t* out);
+// Rotation smoothing: per-tet blend weights from segment distances (kmax <= 4),
+// and the blended, polar-projected tet rotations of the current pose.
+void launch_blend_weights(hipStream_t st, const double* X, const int32_t* tets, int64_t m, int nseg,
+                          const double* sa, const double* sb, const int32_t* sh, int nh, double width, int kmax,
+                          int32_t* out_h, double* out_w);
+void launch_blend_rot(hipStream_t st, const double* Rh, int m, int kmax, const int32_t* bh, const double* bw,
+                      double* Rt);
 void launch_polar(hipStream_t st, const double* F, int64_t count, int fp32, double* U, double* P, double* smin,
                   uint8_t* routed);
 void launch_gather_rows(hipStream_t st, const double* src, const int32_t* perm, int count, int width, double* dst);

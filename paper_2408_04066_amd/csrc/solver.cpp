@@ -52,7 +52,11 @@ int check_pose(const mfs_character* ch, const double* R, const double* t) {
 int upload_pose(mfs_character* ch, const double* R, const double* t) {
   hipStream_t st = ch->ctx->stream;
   MFS_TRY(ch->ctx->up.upload(st, ch->Rh.p, R, 9 * sizeof(double) * ch->nh));
-  return ch->ctx->up.upload(st, ch->th.p, t, 3 * sizeof(double) * ch->nh);
+  MFS_TRY(ch->ctx->up.upload(st, ch->th.p, t, 3 * sizeof(double) * ch->nh));
+  if (ch->blend_k > 0)  // smoothed tet rotations follow every pose (and load step)
+    launch_blend_rot(st, ch->Rh.as<double>(), ch->m, ch->blend_k, ch->blend_h.as<int32_t>(), ch->blend_w.as<double>(),
+                     ch->Rt.as<double>());
+  return MFS_OK;
 }
 
 int solve_systems(mfs_context* ctx, int count, mfs_character* const* chars, const double* const* R,

@@ -456,3 +456,55 @@ def test_persistent_pcg(ctx):
         ch.close()
     finally:
         ctx.set_tuning(**base)
+
+
+def test_rotation_smoothing(ctx):
+    """Rotation smoothing (mfs_blend_weights, mfs_character_set_rotation_blend):
+    blend handles equal to the oracle's and weights within 1e-12; with the
+    oracle's blend, E, grad E and S within 1e-12 relative, stress and
+    multipliers within 1e-12, FP64 frames within 1e-9 * bbox and FP32 +
+    refinement within 1e-7 * bbox of the oracle's smoothed solution; clearing
+    the blend gives the cluster solve again."""
+    mfs = _mfs()
+    prob = _small_humanoid(21, 4000, 15)
+    pose = random_pose(prob, 22, amp_deg=30.0)
+    width = 0.3
+    _say(f"rotation smoothing: humanoid m={len(prob['T'])}, width {width}")
+    Hr, Wr = oracle.blend_weights(prob["X"], prob["T"], prob["seg_a"], prob["seg_b"], prob["seg_handle"], width, 3)
+    Hg, Wg = ctx.blend_weights(prob["X"], prob["T"], prob["seg_a"], prob["seg_b"], prob["seg_handle"],
+                               prob["n_handles"], width, 3)
+    assert np.array_equal(Hg, Hr)
+    assert np.max(np.abs(Wg - Wr)) <= 1e-12
+    assert np.mean(Hr[:, 1] >= 0) > 0.05  # a real share of tets blends
+    pb = dict(prob, blend_handles=Hr, blend_weights=Wr)
+    fr = oracle.Frame(pb, pose)
+    rng = np.random.default_rng(5)
+    ref = oracle.solve_frame(pb, pose, step_tol=1e-12, frame=fr)
+    assert ref["status"] == "ok"
+    x = ref["x"].reshape(-1, 3) + 1e-5 * prob["bbox_diag"] * rng.normal(size=(len(prob["X"]), 3))
+    assert fr.feasible(x.reshape(-1))
+    ch = mfs.Character(ctx, prob)
+    x_cluster, _, rc = ch.solve(*pose, precision=mfs.FP64, step_tol=1e-10, cg_tol=1e-10, max_newton=60)
+    ch.set_rotation_blend(Hr, Wr)
+    ev = ch.evaluate(*pose, x)
+    E = fr.energy(x.reshape(-1))
+    g = fr.gradient(x.reshape(-1)).reshape(-1, 3)
+    s = fr.stretch(x.reshape(-1))
+    assert abs(ev["energy"] - E) <= 1e-12 * abs(E)
+    assert np.max(np.abs(ev["grad"] - g)) <= 1e-11 * np.max(np.abs(g))
+    assert np.max(np.abs(ev["stretch"] - s)) <= 1e-12 * max(1.0, np.abs(s).max())
+    P, L = ch.stress(*pose, x)
+    Pr, Lr = oracle.stress(pb, pose, x)
+    assert np.max(np.abs(P - Pr)) <= 1e-12 * np.max(np.abs(Pr))
+    assert np.max(np.abs(L - Lr)) <= 1e-12 * np.max(np.abs(Lr))
+    x64, st, rc = ch.solve(*pose, precision=mfs.FP64, step_tol=1e-10, cg_tol=1e-10, max_newton=60)
+    _say(f"  FP64 stats {st} err/bbox={_err(x64, ref['x'], prob):.3e}")
+    assert rc == 0 and _err(x64, ref["x"], prob) <= 1e-9
+    x32, st, rc = ch.solve(*pose, precision=mfs.FP32_REFINED, step_tol=1e-9, cg_tol=1e-5, max_newton=60,
+                           cg_adaptive=1)
+    assert rc == 0 and _err(x32, ref["x"], prob) <= 1e-7
+    assert _err(x64, x_cluster, prob) > 1e-6  # smoothing changes the frame
+    ch.set_rotation_blend(None)
+    x0, _, rc = ch.solve(*pose, precision=mfs.FP64, step_tol=1e-10, cg_tol=1e-10, max_newton=60)
+    assert rc == 0 and np.array_equal(x0, x_cluster)
+    ch.close()
