@@ -8,6 +8,10 @@ timing):
   1e6], nu uniform in [0.3, 0.49]); each step solves one frame at a fresh
   random pose (joint Euler angles uniform in +-45 degrees) from the rest
   shape.
+* ``c2x``: the c2 frame with the adjacent features on: rotations smoothed
+  across cluster boundaries (width 5% of the bounding-box diagonal, up to 3
+  handles per tet), constant loads on 200 seeded vertices, and stress and
+  multiplier recovery into device memory after every frame.
 * ``c1``: the 16x4x4 neo-Hookean beam (1536 tets), FP64, exactly 10 Newton
   iterations with PCG tolerance 1e-10 per step.
 * ``c3``: the same generator at ~500k tets / 30 handles; an animation of
@@ -69,6 +73,15 @@ def make_workload(name):
     if name == "c2":
         p = humanoid(2001, target_tets=50000, n_bones=20)
         return [p], (lambda i: [random_pose(p, 2002 + i)]), "humanoid_50k_tets_20_handles_random_pose", fp32
+    if name == "c2x":  # the C2 frame with the adjacent features on: rotation smoothing, loads, stress
+        p = humanoid(2001, target_tets=50000, n_bones=20)
+        rng = np.random.default_rng(2003)
+        n = len(p["X"])
+        p["force_vertex"] = rng.choice(n, 200, replace=False).astype(np.int32)
+        p["force"] = rng.normal(scale=5e-4 * float(np.max(p["youngs"])) * p["bbox_diag"] ** 2 / n, size=(200, 3))
+        p["smooth_width"] = 0.05 * p["bbox_diag"]
+        return [p], (lambda i: [random_pose(p, 2002 + i)]), \
+            "humanoid_50k_tets_20_handles_random_pose_smoothed_rotations_200_loads_stress", fp32
     if name == "c3":
         p = humanoid(3001, target_tets=500000, n_bones=30)
         return [p], (lambda i: [animation_pose(p, 3002, i)]), \
@@ -154,6 +167,22 @@ def frame_bench(args, mfs, torch):
     chars = [mfs.Character(ctx, p) for p in probs]
     infos = [c.info() for c in chars]
     m_tot = sum(i["n_tets"] for i in infos)
+    extended = {}
+    stress_out = None
+    for p, c in zip(probs, chars):
+        if p.get("smooth_width"):
+            H, W = ctx.blend_weights(p["X"], p["T"], p["seg_a"], p["seg_b"], p["seg_handle"], p["n_handles"],
+                                     p["smooth_width"], 3)
+            c.set_rotation_blend(H, W)
+            extended["smoothing_width"] = p["smooth_width"]
+            extended["blended_tet_fraction"] = float(np.mean(H[:, 1] >= 0))
+        if p.get("force_vertex") is not None:
+            c.set_forces(p["force_vertex"], p["force"])
+            extended["loaded_vertices"] = len(p["force_vertex"])
+    if extended:
+        extended["stress_recovery"] = "per frame, P (m x 6) and W R P (m x 9) to device memory"
+        stress_out = [(torch.empty((i["n_tets"], 6), dtype=torch.float64, device="cuda"),
+                       torch.empty((i["n_tets"], 3, 3), dtype=torch.float64, device="cuda")) for i in infos]
     outs = [torch.empty((i["n_vertices"], 3), dtype=torch.float64, device="cuda") for i in infos]
     steps = [pose_of(i) for i in range(args.warmup + args.steps + max(args.roofline_steps, args.fp64_steps))]
     fp64_opts = dict(opts, precision=mfs.FP64)
@@ -167,6 +196,8 @@ def frame_bench(args, mfs, torch):
     def frame(poses, o):
         if len(chars) == 1:
             _, st, rc = chars[0].solve(*poses[0], out=outs[0], **o)
+            if stress_out is not None:
+                chars[0].stress(*poses[0], outs[0], out=stress_out[0])
             return [st], rc
         _, sts, rc = mfs.solve_batch(ctx, chars, poses, outs=outs, **o)
         return sts, rc
@@ -266,7 +297,8 @@ def frame_bench(args, mfs, torch):
                    "step_tol_bbox": opts.get("step_tol"),
                    "newton": "fixed 10" if opts.get("fixed_newton") else f"max {opts['max_newton']}",
                    "warm_start": "previous frame" if warm else "rest",
-                   "pcg_schedule": tuned or ctx.tuning()},
+                   "pcg_schedule": tuned or ctx.tuning(),
+                   **({"extended": extended} if extended else {})},
         "roofline": {
             "bound": "hbm",
             "kernel": kernel,

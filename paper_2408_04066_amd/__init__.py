@@ -405,9 +405,15 @@ class Character:
                                           ctypes.byref(st)))
         return out, st.as_dict(), rc
 
-    def stress(self, R, t, x):
-        """Per-tet stress P (m, 6) and world multiplier W R P (m, 3, 3) at x."""
+    def stress(self, R, t, x, out=None):
+        """Per-tet stress P (m, 6) and world multiplier W R P (m, 3, 3) at x.
+        With x a CUDA torch tensor (n, 3) float64 and ``out`` = (P, L) CUDA
+        tensors of those shapes, everything stays in device memory."""
         R, t = self._pose(R, t)
+        if out is not None:
+            P, L = out
+            _check(lib().mfs_stress(self.handle, _ptr(R), _ptr(t), _ptr(x), MEM_DEVICE, _ptr(P), _ptr(L)))
+            return P, L
         x = _host(x, np.float64).reshape(self.n, 3)
         P = np.empty((self.m, 6))
         L = np.empty((self.m, 3, 3))
