@@ -404,6 +404,8 @@ class Frame:
         self.mu, self.lam = lame(prob["youngs"], prob["poisson"])
         self.G, self.W = rest_shape(self.X, self.T)
         if clusters is None:
+            clusters = prob.get("cluster")  # given clusters (user-defined rule)
+        if clusters is None:
             clusters = cluster_by_segments(self.X, self.T, prob["seg_a"], prob["seg_b"],
                                            prob["seg_handle"])
         self.cluster = np.asarray(clusters, dtype=np.int32)

@@ -1,0 +1,224 @@
+"""GPU edge cases through the C ABI.
+
+Error codes for invalid meshes, poses and options; the smallest meshes (one
+tet, one cube) and sizes at and across the 64-row vertex and 256-tet tile
+boundaries against the oracle; the maximum handle count (256, with one more
+rejected); the widest rotation blend (4 handles per tet); and the degenerate
+cases of the method (zero loads equal no loads, a batch may not hold one
+character twice).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import ARAP, COROT, NH, beam, beam_pose, humanoid, random_pose, tiny_mesh, euler_xyz
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2408_04066_amd as mfs
+    c = mfs.Context(0)
+    yield c
+    c.close()
+
+
+def _mfs():
+    import paper_2408_04066_amd as mfs
+    return mfs
+
+
+def _code(fn):
+    mfs = _mfs()
+    with pytest.raises(mfs.MfsError) as e:
+        fn()
+    return e.value.code
+
+
+def _err(x, ref, prob):
+    return float(np.max(np.linalg.norm(x - ref, axis=1))) / prob["bbox_diag"]
+
+
+def test_character_creation_rejects_bad_meshes(ctx):
+    mfs = _mfs()
+    base = tiny_mesh("cube")
+    base["cluster"] = np.zeros(len(base["T"]), dtype=np.int32)
+    _say("invalid meshes")
+
+    def make(**changes):
+        p = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in base.items()}
+        for k, v in changes.items():
+            p[k] = v
+        return lambda: mfs.Character(ctx, p)
+
+    T = base["T"].copy()
+    T[0, 0] = 99
+    assert _code(make(T=T)) == -1                      # vertex index out of range
+    T = base["T"].copy()
+    T[0, 1] = T[0, 0]
+    assert _code(make(T=T)) == -1                      # repeated vertex
+    X = base["X"].copy()
+    X[0, 0] = np.nan
+    assert _code(make(X=X)) == -1                      # non-finite rest position
+    assert _code(make(model=np.full(len(T), 7, dtype=np.int32))) == -1
+    assert _code(make(poisson=np.full(len(T), 0.5))) == -1
+    assert _code(make(youngs=np.zeros(len(T)))) == -1
+    assert _code(make(cluster=np.full(len(T), 2, dtype=np.int32))) == -1
+    assert _code(make(n_handles=0)) == -1
+    assert _code(make(n_handles=257)) == -1
+    assert _code(make(pin_stiffness=0.0)) == -1
+    assert _code(make(pin_handle=np.full(len(base["pin_vertex"]), 5, dtype=np.int32))) == -1
+    # pins on one line cannot fix rigid motion
+    line = np.nonzero((base["X"][:, 1] == 0) & (base["X"][:, 2] == 0))[0]
+    assert _code(make(pin_vertex=np.concatenate([line, line]).astype(np.int32),
+                      pin_handle=np.zeros(2 * len(line), dtype=np.int32))) == -3
+    # a flat (zero-volume) tet
+    one = tiny_mesh("one")
+    one["cluster"] = np.zeros(1, dtype=np.int32)
+    X = one["X"].copy()
+    X[3] = 0.3 * X[0] + 0.3 * X[1] + 0.4 * X[2]
+    one["X"] = X
+    assert _code(lambda: mfs.Character(ctx, one)) == -2
+
+
+def test_bad_poses_options_and_batches_are_rejected(ctx):
+    mfs = _mfs()
+    prob = beam(4, 1, 1)
+    ch = mfs.Character(ctx, prob)
+    R, t = beam_pose(prob)
+    bad = R.copy()
+    bad[1] *= 1.01
+    assert _code(lambda: ch.solve(bad, t)) == -1        # not a rotation
+    bad = R.copy()
+    bad[1] = -bad[1]
+    assert _code(lambda: ch.solve(bad, t)) == -1        # det -1
+    tb = t.copy()
+    tb[0, 0] = np.inf
+    assert _code(lambda: ch.solve(R, tb)) == -1
+    assert _code(lambda: ch.solve(R, t, precision=3)) == -1
+    assert _code(lambda: ch.solve(R, t, warm_start=5)) == -1
+    assert _code(lambda: ch.solve(R, t, max_newton=0)) == -1
+    assert _code(lambda: mfs.solve_batch(ctx, [ch, ch], [(R, t), (R, t)])) == -1
+    assert _code(lambda: ch.set_forces([99], [[0.0, 0.0, 1.0]])) == -1
+    assert _code(lambda: ch.set_forces([0], [[0.0, np.nan, 1.0]])) == -1
+    assert _code(lambda: ctx.blend_weights(prob["X"], prob["T"], prob["seg_a"], prob["seg_b"],
+                                           prob["seg_handle"], 2, 0.1, 5)) == -1
+    assert _code(lambda: ctx.blend_weights(prob["X"], prob["T"], prob["seg_a"], prob["seg_b"],
+                                           prob["seg_handle"], 2, -0.1, 3)) == -1
+    H = np.full((ch.m, 2), -1, dtype=np.int32)
+    assert _code(lambda: ch.set_rotation_blend(H, np.zeros((ch.m, 2)))) == -1  # no first handle
+    # the character still solves after the rejected calls
+    x, st, rc = ch.solve(R, t)
+    assert rc == 0
+    ch.close()
+
+
+@pytest.mark.parametrize("kind", ["one", "cube"])
+@pytest.mark.parametrize("model", [ARAP, COROT, NH])
+def test_smallest_meshes_match_oracle(ctx, kind, model):
+    mfs = _mfs()
+    prob = tiny_mesh(kind, model=model, youngs=1e3, poisson=0.4, pin_stiffness=50.0)
+    prob["cluster"] = np.zeros(len(prob["T"]), dtype=np.int32)
+    prob["cluster"][-1:] = 1
+    R = np.stack([np.eye(3), euler_xyz(0.3, -0.2, 0.25)])
+    t = np.array([[0.0, 0.0, 0.0], [0.1, -0.05, 0.08]])
+    ref = oracle.solve_frame(prob, (R, t), step_tol=1e-13)
+    assert ref["status"] == "ok"
+    ch = mfs.Character(ctx, prob)
+    x, st, rc = ch.solve(R, t, precision=mfs.FP64, step_tol=1e-12, cg_tol=1e-12, max_newton=60)
+    _say(f"tiny {kind} model {model}: {st['iterations']} iterations, err/bbox {_err(x, ref['x'], prob):.2e}")
+    assert rc == 0 and _err(x, ref["x"], prob) <= 1e-9
+    ch.close()
+
+
+def test_tile_boundary_sizes_and_batch(ctx):
+    """Vertex counts 64 (exactly one tile) and 68 (a tile and a ragged one),
+    264 tets (a full 256-tet tile and a ragged one): FP64 within 1e-9 * bbox
+    and FP32 + refinement within 1e-7 of the oracle, and the three solved as
+    one batch bitwise equal to each solved alone."""
+    mfs = _mfs()
+    probs = [beam(15, 1, 1), beam(16, 1, 1), beam(11, 2, 2)]
+    assert [len(p["X"]) for p in probs] == [64, 68, 108]
+    assert len(probs[2]["T"]) == 264
+    chars = [mfs.Character(ctx, p) for p in probs]
+    poses = [beam_pose(p, 40.0, (1.0, 0.5, 0.0)) for p in probs]
+    kw32 = dict(precision=mfs.FP32_REFINED, step_tol=1e-9, cg_tol=1e-5, max_newton=60, cg_adaptive=1)
+    for p, ch, pose in zip(probs, chars, poses):
+        ref = oracle.solve_frame(p, pose, step_tol=1e-12)
+        assert ref["status"] == "ok"
+        x64, _, rc = ch.solve(*pose, precision=mfs.FP64, step_tol=1e-10, cg_tol=1e-10, max_newton=60)
+        assert rc == 0 and _err(x64, ref["x"], p) <= 1e-9
+        x32, _, rc = ch.solve(*pose, **kw32)
+        assert rc == 0 and _err(x32, ref["x"], p) <= 1e-7
+        _say(f"{p['name']}: n={len(p['X'])} m={len(p['T'])} ok")
+    alone = [ch.solve(*pose, **kw32)[0] for ch, pose in zip(chars, poses)]
+    xs, _, rc = mfs.solve_batch(ctx, chars, poses, **kw32)
+    assert rc == 0
+    for a, b in zip(alone, xs):
+        assert np.array_equal(a, b)
+    for ch in chars:
+        ch.close()
+
+
+def test_max_handles_and_widest_blend(ctx):
+    """256 handles (the maximum): a beam whose tets take one of 256 clusters
+    along its axis, handles twisting progressively, FP64 within 1e-9 * bbox
+    of the oracle; the same with 4-handle rotation blending."""
+    mfs = _mfs()
+    prob = beam(63, 2, 2, model=COROT, youngs=1e4, poisson=0.3)
+    X, T = prob["X"], prob["T"]
+    nh = 256
+    bary = X[T].mean(axis=1)
+    cl = np.minimum((bary[:, 0] / 63.0 * nh).astype(np.int32), nh - 1)
+    centers = np.stack([np.array([(h + 0.5) * 63.0 / nh, 1.0, 1.0]) for h in range(nh)])
+    p = dict(prob, n_handles=nh, cluster=cl, seg_a=centers, seg_b=centers,
+             seg_handle=np.arange(nh, dtype=np.int32))
+    # pins: each end cap on the end handles
+    p["pin_handle"] = np.where(X[p["pin_vertex"], 0] == 0.0, 0, nh - 1).astype(np.int32)
+    ang = np.linspace(0.0, 0.6, nh)
+    R = np.stack([euler_xyz(a, 0.0, 0.0) for a in ang])
+    c = np.array([0.0, 1.0, 1.0])
+    t = np.stack([c - Rh @ c for Rh in R])
+    ref = oracle.solve_frame(p, (R, t), step_tol=1e-12)
+    assert ref["status"] == "ok"
+    ch = mfs.Character(ctx, p)
+    x, st, rc = ch.solve(R, t, precision=mfs.FP64, step_tol=1e-10, cg_tol=1e-10, max_newton=60)
+    _say(f"256 handles: {st['iterations']} iterations, err/bbox {_err(x, ref['x'], p):.2e}")
+    assert rc == 0 and _err(x, ref["x"], p) <= 1e-9
+    width = 2.0 * 63.0 / nh
+    Hr, Wr = oracle.blend_weights(X, T, centers, centers, p["seg_handle"], width, 4)
+    Hg, Wg = ctx.blend_weights(X, T, centers, centers, p["seg_handle"], nh, width, 4)
+    assert np.array_equal(Hg, Hr) and np.max(np.abs(Wg - Wr)) <= 1e-12
+    assert np.any(Hr[:, 3] >= 0)  # some tets blend four handles
+    pb = dict(p, blend_handles=Hr, blend_weights=Wr)
+    refb = oracle.solve_frame(pb, (R, t), step_tol=1e-12)
+    ch.set_rotation_blend(Hr, Wr)
+    xb, st, rc = ch.solve(R, t, precision=mfs.FP64, step_tol=1e-10, cg_tol=1e-10, max_newton=60)
+    assert rc == 0 and _err(xb, refb["x"], p) <= 1e-9
+    ch.close()
+
+
+def test_zero_loads_equal_no_loads(ctx):
+    mfs = _mfs()
+    prob = humanoid(71, target_tets=2000, n_bones=10)
+    pose = random_pose(prob, 72)
+    ch = mfs.Character(ctx, prob)
+    x0, _, rc = ch.solve(*pose, precision=mfs.FP64)
+    assert rc == 0
+    ch.set_forces([0, 5, 9], np.zeros((3, 3)))
+    x1, _, rc = ch.solve(*pose, precision=mfs.FP64)
+    assert rc == 0 and np.array_equal(x0, x1)
+    ch.close()
