@@ -167,3 +167,29 @@ def test_one_slot_reoccupied_by_other_characters(mfs_ctx):
     srv.close()
     for ch in chars:
         ch.close()
+
+
+def test_served_with_loads_and_smoothed_rotations(mfs_ctx):
+    """Characters with external loads and smoothed rotations served in a mix
+    with a plain one: each result equals its solve alone bitwise."""
+    mfs, ctx = mfs_ctx
+    probs, chars = _chars(mfs, ctx, [(1500, 8), (2000, 10), (1000, 9)], 1200)
+    p0, p1 = probs[0], probs[1]
+    H, W = ctx.blend_weights(p0["X"], p0["T"], p0["seg_a"], p0["seg_b"], p0["seg_handle"], p0["n_handles"],
+                             0.05 * p0["bbox_diag"], 3)
+    chars[0].set_rotation_blend(H, W)
+    rng = np.random.default_rng(1201)
+    fv = rng.choice(len(p1["X"]), 20, replace=False).astype(np.int32)
+    chars[1].set_forces(fv, rng.normal(scale=1e-4 * float(np.max(p1["youngs"])) * p1["bbox_diag"] ** 2 / len(p1["X"]),
+                                       size=(20, 3)))
+    poses = [random_pose(p, 1300 + i) for i, p in enumerate(probs)]
+    alone = [ch.solve(*pose, **OPTS)[0] for ch, pose in zip(chars, poses)]
+    _say("server: smoothed, loaded and plain characters")
+    srv = mfs.Server(ctx, slots=3, **OPTS)
+    tickets = [(k, srv.submit(chars[k], *poses[k])) for k in (0, 1, 2, 1, 0)]
+    for k, tk in tickets:
+        x, st, _, rc = srv.wait(tk)
+        assert np.array_equal(x, alone[k]), f"character {k} differs from its solve alone"
+    srv.close()
+    for ch in chars:
+        ch.close()
