@@ -97,7 +97,7 @@ def _workers():
     return max(1, min(16, os.cpu_count() or 1))
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_pcg_humanoid50k.md")
+TRAFFIC_SUMMARIES = os.path.join(ROOT, "profiles")
 TRAFFIC_SOURCES = ("paper_2408_04066_amd/csrc/kernels_cg.hip", "paper_2408_04066_amd/csrc/common.h")
 
 
@@ -111,21 +111,22 @@ def kernel_source_hash():
 
 
 def counted_traffic(workload, kernel):
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (copy-kernel scaled), or None
-    when that summary is for another workload or kernel, or the kernel
-    sources changed since it was taken."""
-    try:
-        lines = open(TRAFFIC_SUMMARY).read().splitlines()
-    except OSError:
-        return None
+    """HBM bytes per launch of the dominant kernel from a committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (profiles/hbm_traffic_*.md, copy-kernel
+    scaled) for this workload and kernel, or None when there is none or the
+    kernel sources changed since it was taken."""
+    import glob
     kv = {}
-    for line in lines:
-        if line.startswith("- ") and ": " in line:
-            k, v = line[2:].split(": ", 1)
-            kv[k.strip("`")] = v.strip().strip("`")
-    if (kv.get("workload") != workload or kv.get("kernel") != kernel
-            or kv.get("kernel_sources_sha256") != kernel_source_hash()):
+    for path in sorted(glob.glob(os.path.join(TRAFFIC_SUMMARIES, "hbm_traffic_*.md"))):
+        fields = {}
+        for line in open(path).read().splitlines():
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                fields[k.strip("`")] = v.strip().strip("`")
+        if fields.get("workload") == workload and fields.get("kernel") == kernel:
+            kv = fields
+            break
+    if kv.get("kernel_sources_sha256") != kernel_source_hash():
         return None
     try:
         return float(kv["traffic_bytes_per_launch"])
