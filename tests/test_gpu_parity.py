@@ -385,6 +385,12 @@ def test_stress_matches_oracle(ctx):
     Pr, Lr = oracle.stress(prob, pose, x)
     assert np.max(np.abs(P - Pr)) <= 1e-12 * np.max(np.abs(Pr))
     assert np.max(np.abs(L - Lr)) <= 1e-12 * np.max(np.abs(Lr))
+    # device-memory path: same values bitwise
+    xd = torch.tensor(x, dtype=torch.float64, device="cuda")
+    Pd = torch.empty((len(prob["T"]), 6), dtype=torch.float64, device="cuda")
+    Ld = torch.empty((len(prob["T"]), 3, 3), dtype=torch.float64, device="cuda")
+    ch.stress(*pose, xd, out=(Pd, Ld))
+    assert np.array_equal(Pd.cpu().numpy(), P) and np.array_equal(Ld.cpu().numpy(), L)
     k = int(np.flatnonzero(fr.model == NH)[0])
     a, b = prob["T"][k][:2]
     xb = x.copy()
