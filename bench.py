@@ -327,64 +327,83 @@ def frame_bench(args, mfs, torch):
 
 
 def serve_bench(args, mfs, torch):
-    """Poisson stream of frame requests through the serving loop."""
+    """Poisson stream of frame requests through the serving loop.  With
+    ``--size-classes K`` > 1 the pool is split by tet count into K classes,
+    each served by its own server on its own context (own HIP stream), so the
+    small characters' frames do not wait for the large ones' PCG runs and the
+    streams overlap on the GPU; the slots are divided between the classes."""
     from workloads import NH, COROT, ARAP, character_pool, random_pose
     probs = character_pool(args.pool, 5001, (2000, 300000), (8, 30), (NH, COROT, ARAP),
                            workers=_workers())
-    ctx = mfs.Context(0)
-    chars = [mfs.Character(ctx, p) for p in probs]
+    K = max(1, args.size_classes)
+    sizes = np.array([len(p["T"]) for p in probs])
+    edges = np.quantile(sizes, np.linspace(0, 1, K + 1))[1:-1] if K > 1 else []
+    cls = np.searchsorted(edges, sizes, side="right") if K > 1 else np.zeros(len(probs), dtype=int)
+    ctxs = [mfs.Context(0) for _ in range(K)]
+    chars = [mfs.Character(ctxs[c], p) for c, p in zip(cls, probs)]
     infos = [c.info() for c in chars]
-    ws = sorted((c.footprint()[1] for c in chars), reverse=True)
+    slots = [max(1, args.slots // K)] * K
+    budgets = []
+    for g in range(K):
+        ws = sorted((chars[k].footprint()[1] for k in range(len(chars)) if cls[k] == g), reverse=True)
+        budgets.append(2 * sum(ws[:slots[g]]))
     for c in chars:
         c.release_workspace()
-    budget = 2 * sum(ws[:args.slots])
     opts = dict(precision=1, cg_tol=1e-5, step_tol=1e-8, max_newton=60, cg_adaptive=1)
     rng = np.random.default_rng(5002)
     n_req = int(args.rate * args.duration)
     arrivals = np.cumsum(rng.exponential(1.0 / args.rate, size=n_req))
     who = rng.integers(0, len(chars), size=n_req)
     poses = [random_pose(probs[k], 50000 + j) for j, k in enumerate(who)]
-    tuned = None
-    if not args.no_autotune:  # schedule for a batch like the served mix: a sample of the pool
-        sample = list(range(0, len(chars), max(1, len(chars) // args.slots)))[:args.slots]
-        for k in sample:
-            chars[k].solve(*random_pose(probs[k], 1), **opts)  # re-creates the released workspace
-        tuned, tms = mfs.autotune(ctx, [chars[k] for k in sample], [random_pose(probs[k], 1) for k in sample],
+    tuned = []
+    if not args.no_autotune:  # schedule for a batch like each served mix: a sample of the class
+        for g in range(K):
+            members = [k for k in range(len(chars)) if cls[k] == g]
+            sample = members[::max(1, len(members) // slots[g])][:slots[g]]
+            for k in sample:
+                chars[k].solve(*random_pose(probs[k], 1), **opts)  # re-creates the released workspace
+            t, tms = mfs.autotune(ctxs[g], [chars[k] for k in sample], [random_pose(probs[k], 1) for k in sample],
                                   newton_iterations=4, cache_path=args.tune_cache, **opts)
-        for k in sample:
-            chars[k].release_workspace()
-        _progress(f"autotuned PCG schedule {tuned} ({tms:.1f} ms per 4 Newton iterations)")
-    srv = mfs.Server(ctx, slots=args.slots, queue_capacity=args.queue, workspace_budget_bytes=budget, **opts)
+            for k in sample:
+                chars[k].release_workspace()
+            tuned.append(t)
+            _progress(f"class {g}: autotuned PCG schedule {t} ({tms:.1f} ms per 4 Newton iterations)")
+    queue = max(1, args.queue // K)  # the same total queue capacity however the pool is split
+    srvs = [mfs.Server(ctxs[g], slots=slots[g], queue_capacity=queue, workspace_budget_bytes=budgets[g],
+                       **opts) for g in range(K)]
     for j in range(min(args.warmup, n_req)):  # warm the kernels and graphs
-        srv.wait(srv.submit(chars[who[j]], *poses[j]))
-    info0 = srv.info()
+        srvs[cls[who[j]]].wait(srvs[cls[who[j]]].submit(chars[who[j]], *poses[j]))
+    info0 = [s.info() for s in srvs]
     tickets, rejected = [], 0
     t0 = time.perf_counter()
-    _progress(f"pool of {len(chars)} characters resident; streaming {n_req} requests")
+    _progress(f"pool of {len(chars)} characters resident in {K} size class(es); streaming {n_req} requests")
     for j in range(n_req):
         if j % 1000 == 0 and j:
-            _progress(f"submitted {j} requests, {srv.info()['completed']} completed")
+            _progress(f"submitted {j} requests, {sum(s.info()['completed'] for s in srvs)} completed")
         delay = arrivals[j] - (time.perf_counter() - t0)
         if delay > 0:
             time.sleep(delay)
+        k = who[j]
         try:
-            tickets.append((who[j], srv.submit(chars[who[j]], *poses[j])))
+            tickets.append((k, srvs[cls[k]].submit(chars[k], *poses[j])))
         except mfs.MfsError as e:
             if e.code != -6:
                 raise
             rejected += 1
     lat, tet_iters, done_t, conv, first_submit = [], 0, [], [], None
     for k, tk in tickets:
-        _, st, tm, _ = srv.wait(tk)
+        _, st, tm, _ = srvs[cls[k]].wait(tk)
         lat.append(tm["done_s"] - tm["submit_s"])
         first_submit = tm["submit_s"] if first_submit is None else min(first_submit, tm["submit_s"])
         done_t.append(tm["done_s"])
         tet_iters += infos[k]["n_tets"] * st["iterations"]
         conv.append(st["status"] == 0)
-    info = srv.info()
-    srv.close()
+    info = [s.info() for s in srvs]
+    for s_ in srvs:
+        s_.close()
     span = max(done_t) - first_submit
-    steps = info["steps"] - info0["steps"]
+    steps = sum(i1["steps"] - i0["steps"] for i0, i1 in zip(info0, info))
+    slot_steps = sum(i1["slot_steps"] - i0["slot_steps"] for i0, i1 in zip(info0, info))
     result = {
         "metric": "tet*Newton-iter/s (frames/s at 1e-7 rel err; p50/p99 frame latency)",
         "value": tet_iters / span,
@@ -405,19 +424,20 @@ def serve_bench(args, mfs, torch):
         "requests": n_req,
         "rejected_queue_full": rejected,
         "converged_fraction": float(np.mean(conv)),
-        "mean_batch_width": (info["slot_steps"] - info0["slot_steps"]) / max(steps, 1),
-        "arena_peak_bytes": info["arena_peak"],
+        "mean_batch_width": slot_steps / max(steps, 1),
+        "arena_peak_bytes": sum(i["arena_peak"] for i in info),
         "config": {"workload": f"serving_pool_{args.pool}_humanoids_2k_300k_tets_poisson_{args.rate:g}_per_s",
-                   "characters": len(chars), "tets": sum(i["n_tets"] for i in infos),
-                   "slots": args.slots, "queue_capacity": args.queue, "arena_bytes": budget,
+                   "characters": len(chars), "tets": int(sizes.sum()),
+                   "size_classes": K, "class_tet_edges": [float(e) for e in edges],
+                   "slots": slots, "queue_capacity": [queue] * K, "arena_bytes": budgets,
                    "duration_s": args.duration, "precision": "fp32 pcg + fp64 refinement",
-                   "pcg_schedule": tuned or ctx.tuning()},
+                   "pcg_schedule": tuned or [c.tuning() for c in ctxs]},
     }
     for c in chars:
         c.close()
-    ctx.close()
+    for c in ctxs:
+        c.close()
     return result
-
 
 def main():
     ap = argparse.ArgumentParser()
@@ -440,6 +460,8 @@ def main():
     ap.add_argument("--duration", type=float, default=60.0, help="c5: seconds of arrivals")
     ap.add_argument("--slots", type=int, default=16, help="c5: requests in flight at once")
     ap.add_argument("--queue", type=int, default=512, help="c5: queued requests before rejection")
+    ap.add_argument("--size-classes", type=int, default=1,
+                    help="c5: servers (each on its own context and stream) by tet-count class")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: each frame solve runs on a single device and "
