@@ -164,16 +164,25 @@ def cpu_baseline(prob, pose, iterations=2):
 
 def frame_bench(args, mfs, torch):
     probs, pose_of, wname, opts = make_workload(args.workload)
-    ctx = mfs.Context(0)
-    chars = [mfs.Character(ctx, p) for p in probs]
+    # size classes (batches only): each class is solved as its own batch on its
+    # own context (HIP stream) from its own host thread, so a small
+    # character's Newton steps do not wait for a large one's PCG runs
+    K = max(1, min(args.size_classes, len(probs)))
+    sizes = np.array([len(p["T"]) for p in probs])
+    edges = np.quantile(sizes, np.linspace(0, 1, K + 1))[1:-1] if K > 1 else []
+    cls = np.searchsorted(edges, sizes, side="right") if K > 1 else np.zeros(len(probs), dtype=int)
+    ctxs = [mfs.Context(0) for _ in range(K)]
+    ctx = ctxs[0]
+    chars = [mfs.Character(ctxs[c], p) for c, p in zip(cls, probs)]
+    members = [[i for i in range(len(chars)) if cls[i] == g] for g in range(K)]
     infos = [c.info() for c in chars]
     m_tot = sum(i["n_tets"] for i in infos)
     extended = {}
     stress_out = None
     for p, c in zip(probs, chars):
         if p.get("smooth_width"):
-            H, W = ctx.blend_weights(p["X"], p["T"], p["seg_a"], p["seg_b"], p["seg_handle"], p["n_handles"],
-                                     p["smooth_width"], 3)
+            H, W = c.ctx.blend_weights(p["X"], p["T"], p["seg_a"], p["seg_b"], p["seg_handle"], p["n_handles"],
+                                       p["smooth_width"], 3)
             c.set_rotation_blend(H, W)
             extended["smoothing_width"] = p["smooth_width"]
             extended["blended_tet_fraction"] = float(np.mean(H[:, 1] >= 0))
@@ -191,8 +200,23 @@ def frame_bench(args, mfs, torch):
     _progress(f"{wname}: {len(chars)} characters resident, {m_tot} tets")
     tuned = None
     if not args.no_autotune:
-        tuned, tms = mfs.autotune(ctx, chars, steps[0], newton_iterations=4, cache_path=args.tune_cache, **opts)
-        _progress(f"autotuned PCG schedule {tuned} ({tms:.1f} ms per 4 Newton iterations)")
+        tuned = []
+        for g in range(K):
+            t, tms = mfs.autotune(ctxs[g], [chars[i] for i in members[g]], [steps[0][i] for i in members[g]],
+                                  newton_iterations=4, cache_path=args.tune_cache, **opts)
+            tuned.append(t)
+            _progress(f"class {g}: autotuned PCG schedule {t} ({tms:.1f} ms per 4 Newton iterations)")
+        tuned = tuned[0] if K == 1 else tuned
+    pool = None
+    if K > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        pool = ThreadPoolExecutor(max_workers=K)
+
+    def batch(g, poses, o):
+        ids = members[g]
+        _, sts, rc = mfs.solve_batch(ctxs[g], [chars[i] for i in ids], [poses[i] for i in ids],
+                                     outs=[outs[i] for i in ids], **o)
+        return ids, sts, rc
 
     def frame(poses, o):
         if len(chars) == 1:
@@ -200,7 +224,14 @@ def frame_bench(args, mfs, torch):
             if stress_out is not None:
                 chars[0].stress(*poses[0], outs[0], out=stress_out[0])
             return [st], rc
-        _, sts, rc = mfs.solve_batch(ctx, chars, poses, outs=outs, **o)
+        if K == 1:
+            _, sts, rc = mfs.solve_batch(ctx, chars, poses, outs=outs, **o)
+            return sts, rc
+        sts, rc = [None] * len(chars), 0
+        for ids, s_, r_ in pool.map(lambda g: batch(g, poses, o), range(K)):
+            for i, st in zip(ids, s_):
+                sts[i] = st
+            rc = max(rc, r_)
         return sts, rc
 
     for i in range(args.warmup):
@@ -229,12 +260,16 @@ def frame_bench(args, mfs, torch):
     # sequence), kernels launched directly, every stride-th launch of each
     # family timed by HIP events carried in its dispatches ----
     nxt = args.warmup + args.steps
-    ctx.profile_enable(args.profile_stride)
-    ctx.profile_read(reset=True)
+    for c in ctxs:
+        c.profile_enable(args.profile_stride)
+        c.profile_read(reset=True)
     for i in range(args.roofline_steps):
         frame(steps[nxt + i], opts)
-    prof = ctx.profile_read(reset=True)
-    ctx.profile_enable(0)
+    prof = {}
+    for c in ctxs:
+        for fam, v in c.profile_read(reset=True).items():
+            prof[fam] = tuple(a + b for a, b in zip(prof.get(fam, (0.0, 0, 0, 0.0)), v))
+        c.profile_enable(0)
     _progress("roofline pass done")
 
     # ---- FP32 + refinement against the FP64 form of the same solve, both
@@ -261,7 +296,8 @@ def frame_bench(args, mfs, torch):
     achieved = spmv_bytes / (spmv_ms * 1e-3) / 1e9 if spmv_ms > 0 else None
     nchar = len(chars)
     fp32 = opts["precision"] == mfs.FP32_REFINED
-    pipelined = fp32 and ctx.tuning()["pcg_pipelined"] == 1
+    big = max(range(K), key=lambda g: sum(sizes[i] for i in members[g]))  # the class with most tets
+    pipelined = fp32 and ctxs[big].tuning()["pcg_pipelined"] == 1
     kernel = ("k_pcg_iter<float>" if pipelined else "k_cg_spmv<float>") if fp32 else "k_cg_spmv<double>"
     result = {
         "metric": "tet*Newton-iter/s (frames/s at 1e-7 rel err; p50/p99 frame latency)",
@@ -299,6 +335,8 @@ def frame_bench(args, mfs, torch):
                    "newton": "fixed 10" if opts.get("fixed_newton") else f"max {opts['max_newton']}",
                    "warm_start": "previous frame" if warm else "rest",
                    "pcg_schedule": tuned or ctx.tuning(),
+                   **({"size_classes": K, "class_tet_edges": [float(e) for e in edges],
+                       "class_sizes": [len(m_) for m_ in members]} if K > 1 else {}),
                    **({"extended": extended} if extended else {})},
         "roofline": {
             "bound": "hbm",
@@ -322,7 +360,10 @@ def frame_bench(args, mfs, torch):
         result["cpu_baseline"] = cpu_baseline(probs[k], steps[args.warmup][k])
     for c in chars:
         c.close()
-    ctx.close()
+    if pool is not None:
+        pool.shutdown()
+    for c in ctxs:
+        c.close()
     return result
 
 
@@ -461,7 +502,7 @@ def main():
     ap.add_argument("--slots", type=int, default=16, help="c5: requests in flight at once")
     ap.add_argument("--queue", type=int, default=512, help="c5: queued requests before rejection")
     ap.add_argument("--size-classes", type=int, default=1,
-                    help="c5: servers (each on its own context and stream) by tet-count class")
+                    help="c4, c5: batches / servers by tet-count class, each on its own context and stream")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: each frame solve runs on a single device and "

@@ -159,8 +159,11 @@ typedef struct mfs_tuning {
   int32_t pcg_lanes_per_row;  /* lanes per block row in the PCG SpMV: 2, 4 or 8 */
   int32_t use_graphs;         /* 1: replay runs of PCG iterations as captured HIP graphs */
   int32_t graph_iterations;   /* PCG iterations per captured graph, 1..64 */
-  int32_t first_check;        /* PCG iterations before the first convergence check */
-  int32_t min_run, max_run;   /* bounds of later runs between checks */
+  int32_t first_check;        /* PCG iterations in the first queued chunk of a solve */
+  int32_t min_run, max_run;   /* later chunks: min_run iterations (at most max_run).  Chunks are
+                                 queued one ahead of the running one; the kernels raise a
+                                 host-mapped flag when a system stops, so the host never
+                                 synchronises to check convergence */
   int32_t pcg_pipelined;      /* 1: FP32_REFINED solves run the pipelined PCG of Ghysels and
                                  Vanroose (one kernel per iteration, dot products overlapped
                                  with the SpMV; FP32 matrix values, FP64 vectors and
