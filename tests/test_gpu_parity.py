@@ -514,3 +514,30 @@ def test_rotation_smoothing(ctx):
     x0, _, rc = ch.solve(*pose, precision=mfs.FP64, step_tol=1e-10, cg_tol=1e-10, max_newton=60)
     assert rc == 0 and np.array_equal(x0, x_cluster)
     ch.close()
+
+
+def test_two_contexts_concurrently(ctx):
+    """Two contexts (two HIP streams) solving batches from two host threads at
+    once give bitwise the results of the same batches solved one after the
+    other: the library keeps no state across contexts."""
+    from concurrent.futures import ThreadPoolExecutor
+    mfs = _mfs()
+    kw = dict(precision=mfs.FP32_REFINED, cg_tol=1e-5, step_tol=1e-9, max_newton=60, cg_adaptive=1)
+    groups = [[(1500, 8), (900, 9)], [(3500, 12), (2500, 10)]]
+    ctxs = [mfs.Context(0), mfs.Context(0)]
+    probs = [[humanoid(1400 + 10 * g + i, target_tets=t, n_bones=b, models=(NH, COROT))
+              for i, (t, b) in enumerate(spec)] for g, spec in enumerate(groups)]
+    chars = [[mfs.Character(c, p) for p in ps] for c, ps in zip(ctxs, probs)]
+    poses = [[random_pose(p, 1500 + i) for i, p in enumerate(ps)] for ps in probs]
+    seq = [mfs.solve_batch(c, ch, po, **kw)[0] for c, ch, po in zip(ctxs, chars, poses)]
+    _say("two contexts from two threads")
+    with ThreadPoolExecutor(max_workers=2) as ex:
+        par = list(ex.map(lambda g: mfs.solve_batch(ctxs[g], chars[g], poses[g], **kw)[0], range(2)))
+    for a, b in zip(seq, par):
+        for xa, xb in zip(a, b):
+            assert np.array_equal(xa, xb)
+    for ch in chars:
+        for c in ch:
+            c.close()
+    for c in ctxs:
+        c.close()
