@@ -26,7 +26,11 @@ pipelined form, lanes per row, graph length, run sizing) on the first
 step's frames (``--no-autotune`` keeps the default).
 * ``c5``: serving: a pool of characters of 2k-300k tets and a Poisson stream
   of frame requests (fresh random pose of a uniformly chosen character)
-  through the continuous-batching server; reports p50/p99 latency.
+  through the continuous-batching server; reports p50/p99 latency.  By
+  default the pool is split at its median size into two classes, each served
+  by its own server on its own context (HIP stream) with half the slots and
+  half the queue, so small characters' frames do not wait on large ones'
+  PCG runs (``--size-classes 1``: one server for the whole pool).
 
 The timed path (c2-c5) is the FP32 + FP64-refinement form (FP32 Hessian
 values and PCG; FP64 residual, energies and updates), inexact Newton
@@ -501,9 +505,12 @@ def main():
     ap.add_argument("--duration", type=float, default=60.0, help="c5: seconds of arrivals")
     ap.add_argument("--slots", type=int, default=16, help="c5: requests in flight at once")
     ap.add_argument("--queue", type=int, default=512, help="c5: queued requests before rejection")
-    ap.add_argument("--size-classes", type=int, default=1,
-                    help="c4, c5: batches / servers by tet-count class, each on its own context and stream")
+    ap.add_argument("--size-classes", type=int, default=None,
+                    help="c4, c5: batches / servers by tet-count class, each on its own context and stream "
+                         "(default: 2 for c5, 1 otherwise)")
     args = ap.parse_args()
+    if args.size_classes is None:
+        args.size_classes = 2 if args.workload == "c5" else 1
     if args.gpus != 1:
         print("bench.py measures one GPU: each frame solve runs on a single device and "
               "multi-GPU sharding is not implemented", file=sys.stderr)
