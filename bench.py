@@ -374,8 +374,9 @@ def frame_bench(args, mfs, torch):
 def serve_bench(args, mfs, torch):
     """Poisson stream of frame requests through the serving loop.  With
     ``--size-classes K`` > 1 the pool is split by tet count into K classes,
-    each served by its own server on its own context (own HIP stream), so the
-    small characters' frames do not wait for the large ones' PCG runs and the
+    each served by its own lane of one server (a batch on its own context and
+    HIP stream, with the PCG schedule autotuned for that class), so the small
+    characters' frames do not wait for the large ones' PCG runs and the
     streams overlap on the GPU; the slots are divided between the classes."""
     from workloads import NH, COROT, ARAP, character_pool, random_pose
     probs = character_pool(args.pool, 5001, (2000, 300000), (8, 30), (NH, COROT, ARAP),
@@ -384,9 +385,10 @@ def serve_bench(args, mfs, torch):
     sizes = np.array([len(p["T"]) for p in probs])
     edges = np.quantile(sizes, np.linspace(0, 1, K + 1))[1:-1] if K > 1 else []
     cls = np.searchsorted(edges, sizes, side="right") if K > 1 else np.zeros(len(probs), dtype=int)
-    ctxs = [mfs.Context(0) for _ in range(K)]
-    chars = [mfs.Character(ctxs[c], p) for c, p in zip(cls, probs)]
+    ctx = mfs.Context(0)
+    chars = [mfs.Character(ctx, p) for p in probs]
     infos = [c.info() for c in chars]
+    lane_max = [int(sizes[cls == g].max()) for g in range(K - 1)]  # lane g takes tets <= lane_max[g]
     slots = [max(1, args.slots // K)] * K
     budgets = []
     for g in range(K):
@@ -407,48 +409,49 @@ def serve_bench(args, mfs, torch):
             sample = members[::max(1, len(members) // slots[g])][:slots[g]]
             for k in sample:
                 chars[k].solve(*random_pose(probs[k], 1), **opts)  # re-creates the released workspace
-            t, tms = mfs.autotune(ctxs[g], [chars[k] for k in sample], [random_pose(probs[k], 1) for k in sample],
+            t, tms = mfs.autotune(ctx, [chars[k] for k in sample], [random_pose(probs[k], 1) for k in sample],
                                   newton_iterations=4, cache_path=args.tune_cache, **opts)
             for k in sample:
                 chars[k].release_workspace()
             tuned.append(t)
             _progress(f"class {g}: autotuned PCG schedule {t} ({tms:.1f} ms per 4 Newton iterations)")
     queue = max(1, args.queue // K)  # the same total queue capacity however the pool is split
-    srvs = [mfs.Server(ctxs[g], slots=slots[g], queue_capacity=queue, workspace_budget_bytes=budgets[g],
-                       **opts) for g in range(K)]
+    srv = mfs.Server(ctx, slots=slots[0], queue_capacity=queue, workspace_budget_bytes=max(budgets),
+                     lane_max_tets=lane_max, **opts)
+    for g, t in enumerate(tuned):
+        srv.set_lane_tuning(g, **t)
     for j in range(min(args.warmup, n_req)):  # warm the kernels and graphs
-        srvs[cls[who[j]]].wait(srvs[cls[who[j]]].submit(chars[who[j]], *poses[j]))
-    info0 = [s.info() for s in srvs]
+        srv.wait(srv.submit(chars[who[j]], *poses[j]))
+    info0 = srv.info()
     tickets, rejected = [], 0
     t0 = time.perf_counter()
     _progress(f"pool of {len(chars)} characters resident in {K} size class(es); streaming {n_req} requests")
     for j in range(n_req):
         if j % 1000 == 0 and j:
-            _progress(f"submitted {j} requests, {sum(s.info()['completed'] for s in srvs)} completed")
+            _progress(f"submitted {j} requests, {srv.info()['completed']} completed")
         delay = arrivals[j] - (time.perf_counter() - t0)
         if delay > 0:
             time.sleep(delay)
         k = who[j]
         try:
-            tickets.append((k, srvs[cls[k]].submit(chars[k], *poses[j])))
+            tickets.append((k, srv.submit(chars[k], *poses[j])))
         except mfs.MfsError as e:
             if e.code != -6:
                 raise
             rejected += 1
     lat, tet_iters, done_t, conv, first_submit = [], 0, [], [], None
     for k, tk in tickets:
-        _, st, tm, _ = srvs[cls[k]].wait(tk)
+        _, st, tm, _ = srv.wait(tk)
         lat.append(tm["done_s"] - tm["submit_s"])
         first_submit = tm["submit_s"] if first_submit is None else min(first_submit, tm["submit_s"])
         done_t.append(tm["done_s"])
         tet_iters += infos[k]["n_tets"] * st["iterations"]
         conv.append(st["status"] == 0)
-    info = [s.info() for s in srvs]
-    for s_ in srvs:
-        s_.close()
+    info = srv.info()
+    srv.close()
     span = max(done_t) - first_submit
-    steps = sum(i1["steps"] - i0["steps"] for i0, i1 in zip(info0, info))
-    slot_steps = sum(i1["slot_steps"] - i0["slot_steps"] for i0, i1 in zip(info0, info))
+    steps = info["steps"] - info0["steps"]
+    slot_steps = info["slot_steps"] - info0["slot_steps"]
     result = {
         "metric": "tet*Newton-iter/s (frames/s at 1e-7 rel err; p50/p99 frame latency)",
         "value": tet_iters / span,
@@ -470,18 +473,17 @@ def serve_bench(args, mfs, torch):
         "rejected_queue_full": rejected,
         "converged_fraction": float(np.mean(conv)),
         "mean_batch_width": slot_steps / max(steps, 1),
-        "arena_peak_bytes": sum(i["arena_peak"] for i in info),
+        "arena_peak_bytes": info["arena_peak"],
         "config": {"workload": f"serving_pool_{args.pool}_humanoids_2k_300k_tets_poisson_{args.rate:g}_per_s",
                    "characters": len(chars), "tets": int(sizes.sum()),
-                   "size_classes": K, "class_tet_edges": [float(e) for e in edges],
-                   "slots": slots, "queue_capacity": [queue] * K, "arena_bytes": budgets,
+                   "size_classes": K, "lane_max_tets": lane_max,
+                   "slots_per_lane": slots[0], "queue_capacity_per_lane": queue, "arena_bytes_per_lane": max(budgets),
                    "duration_s": args.duration, "precision": "fp32 pcg + fp64 refinement",
-                   "pcg_schedule": tuned or [c.tuning() for c in ctxs]},
+                   "pcg_schedule": tuned or [ctx.tuning()]},
     }
     for c in chars:
         c.close()
-    for c in ctxs:
-        c.close()
+    ctx.close()
     return result
 
 def main():

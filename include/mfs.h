@@ -318,6 +318,14 @@ int mfs_autotune(mfs_context* ctx, int32_t count, mfs_character* const* chars,
  * thread owns the context's stream while the server exists: between
  * server_create and server_destroy the context and its characters are used
  * only through mfs_server_* calls (which may come from any host thread).
+ * With lanes > 1 the server runs that many such loops at once, each with
+ * its own worker thread, batch and stream (lane 0 on the caller's context,
+ * the others on contexts the server creates on the same device with the
+ * caller's PCG tuning, destroyed with the server); a request goes to the
+ * first lane i whose lane_max_tets[i] is at least its character's tet count,
+ * else to the last lane, so small characters are not held back by the long
+ * PCG solves of large ones in a shared batch.  slots, queue_capacity and
+ * workspace_budget_bytes hold per lane.
  * Each request is one frame solve (as mfs_solve_frame, with the server's
  * solve options).  Between Newton steps the worker admits queued requests
  * in submission order into free slots of the running batch; a request
@@ -334,6 +342,9 @@ typedef struct mfs_server_opts {
   uint64_t workspace_budget_bytes;  /* device arena lent to requests whose character has no
                                        workspace of its own; 0 = no arena */
   mfs_solve_opts solve;             /* options of every solve; output_memory must be host */
+  int32_t lanes;                    /* concurrent batches, 1..4 */
+  int32_t reserved;                 /* 0 */
+  int64_t lane_max_tets[3];         /* size-class bounds of lanes 0..lanes-2, increasing */
 } mfs_server_opts;
 
 typedef struct mfs_request_times {  /* seconds since the server was created (steady clock) */
@@ -352,7 +363,7 @@ typedef struct mfs_server_info {
                                        (slot_steps / steps = mean batch width) */
 } mfs_server_info;
 
-/* slots 16, queue 4096, no arena, mfs_default_opts. */
+/* slots 16, queue 4096, no arena, mfs_default_opts, one lane. */
 void mfs_default_server_opts(mfs_server_opts* opts);
 /* opts may be NULL (defaults).  Errors: MFS_E_INVALID, MFS_E_UNSUPPORTED,
  * MFS_E_OOM (arena), MFS_E_HIP. */
@@ -375,6 +386,13 @@ int mfs_server_wait(mfs_server* srv, uint64_t ticket, double* x_out, mfs_solve_s
                     mfs_request_times* times);
 /* Counters of the server; returns the worker's error if it stopped on one. */
 int mfs_server_get_info(mfs_server* srv, mfs_server_info* info);
+/* Sets the PCG schedule (as mfs_context_set_tuning) of one lane, 0..lanes-1;
+ * a lane starts with the caller's context's schedule.  The lane's worker
+ * applies it before its next Newton step, so frames in flight may run some
+ * steps under each schedule.  Lets each size class run the schedule that
+ * mfs_autotune chose for a batch of its characters.  Errors: MFS_E_INVALID
+ * (lane out of range, a field out of range). */
+int mfs_server_set_lane_tuning(mfs_server* srv, int32_t lane, const mfs_tuning* tuning);
 
 /* ---- introspection and profiling ------------------------------------- */
 

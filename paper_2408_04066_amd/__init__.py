@@ -33,6 +33,7 @@ EXPORTED = ("mfs_default_opts", "mfs_status_string", "mfs_last_error", "mfs_cont
             "mfs_profile_enable", "mfs_profile_read", "mfs_context_get_tuning",
             "mfs_context_set_tuning", "mfs_character_release_workspace", "mfs_default_server_opts",
             "mfs_server_create", "mfs_server_destroy", "mfs_server_submit", "mfs_server_poll",
+            "mfs_server_set_lane_tuning",
             "mfs_server_wait", "mfs_server_get_info", "mfs_autotune", "mfs_character_set_forces",
             "mfs_stress")
 
@@ -100,7 +101,7 @@ _lib = None
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("slots", c_i32), ("queue_capacity", c_i32), ("workspace_budget_bytes", ctypes.c_uint64),
-                ("solve", SolveOpts)]
+                ("solve", SolveOpts), ("lanes", c_i32), ("reserved", c_i32), ("lane_max_tets", c_i64 * 3)]
 
 
 class RequestTimes(ctypes.Structure):
@@ -157,6 +158,7 @@ def lib():
                                            P(c_i32)]),
         "mfs_server_wait": (ctypes.c_int, [c_vp, ctypes.c_uint64, c_vp, P(SolveStats), P(RequestTimes)]),
         "mfs_server_get_info": (ctypes.c_int, [c_vp, P(ServerInfo)]),
+        "mfs_server_set_lane_tuning": (ctypes.c_int, [c_vp, c_i32, P(Tuning)]),
         "mfs_autotune": (ctypes.c_int, [c_vp, c_i32, c_vp, c_vp, c_vp, P(SolveOpts), c_i32, ctypes.c_char_p,
                                         c_i32, P(Tuning), P(c_dbl)]),
     }
@@ -462,12 +464,25 @@ class Server:
     context and its characters only through the server.  ``submit`` returns
     a ticket at once; ``poll`` returns None until the frame is done, then
     (x, stats, times, rc); ``wait`` blocks for it.  ``times`` holds submit,
-    admit and completion times in seconds on the server's clock."""
+    admit and completion times in seconds on the server's clock.
 
-    def __init__(self, ctx, slots=16, queue_capacity=4096, workspace_budget_bytes=0, **solve_opts):
+    ``lane_max_tets`` (a list of up to three increasing tet counts) splits the
+    server into ``len(lane_max_tets) + 1`` lanes, each a batch of its own on a
+    stream of its own: a character goes to the first lane whose bound is at
+    least its tet count, else to the last.  ``slots``, ``queue_capacity`` and
+    ``workspace_budget_bytes`` hold per lane."""
+
+    def __init__(self, ctx, slots=16, queue_capacity=4096, workspace_budget_bytes=0, lane_max_tets=(),
+                 **solve_opts):
         o = ServerOpts()
         lib().mfs_default_server_opts(ctypes.byref(o))
         o.slots, o.queue_capacity = slots, queue_capacity
+        bounds = [int(v) for v in lane_max_tets]
+        if len(bounds) > 3:
+            raise ValueError("at most three lane bounds (four lanes)")
+        o.lanes = len(bounds) + 1
+        for i, v in enumerate(bounds):
+            o.lane_max_tets[i] = v
         o.workspace_budget_bytes = int(workspace_budget_bytes)
         o.solve = default_opts(**solve_opts)
         o.solve.output_memory = MEM_HOST
@@ -520,3 +535,15 @@ class Server:
         i = ServerInfo()
         _check(lib().mfs_server_get_info(self.handle, ctypes.byref(i)))
         return {k: getattr(i, k) for k, _ in i._fields_}
+
+    def set_lane_tuning(self, lane, **tuning):
+        """PCG schedule of one lane (fields as ``Context.tuning()``; the ones
+        not given keep the caller's context's values), applied by the lane
+        before its next Newton step."""
+        t = Tuning()
+        _check(lib().mfs_context_get_tuning(self.ctx.handle, ctypes.byref(t)))
+        for k, v in tuning.items():
+            if not hasattr(t, k):
+                raise TypeError(f"unknown tuning field {k}")
+            setattr(t, k, int(v))
+        _check(lib().mfs_server_set_lane_tuning(self.handle, int(lane), ctypes.byref(t)))

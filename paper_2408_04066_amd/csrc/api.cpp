@@ -219,9 +219,8 @@ extern "C" int mfs_context_get_tuning(const mfs_context* ctx, mfs_tuning* out) {
   return MFS_OK;
 }
 
-extern "C" int mfs_context_set_tuning(mfs_context* ctx, const mfs_tuning* t) {
-  clear_error();
-  if (!ctx || !t) return set_error(MFS_E_INVALID, "null argument");
+int mfs::check_tuning(const mfs_tuning* t) {
+  if (!t) return set_error(MFS_E_INVALID, "null tuning");
   if (t->pcg_lanes_per_row != 2 && t->pcg_lanes_per_row != 4 && t->pcg_lanes_per_row != 8)
     return set_error(MFS_E_INVALID, "pcg_lanes_per_row must be 2, 4 or 8");
   if (t->graph_iterations < 1 || t->graph_iterations > 64)
@@ -232,6 +231,13 @@ extern "C" int mfs_context_set_tuning(mfs_context* ctx, const mfs_tuning* t) {
   if (t->allread_max_tiles < 0) return set_error(MFS_E_INVALID, "allread_max_tiles must be >= 0");
   if (t->pcg_persistent != 0 && t->pcg_persistent != 1)
     return set_error(MFS_E_INVALID, "pcg_persistent must be 0 or 1");
+  return MFS_OK;
+}
+
+extern "C" int mfs_context_set_tuning(mfs_context* ctx, const mfs_tuning* t) {
+  clear_error();
+  if (!ctx || !t) return set_error(MFS_E_INVALID, "null argument");
+  MFS_TRY(check_tuning(t));
   MFS_HIP(hipSetDevice(ctx->device));
   MFS_HIP(hipStreamSynchronize(ctx->stream));
   for (const CgGraph& g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);

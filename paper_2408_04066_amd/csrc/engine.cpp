@@ -295,7 +295,7 @@ int Engine::set_pose(int i, double tau) {
       }
     }
   }
-  return upload_pose(S.ch, S.Rc.data(), S.tc.data());
+  return upload_pose(ctx_, S.ch, S.Rc.data(), S.tc.data());
 }
 
 // Start a new load step from the state in xb: the slot re-enters the mixed
@@ -358,7 +358,10 @@ bool Engine::any_busy() const {
 
 int Engine::attach(int i, mfs_character* ch, const double* R, const double* t) {
   if (i < 0 || i >= (int)slot_.size() || slot_[i].used) return set_error(MFS_E_INVALID, "slot %d unavailable", i);
-  if (!ch || ch->ctx != ctx_) return set_error(MFS_E_INVALID, "character is null or of another context");
+  // A character may come from another context on the same device (a server
+  // lane runs on a context of its own); its frame then runs on this stream.
+  if (!ch || ch->ctx->device != ctx_->device)
+    return set_error(MFS_E_INVALID, "character is null or on another device");
   for (const SlotState& s : slot_)
     if (s.used && s.ch == ch) return set_error(MFS_E_INVALID, "character already has a frame in flight");
   MFS_TRY(check_pose(ch, R, t));

@@ -202,6 +202,11 @@ struct ProfScope {
 };
 // Fold completed event pairs into the counters (call after a stream sync).
 void prof_resolve(mfs_context* c);
-int upload_pose(mfs_character* ch, const double* R, const double* t);
+// MFS_OK when every field of t is in its documented range.
+int check_tuning(const mfs_tuning* t);
+
+// Uploads a validated pose into the character's pose buffers on ctx's stream
+// (and smooths the per-tet rotations there when the character has a blend).
+int upload_pose(mfs_context* ctx, mfs_character* ch, const double* R, const double* t);
 
 }  // namespace mfs

@@ -106,7 +106,11 @@ struct Request {
 
 using namespace mfs;
 
-struct mfs_server {
+namespace mfs {
+namespace {
+
+// One lane: a worker thread, its context's stream and one batch Engine.
+struct ServerLane {
   mfs_context* ctx = nullptr;
   mfs_server_opts o{};
   Engine eng;
@@ -125,8 +129,10 @@ struct mfs_server {
   double slot_steps = 0.0;
   std::chrono::steady_clock::time_point origin = std::chrono::steady_clock::now();
   std::thread worker;
+  bool retune = false;  // a PCG schedule waits to be applied between steps
+  mfs_tuning tuning{};
 
-  explicit mfs_server(mfs_context* c) : ctx(c), eng(c) {}
+  explicit ServerLane(mfs_context* c) : ctx(c), eng(c) {}
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - origin).count();
   }
@@ -136,7 +142,7 @@ struct mfs_server {
   int complete_finished();
 };
 
-void mfs_server::fail_all_locked(int code, const std::string& msg) {
+void ServerLane::fail_all_locked(int code, const std::string& msg) {
   fatal = code;
   fatal_msg = msg;
   for (auto& kv : reqs) {
@@ -156,7 +162,7 @@ void mfs_server::fail_all_locked(int code, const std::string& msg) {
 // skipping requests whose character has a frame in flight; stop at the
 // first request whose workspace does not fit the arena (so a large request
 // is not starved by smaller ones behind it).
-void mfs_server::admit_locked() {
+void ServerLane::admit_locked() {
   for (auto it = queue.begin(); it != queue.end();) {
     int slot = -1;
     for (int i = 0; i < (int)slot_req.size(); ++i)
@@ -200,7 +206,7 @@ void mfs_server::admit_locked() {
 }
 
 // Worker only: copy out and retire every finished slot.
-int mfs_server::complete_finished() {
+int ServerLane::complete_finished() {
   bool any = false;
   for (int i = 0; i < eng.slots(); ++i) any = any || eng.finished(i);
   if (!any) return MFS_OK;
@@ -235,13 +241,21 @@ int mfs_server::complete_finished() {
   return MFS_OK;
 }
 
-void mfs_server::run() {
+void ServerLane::run() {
   (void)hipSetDevice(ctx->device);
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(mu);
       cv_work.wait(lk, [&] { return stop || !queue.empty() || eng.any_busy(); });
       if (stop) return;
+      if (retune) {  // between steps: no kernel of this lane is in flight after the sync inside
+        retune = false;
+        const int rc = mfs_context_set_tuning(ctx, &tuning);
+        if (rc < 0) {
+          fail_all_locked(rc, last_error_text());
+          return;
+        }
+      }
       admit_locked();
       if (!eng.any_busy()) continue;  // everything admitted this round failed
       int occupied = 0;
@@ -260,6 +274,9 @@ void mfs_server::run() {
   }
 }
 
+}  // namespace
+}  // namespace mfs
+
 extern "C" void mfs_default_server_opts(mfs_server_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof *o);
@@ -267,39 +284,51 @@ extern "C" void mfs_default_server_opts(mfs_server_opts* o) {
   o->queue_capacity = 4096;
   o->workspace_budget_bytes = 0;
   mfs_default_opts(&o->solve);
+  o->lanes = 1;
 }
 
-extern "C" int mfs_server_create(mfs_context* ctx, const mfs_server_opts* opts, mfs_server** out) {
-  clear_error();
-  if (!ctx || !out) return set_error(MFS_E_INVALID, "null context or output");
-  *out = nullptr;
-  mfs_server_opts o;
-  mfs_default_server_opts(&o);
-  if (opts) o = *opts;
-  if (o.slots < 1 || o.slots > 1024) return set_error(MFS_E_INVALID, "slots must be in 1..1024");
-  if (o.queue_capacity < 1) return set_error(MFS_E_INVALID, "queue capacity must be positive");
-  if (o.solve.output_memory != MFS_MEM_HOST)
-    return set_error(MFS_E_UNSUPPORTED, "server results are returned in host memory");
+// The server: lanes of their own (lane 0 on the caller's context, the others
+// on contexts of their own on the same device, each with its own stream),
+// a request going to the lane of its character's size class.  Tickets carry
+// the lane in their low bits.
+constexpr int kMaxLanes = 4;
+
+struct mfs_server {
+  mfs_context* ctx = nullptr;  // the caller's context (characters belong to it)
+  std::vector<std::unique_ptr<mfs::ServerLane>> lanes;
+  std::vector<mfs_context*> own_ctx;  // contexts made for lanes 1.. (destroyed with the server)
+  std::vector<int64_t> max_tets;      // lane i < lanes - 1 takes characters of at most max_tets[i] tets
+  int lane_of(const mfs_character* ch) const {
+    for (size_t i = 0; i < max_tets.size(); ++i)
+      if (ch->m <= max_tets[i]) return (int)i;
+    return (int)lanes.size() - 1;
+  }
+  ~mfs_server();
+};
+
+namespace mfs {
+namespace {
+
+int lane_start(mfs_context* ctx, const mfs_server_opts& o, std::unique_ptr<ServerLane>* out) {
   MFS_HIP(hipSetDevice(ctx->device));
-  std::unique_ptr<mfs_server> s(new mfs_server(ctx));
+  std::unique_ptr<ServerLane> s(new ServerLane(ctx));
   s->o = o;
   MFS_TRY(s->eng.configure(&o.solve));
   MFS_TRY(s->eng.reserve(o.slots));
   MFS_TRY(s->arena.init(o.workspace_budget_bytes));
   s->slot_req.assign(o.slots, 0);
   MFS_HIP(hipStreamSynchronize(ctx->stream));
-  mfs_server* raw = s.get();
+  ServerLane* raw = s.get();
   try {
     s->worker = std::thread([raw] { raw->run(); });
   } catch (...) {
-    return set_error(MFS_E_UNSUPPORTED, "could not start the server thread");
+    return set_error(MFS_E_UNSUPPORTED, "could not start a server thread");
   }
-  *out = s.release();
+  *out = std::move(s);
   return MFS_OK;
 }
 
-extern "C" int mfs_server_destroy(mfs_server* s) {
-  if (!s) return MFS_OK;
+void lane_stop(ServerLane* s) {
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
@@ -308,16 +337,9 @@ extern "C" int mfs_server_destroy(mfs_server* s) {
   if (s->worker.joinable()) s->worker.join();
   (void)hipSetDevice(s->ctx->device);
   (void)hipStreamSynchronize(s->ctx->stream);
-  delete s;
-  return MFS_OK;
 }
 
-extern "C" int mfs_server_submit(mfs_server* s, mfs_character* ch, const double* R, const double* t,
-                                 uint64_t* ticket) {
-  clear_error();
-  if (!s || !ch || !ticket) return set_error(MFS_E_INVALID, "null server, character or ticket");
-  if (ch->ctx != s->ctx) return set_error(MFS_E_INVALID, "character belongs to another context");
-  MFS_TRY(check_pose(ch, R, t));
+int lane_submit(ServerLane* s, mfs_character* ch, const double* R, const double* t, uint64_t* ticket) {
   Request r;
   r.ch = ch;
   r.R.assign(R, R + 9 * (size_t)ch->nh);
@@ -341,8 +363,8 @@ extern "C" int mfs_server_submit(mfs_server* s, mfs_character* ch, const double*
   return MFS_OK;
 }
 
-static int take_result(mfs_server* s, std::unique_lock<std::mutex>& lk, uint64_t ticket, double* x_out,
-                       mfs_solve_stats* stats, mfs_request_times* times) {
+int take_result(ServerLane* s, std::unique_lock<std::mutex>& lk, uint64_t ticket, double* x_out,
+                mfs_solve_stats* stats, mfs_request_times* times) {
   auto it = s->reqs.find(ticket);
   Request& r = it->second;
   const int status = r.status;
@@ -357,52 +379,151 @@ static int take_result(mfs_server* s, std::unique_lock<std::mutex>& lk, uint64_t
   return status;
 }
 
+int decode(mfs_server* s, uint64_t ticket, ServerLane** lane, uint64_t* lane_ticket) {
+  const uint64_t l = ticket % kMaxLanes;
+  if (l >= s->lanes.size()) return set_error(MFS_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+  *lane = s->lanes[l].get();
+  *lane_ticket = ticket / kMaxLanes;
+  return MFS_OK;
+}
+
+}  // namespace
+}  // namespace mfs
+
+mfs_server::~mfs_server() {
+  for (auto& l : lanes) mfs::lane_stop(l.get());
+  lanes.clear();
+  for (mfs_context* c : own_ctx) (void)mfs_context_destroy(c);
+}
+
+extern "C" int mfs_server_create(mfs_context* ctx, const mfs_server_opts* opts, mfs_server** out) {
+  clear_error();
+  if (!ctx || !out) return set_error(MFS_E_INVALID, "null context or output");
+  *out = nullptr;
+  mfs_server_opts o;
+  mfs_default_server_opts(&o);
+  if (opts) o = *opts;
+  if (o.slots < 1 || o.slots > 1024) return set_error(MFS_E_INVALID, "slots must be in 1..1024");
+  if (o.queue_capacity < 1) return set_error(MFS_E_INVALID, "queue capacity must be positive");
+  if (o.lanes < 1 || o.lanes > kMaxLanes) return set_error(MFS_E_INVALID, "lanes must be in 1..%d", kMaxLanes);
+  for (int i = 0; i + 1 < o.lanes; ++i)
+    if (o.lane_max_tets[i] < 1 || (i > 0 && o.lane_max_tets[i] <= o.lane_max_tets[i - 1]))
+      return set_error(MFS_E_INVALID, "lane_max_tets must be positive and increasing");
+  if (o.solve.output_memory != MFS_MEM_HOST)
+    return set_error(MFS_E_UNSUPPORTED, "server results are returned in host memory");
+  MFS_HIP(hipSetDevice(ctx->device));
+  std::unique_ptr<mfs_server> s(new mfs_server());
+  s->ctx = ctx;
+  s->max_tets.assign(o.lane_max_tets, o.lane_max_tets + (o.lanes - 1));
+  mfs_tuning tuning;
+  MFS_TRY(mfs_context_get_tuning(ctx, &tuning));
+  for (int l = 0; l < o.lanes; ++l) {
+    mfs_context* lc = ctx;
+    if (l > 0) {  // a context of its own (own stream), with the caller's PCG schedule
+      MFS_TRY(mfs_context_create(ctx->device, nullptr, &lc));
+      s->own_ctx.push_back(lc);
+      MFS_TRY(mfs_context_set_tuning(lc, &tuning));
+    }
+    std::unique_ptr<ServerLane> lane;
+    MFS_TRY(lane_start(lc, o, &lane));
+    s->lanes.push_back(std::move(lane));
+  }
+  *out = s.release();
+  return MFS_OK;
+}
+
+extern "C" int mfs_server_destroy(mfs_server* s) {
+  if (!s) return MFS_OK;
+  delete s;
+  return MFS_OK;
+}
+
+extern "C" int mfs_server_submit(mfs_server* s, mfs_character* ch, const double* R, const double* t,
+                                 uint64_t* ticket) {
+  clear_error();
+  if (!s || !ch || !ticket) return set_error(MFS_E_INVALID, "null server, character or ticket");
+  if (ch->ctx != s->ctx) return set_error(MFS_E_INVALID, "character belongs to another context");
+  MFS_TRY(check_pose(ch, R, t));
+  const int l = s->lane_of(ch);
+  uint64_t tk = 0;
+  MFS_TRY(lane_submit(s->lanes[l].get(), ch, R, t, &tk));
+  *ticket = tk * kMaxLanes + (uint64_t)l;
+  return MFS_OK;
+}
+
 extern "C" int mfs_server_poll(mfs_server* s, uint64_t ticket, double* x_out, mfs_solve_stats* stats,
                                mfs_request_times* times, int32_t* done) {
   clear_error();
   if (!s || !done) return set_error(MFS_E_INVALID, "null server or done flag");
-  std::unique_lock<std::mutex> lk(s->mu);
-  auto it = s->reqs.find(ticket);
-  if (it == s->reqs.end()) return set_error(MFS_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+  ServerLane* lane;
+  uint64_t tk;
+  MFS_TRY(decode(s, ticket, &lane, &tk));
+  std::unique_lock<std::mutex> lk(lane->mu);
+  auto it = lane->reqs.find(tk);
+  if (it == lane->reqs.end()) return set_error(MFS_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
   if (it->second.state != kDone) {
     *done = 0;
     return MFS_OK;
   }
   *done = 1;
-  return take_result(s, lk, ticket, x_out, stats, times);
+  return take_result(lane, lk, tk, x_out, stats, times);
 }
 
 extern "C" int mfs_server_wait(mfs_server* s, uint64_t ticket, double* x_out, mfs_solve_stats* stats,
                                mfs_request_times* times) {
   clear_error();
   if (!s) return set_error(MFS_E_INVALID, "null server");
-  std::unique_lock<std::mutex> lk(s->mu);
-  auto it = s->reqs.find(ticket);
-  if (it == s->reqs.end()) return set_error(MFS_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
-  s->cv_done.wait(lk, [&] {
-    auto j = s->reqs.find(ticket);
-    return j == s->reqs.end() || j->second.state == kDone;
+  ServerLane* lane;
+  uint64_t tk;
+  MFS_TRY(decode(s, ticket, &lane, &tk));
+  std::unique_lock<std::mutex> lk(lane->mu);
+  auto it = lane->reqs.find(tk);
+  if (it == lane->reqs.end()) return set_error(MFS_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+  lane->cv_done.wait(lk, [&] {
+    auto j = lane->reqs.find(tk);
+    return j == lane->reqs.end() || j->second.state == kDone;
   });
-  if (s->reqs.find(ticket) == s->reqs.end())
+  if (lane->reqs.find(tk) == lane->reqs.end())
     return set_error(MFS_E_INVALID, "ticket %llu was taken by another caller", (unsigned long long)ticket);
-  return take_result(s, lk, ticket, x_out, stats, times);
+  return take_result(lane, lk, tk, x_out, stats, times);
+}
+
+extern "C" int mfs_server_set_lane_tuning(mfs_server* s, int32_t lane, const mfs_tuning* t) {
+  clear_error();
+  if (!s || !t) return set_error(MFS_E_INVALID, "null server or tuning");
+  if (lane < 0 || lane >= (int)s->lanes.size()) return set_error(MFS_E_INVALID, "lane %d out of range", lane);
+  MFS_TRY(check_tuning(t));
+  mfs::ServerLane* l = s->lanes[lane].get();
+  std::lock_guard<std::mutex> lk(l->mu);
+  if (l->fatal < 0) return set_error(l->fatal, "server stopped: %s", l->fatal_msg.c_str());
+  l->tuning = *t;
+  l->retune = true;
+  l->cv_work.notify_one();
+  return MFS_OK;
 }
 
 extern "C" int mfs_server_get_info(mfs_server* s, mfs_server_info* info) {
   clear_error();
   if (!s || !info) return set_error(MFS_E_INVALID, "null server or info");
-  std::lock_guard<std::mutex> lk(s->mu);
   std::memset(info, 0, sizeof *info);
-  info->submitted = s->submitted;
-  info->completed = s->completed;
-  info->steps = s->steps;
-  info->queued = (int32_t)s->queue.size();
-  int running = 0;
-  for (uint64_t tk : s->slot_req) running += tk != 0;
-  info->running = running;
-  info->arena_bytes = s->arena.capacity();
-  info->arena_in_use = s->arena.in_use();
-  info->arena_peak = s->arena.peak();
-  info->slot_steps = s->slot_steps;
-  return s->fatal < 0 ? set_error(s->fatal, "server stopped: %s", s->fatal_msg.c_str()) : MFS_OK;
+  int fatal = MFS_OK;
+  std::string msg;
+  for (auto& lp : s->lanes) {
+    ServerLane* l = lp.get();
+    std::lock_guard<std::mutex> lk(l->mu);
+    info->submitted += l->submitted;
+    info->completed += l->completed;
+    info->steps += l->steps;
+    info->queued += (int32_t)l->queue.size();
+    for (uint64_t tk : l->slot_req) info->running += tk != 0;
+    info->arena_bytes += l->arena.capacity();
+    info->arena_in_use += l->arena.in_use();
+    info->arena_peak += l->arena.peak();
+    info->slot_steps += l->slot_steps;
+    if (l->fatal < 0 && fatal == MFS_OK) {
+      fatal = l->fatal;
+      msg = l->fatal_msg;
+    }
+  }
+  return fatal < 0 ? set_error(fatal, "server stopped: %s", msg.c_str()) : MFS_OK;
 }

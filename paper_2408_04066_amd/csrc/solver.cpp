@@ -49,10 +49,10 @@ int check_pose(const mfs_character* ch, const double* R, const double* t) {
   return MFS_OK;
 }
 
-int upload_pose(mfs_character* ch, const double* R, const double* t) {
-  hipStream_t st = ch->ctx->stream;
-  MFS_TRY(ch->ctx->up.upload(st, ch->Rh.p, R, 9 * sizeof(double) * ch->nh));
-  MFS_TRY(ch->ctx->up.upload(st, ch->th.p, t, 3 * sizeof(double) * ch->nh));
+int upload_pose(mfs_context* ctx, mfs_character* ch, const double* R, const double* t) {
+  hipStream_t st = ctx->stream;
+  MFS_TRY(ctx->up.upload(st, ch->Rh.p, R, 9 * sizeof(double) * ch->nh));
+  MFS_TRY(ctx->up.upload(st, ch->th.p, t, 3 * sizeof(double) * ch->nh));
   if (ch->blend_k > 0)  // smoothed tet rotations follow every pose (and load step)
     launch_blend_rot(st, ch->Rh.as<double>(), ch->m, ch->blend_k, ch->blend_h.as<int32_t>(), ch->blend_w.as<double>(),
                      ch->Rt.as<double>());
@@ -136,7 +136,7 @@ extern "C" int mfs_evaluate(mfs_character* ch, const double* handle_R, const dou
   hd.cg = ctx->cg.as<CgState>();
   hd.ctrl = ctx->ctrl.as<Ctrl>();
   MFS_TRY(ctx->up.upload(st, ctx->desc.p, &hd, sizeof(SysDesc)));
-  MFS_TRY(upload_pose(ch, handle_R, handle_t));
+  MFS_TRY(upload_pose(ctx, ch, handle_R, handle_t));
   double* tmp = ctx->tmp.as<double>();
   const double* xs = x;
   if (host) {
@@ -209,7 +209,7 @@ extern "C" int mfs_stress(mfs_character* ch, const double* handle_R, const doubl
   MFS_TRY(ctx->desc.reserve(sizeof(SysDesc)));
   MFS_HIP(hipStreamSynchronize(st));
   MFS_TRY(ctx->up.upload(st, ctx->desc.p, &ch->desc, sizeof(SysDesc)));
-  MFS_TRY(upload_pose(ch, handle_R, handle_t));
+  MFS_TRY(upload_pose(ctx, ch, handle_R, handle_t));
   double* tmp = ctx->tmp.as<double>();
   const double* xs = x;
   if (host) {

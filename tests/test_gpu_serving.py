@@ -193,3 +193,58 @@ def test_served_with_loads_and_smoothed_rotations(mfs_ctx):
     srv.close()
     for ch in chars:
         ch.close()
+
+
+def test_lanes_route_by_size_and_equal_alone(mfs_ctx):
+    """Three lanes (size classes up to 1200 tets, up to 4000, larger), each
+    a batch on a stream of its own: small, medium and large characters (one
+    with smoothed rotations, one on a lent workspace) served in a mix equal
+    their solves alone bitwise, and the server's counters add up over the
+    lanes."""
+    mfs, ctx = mfs_ctx
+    probs, chars = _chars(mfs, ctx, [(800, 8), (1000, 10), (2500, 12), (3000, 9), (6000, 14)], 1400)
+    p2 = probs[2]
+    H, W = ctx.blend_weights(p2["X"], p2["T"], p2["seg_a"], p2["seg_b"], p2["seg_handle"], p2["n_handles"],
+                             0.05 * p2["bbox_diag"], 3)
+    chars[2].set_rotation_blend(H, W)
+    poses = [random_pose(p, 1500 + i) for i, p in enumerate(probs)]
+    alone = [ch.solve(*pose, **OPTS)[0] for ch, pose in zip(chars, poses)]
+    # the large lane runs another PCG schedule: its reference is solved under it
+    base = ctx.tuning()
+    alt = 8 if base["pcg_lanes_per_row"] != 8 else 4
+    ctx.set_tuning(pcg_lanes_per_row=alt)
+    alone[4] = chars[4].solve(*poses[4], **OPTS)[0]
+    ctx.set_tuning(**base)
+    chars[0].release_workspace()
+    budget = chars[0].footprint()[1] + 4096
+    with pytest.raises(mfs.MfsError) as e:
+        mfs.Server(ctx, lane_max_tets=(4000, 1200), **OPTS)
+    assert e.value.code == -1
+    _say(f"server: 3 lanes, tets {[ch.info()['n_tets'] for ch in chars]}")
+    srv = mfs.Server(ctx, slots=2, workspace_budget_bytes=budget, lane_max_tets=(1200, 4000), **OPTS)
+    with pytest.raises(mfs.MfsError) as e:
+        srv.set_lane_tuning(3, pcg_lanes_per_row=alt)
+    assert e.value.code == -1
+    with pytest.raises(mfs.MfsError) as e:
+        srv.set_lane_tuning(2, pcg_lanes_per_row=3)
+    assert e.value.code == -1
+    srv.set_lane_tuning(2, pcg_lanes_per_row=alt)
+    order = [4, 0, 2, 1, 3, 0, 4, 2]
+    tickets = [(k, srv.submit(chars[k], *poses[k])) for k in order]
+    for k, tk in tickets:
+        x, st, times, rc = srv.wait(tk)
+        assert np.array_equal(x, alone[k]), f"character {k} differs from its solve alone"
+        assert times["submit_s"] <= times["admit_s"] <= times["done_s"]
+    info = srv.info()
+    srv.close()
+    _say(f"server info {info}")
+    assert info["submitted"] == info["completed"] == len(order)
+    assert info["queued"] == 0 and info["running"] == 0 and info["arena_in_use"] == 0
+    assert info["arena_bytes"] >= 3 * (budget // 256 * 256)
+    # the caller's context is usable again after the server is gone, with its
+    # own schedule
+    assert ctx.tuning() == base
+    x, _, _ = chars[3].solve(*poses[3], **OPTS)
+    assert np.array_equal(x, alone[3])
+    for ch in chars:
+        ch.close()
