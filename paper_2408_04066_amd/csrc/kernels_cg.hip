@@ -32,6 +32,35 @@ __device__ __forceinline__ void precondition(const T* __restrict__ mi, const V r
   zv[2] = m4 * rv[0] + m3 * rv[1] + m2 * rv[2];
 }
 
+// Row i (i = lane < 3) of the packed symmetric 3x3 block of row `row` of
+// M^-1, in the order precondition() takes it: (m0 m5 m4), (m5 m1 m3),
+// (m4 m3 m2).
+template <typename T>
+__device__ __forceinline__ void precond_row(const SysDesc& S, int row, int lane, T mb[3]) {
+  const T* m = (const T*)S.minv + 6 * row;
+  mb[0] = m[lane == 0 ? 0 : (lane == 1 ? 5 : 4)];
+  mb[1] = m[lane == 0 ? 5 : (lane == 1 ? 1 : 3)];
+  mb[2] = m[lane == 0 ? 4 : (lane == 1 ? 3 : 2)];
+}
+
+// Component i = lane of a row's 3-vector.
+template <typename V>
+__device__ __forceinline__ V component(const V v[3], int lane) {
+  return lane == 0 ? v[0] : (lane == 1 ? v[1] : v[2]);
+}
+
+// (M^-1 w)_i on lane i < 3 of a row group aligned to four lanes, lane j
+// holding w_j and row i of the block (precond_row): the three components
+// are broadcast within the quad by DPP, and the products are added in
+// precondition()'s order.  Called with all 64 lanes active (lanes that hold
+// no component pass zeros).
+template <typename T, typename V>
+__device__ __forceinline__ V precondition_component(const T mb[3], V wi) {
+  constexpr int kQuadLane0 = 0x00, kQuadLane1 = 0x55, kQuadLane2 = 0xAA;  // quad_perm [j,j,j,j]
+  const V w0 = dpp<kQuadLane0>(wi), w1 = dpp<kQuadLane1>(wi), w2 = dpp<kQuadLane2>(wi);
+  return (V)mb[0] * w0 + (V)mb[1] * w1 + (V)mb[2] * w2;
+}
+
 // ONE: a single system whose descriptor is the kernel argument `one` and
 // whose tiles are implicit (tile j = rows [64 j, 64 j + 64)); saves the two
 // dependent loads (tile, descriptor) at the head of every workgroup.
@@ -112,12 +141,43 @@ __global__ __launch_bounds__(64) void k_cg_init(const SysDesc* __restrict__ sd, 
   }
 }
 
+// This lane's terms of four partial planes over the share of wave w of W:
+// tiles l + 64 (w + W k), k = 0, 1, ... (l = lane), added in sequence, the
+// loads of four terms per plane issued before their additions.
+template <int W>
+__device__ __forceinline__ void share_sums4(const double* a, const double* b, const double* c, const double* d,
+                                            int count, double s[4]) {
+  s[0] = s[1] = s[2] = s[3] = 0.0;
+  for (int i0 = (threadIdx.x & 63) + 64 * (threadIdx.x >> 6); i0 < count; i0 += 256 * W) {
+    double v[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + 64 * W * u < count ? i0 + 64 * W * u : i0;
+      v[0][u] = a[i];
+      v[1][u] = b[i];
+      v[2][u] = c[i];
+      v[3][u] = d[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (i0 + 64 * W * u < count) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[k] += v[k][u];
+      }
+    }
+  }
+}
+
 // Search direction p_it = z + beta p_{it-1} and q = K p_it: one pass of 64
 // rows, LPR lanes per row; partial p.q.  What the launch reads and no
 // workgroup of it writes (the PCG state, the row's block range, the row's z
 // and both p buffers, the partial sums of the previous launches) is loaded
-// at its head, so those loads overlap; in all-read mode every wave folds the
-// sums itself (same order in each), with no barrier before the SpMV.
+// at its head, so those loads overlap.  In all-read mode the LPR waves of a
+// workgroup fold the sums together: wave w adds the tiles of its share in
+// sequence (share_sums4), the shares meet in LDS in wave order and each wave
+// sums the 64 lanes itself.  Every workgroup takes the same order, so all
+// of them reach the same beta and convergence decision; each reads 1/LPR of
+// the partials a wave folding alone would read.
 template <typename T, int LPR, bool ONE>
 __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
                                                       int ntiles, const SysDesc one) {
@@ -141,12 +201,10 @@ __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict_
       op1[i] = ((const T*)S.p1)[3 * row + i];
     }
   }
-  double lrr = 0.0, lbb = 0.0, lz0 = 0.0, lz1 = 0.0, lunused = 0.0;
-  if (!S.ticket) {
-    lane_sums3(S.part + P_RR * S.ptile, S.part + P_BB * S.ptile, S.part + P_RZ0 * S.ptile, S.ntv, lrr, lbb, lz0);
-    lane_sums3(S.part + P_RZ1 * S.ptile, S.part + P_RZ1 * S.ptile, S.part + P_RZ1 * S.ptile, S.ntv, lz1, lunused,
-               lunused);
-  }
+  double ls[4] = {0.0, 0.0, 0.0, 0.0};  // rr, bb, rz0, rz1: this lane's share
+  if (!S.ticket)
+    share_sums4<LPR>(S.part + P_RR * S.ptile, S.part + P_BB * S.ptile, S.part + P_RZ0 * S.ptile,
+                     S.part + P_RZ1 * S.ptile, S.ntv, ls);
   const int stopped = st->done;
   const int it_t = st->it, it_all = st->it_a;
   const double rz_t = st->rz, rzp_t = st->rz_prev;
@@ -159,9 +217,20 @@ __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict_
     beta = it == 0 ? 0.0 : rz_t / rzp_t;
   } else {
     it = it_all;
-    const double rr = wave_sum(lrr);
-    const double bb = wave_sum(lbb);
-    const double rz0 = wave_sum(lz0), rz1 = wave_sum(lz1);
+    __shared__ double share[4][LPR][64];
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) share[k][wv][ln] = ls[k];
+    __syncthreads();
+    double f[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      f[k] = share[k][0][ln];
+#pragma unroll
+      for (int j = 1; j < LPR; ++j) f[k] += share[k][j][ln];
+      f[k] = wave_sum(f[k]);
+    }
+    const double rr = f[0], bb = f[1], rz0 = f[2], rz1 = f[3];
     const bool conv = rr <= pcg_tol2(ctrl, bb) * bb;
     if (t.local == 0 && threadIdx.x == 0) {
       st->rr = rr;
@@ -519,8 +588,15 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_start(const SysDesc* __restric
 // vector entries, the partial sums of the previous launch, the PCG state) is
 // loaded at its head, before the convergence flag is tested, so the loads
 // overlap instead of forming a chain; a launch for a stopped system reads
-// them and discards them.  Every wave folds the partial sums itself (the
-// same fixed order in each), so no barrier separates the fold from the SpMV.
+// them and discards them.  In all-read mode the first wave folds the partial
+// sums (every workgroup in the same fixed order) and hands them to the other
+// waves through LDS after the SpMV: one fold per workgroup rather than one
+// per wave, which at a thousand tiles was more L2 traffic than the
+// iteration's own bytes.  The waves of a workgroup may read the convergence
+// flag on either side of its setting (it is set during the launch that
+// converges), so the folding wave never leaves before the hand-over and the
+// stop decision after it is the folding wave's, taken by every wave.  The
+// flag changes only in a launch whose fold tells every workgroup to stop.
 template <typename T, typename V, int LPR, bool ONE>
 __global__ __launch_bounds__(64 * LPR) void k_pcg_iter(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
                                                        int ntiles, const SysDesc one, int parity) {
@@ -546,9 +622,32 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_iter(const SysDesc* __restrict
   V* wv = (V*)S.v0;
   const int rb = valid ? S.rowptr[row] : 0;
   const int re = valid ? S.rowptr[row + 1] : 0;
+  // Row vectors: with LPR >= 4, lane i < 3 of the row's group keeps component
+  // i of every vector (entry 0 of the arrays) and the row i of its 3x3
+  // preconditioner block, so each vector moves in one load or store per
+  // row-group instead of three from lane 0; with LPR = 2 lane 0 keeps all
+  // three.
+  constexpr bool CL = LPR >= 4;
+  const bool comp = valid && lane < 3;
   V oz[3], oq[3], os[3], op[3], ox[3], orr[3], ou[3], ow[3], om[3];
   T mb[6];
-  if (owner) {
+  if (CL) {
+    if (comp) {
+      const int k = 3 * row + lane;
+      oz[0] = zv[k];
+      oq[0] = qv[k];
+      os[0] = sv[k];
+      op[0] = pv[k];
+      ox[0] = xv[k];
+      orr[0] = rv[k];
+      ou[0] = uv[k];
+      ow[0] = wv[k];
+      om[0] = mi[k];
+      precond_row(S, row, lane, mb);
+    } else {
+      mb[0] = mb[1] = mb[2] = (T)0;
+    }
+  } else if (owner) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const int k = 3 * row + i;
@@ -565,8 +664,9 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_iter(const SysDesc* __restrict
 #pragma unroll
     for (int i = 0; i < 6; ++i) mb[i] = ((const T*)S.minv)[6 * row + i];
   }
+  const bool folder = !S.ticket && threadIdx.x < 64;
   double lr = 0.0, lg = 0.0, ld = 0.0;
-  if (!S.ticket)
+  if (folder)
     lane_sums3(S.part + (par ? P_RR1 : P_RR) * S.ptile, S.part + (P_G0 + par) * S.ptile,
                S.part + (P_D0 + par) * S.ptile, S.ntv, lr, lg, ld);
   const int stopped = st->done;
@@ -577,19 +677,30 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_iter(const SysDesc* __restrict
   // A run of launches goes on after convergence (or a breakdown) while its
   // parity argument keeps alternating; the planes of the other parity still
   // hold the previous iteration's sums, so every later launch must stop here.
-  // (Within the launch that sets `done`, every workgroup stops anyway.)
-  if (stopped) return;
+  if (stopped && !folder) return;
   // n_i = K m_i: needs nothing from the fold below
-  V nv[3];
-  row_range_product<T, V, LPR>(S, mi, rb, re, lane, nv);
+  V nv[3] = {(V)0, (V)0, (V)0};
+  if (!stopped) row_range_product<T, V, LPR>(S, mi, rb, re, lane, nv);
   double gam, del;
   if (S.ticket) {
     gam = g_t;
     del = d_t;
   } else {
-    const double rr = wave_sum(lr);
-    gam = wave_sum(lg);
-    del = wave_sum(ld);
+    __shared__ double fold[4];
+    if (folder) {
+      const double f0 = wave_sum(lr), f1 = wave_sum(lg), f2 = wave_sum(ld);
+      if (threadIdx.x == 0) {
+        fold[0] = f0;
+        fold[1] = f1;
+        fold[2] = f2;
+        fold[3] = stopped ? 1.0 : 0.0;
+      }
+    }
+    __syncthreads();  // waves that saw the flag set may have left; the barrier waits for the others only
+    if (fold[3] != 0.0) return;
+    const double rr = fold[0];
+    gam = fold[1];
+    del = fold[2];
     if (rr <= pcg_tol2(ctrl, bb) * bb) {
       if (t.local == 0 && threadIdx.x == 0) {
         st->rr = rr;
@@ -617,7 +728,32 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_iter(const SysDesc* __restrict
   }
   const V ta = (V)alpha, tb = (V)beta;
   double g = 0.0, dl = 0.0, rr = 0.0;
-  if (owner) {
+  if (CL) {
+    V wi = (V)0;
+    if (comp) {
+      const int k = 3 * row + lane;
+      const V z = component(nv, lane) + tb * oz[0];
+      const V q = om[0] + tb * oq[0];
+      const V sk = ow[0] + tb * os[0];
+      const V pk = ou[0] + tb * op[0];
+      zv[k] = z;
+      qv[k] = q;
+      sv[k] = sk;
+      pv[k] = pk;
+      xv[k] = ox[0] + ta * pk;
+      const V r = orr[0] - ta * sk;
+      const V u = ou[0] - ta * q;
+      wi = ow[0] - ta * z;
+      rv[k] = r;
+      uv[k] = u;
+      wv[k] = wi;
+      g = (double)r * (double)u;
+      dl = (double)wi * (double)u;
+      rr = (double)r * (double)r;
+    }
+    const V mnew = precondition_component<T>(mb, wi);
+    if (comp) mn[3 * row + lane] = mnew;
+  } else if (owner) {
     V w[3], mnew[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -799,10 +935,29 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_persist(const SysDesc* __restr
   const bool valid = row < t.end;
   const bool owner = valid && lane == 0;
   V* xv = (V*)S.xc;
-  // ---- the rows' vectors and recurrences, kept in registers ----
+  // ---- the rows' vectors and recurrences, kept in registers (split by
+  // component over lanes 0-2 of the row's group as in k_pcg_iter) ----
+  constexpr bool CL = LPR >= 4;
+  const bool comp = valid && lane < 3;
   V oz[3], oq[3], os[3], op[3], ox[3], orr[3], ou[3], ow[3], om[3];
   T mb[6];
-  if (owner) {
+  if (CL) {
+    if (comp) {
+      const int k = 3 * row + lane;
+      oz[0] = ((const V*)S.v1)[k];
+      oq[0] = ((const V*)S.v2)[k];
+      os[0] = ((const V*)S.v3)[k];
+      op[0] = ((const V*)S.p0)[k];
+      ox[0] = xv[k];
+      orr[0] = ((const V*)S.r)[k];
+      ou[0] = ((const V*)S.z)[k];
+      ow[0] = ((const V*)S.v0)[k];
+      om[0] = ((const V*)S.p1)[k];  // m_0 (iteration 0 has parity 0)
+      precond_row(S, row, lane, mb);
+    } else {
+      mb[0] = mb[1] = mb[2] = (T)0;
+    }
+  } else if (owner) {
     const V* zv = (const V*)S.v1;
     const V* qv = (const V*)S.v2;
     const V* sv = (const V*)S.v3;
@@ -896,7 +1051,34 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_persist(const SysDesc* __restr
     g_prev = gam;
     const V ta = (V)alpha, tb = (V)beta;
     double g = 0.0, dl = 0.0, r2 = 0.0;
-    if (owner) {
+    if (CL) {
+      V wi = (V)0;
+      if (comp) {
+        const V z = component(nv, lane) + tb * oz[0];
+        const V q = om[0] + tb * oq[0];
+        const V sk = ow[0] + tb * os[0];
+        const V pk = ou[0] + tb * op[0];
+        oz[0] = z;
+        oq[0] = q;
+        os[0] = sk;
+        op[0] = pk;
+        ox[0] = ox[0] + ta * pk;
+        const V r = orr[0] - ta * sk;
+        const V u = ou[0] - ta * q;
+        wi = ow[0] - ta * z;
+        orr[0] = r;
+        ou[0] = u;
+        ow[0] = wi;
+        g = (double)r * (double)u;
+        dl = (double)wi * (double)u;
+        r2 = (double)r * (double)r;
+      }
+      const V mnew = precondition_component<T>(mb, wi);
+      if (comp) {
+        st_dev(mn + 3 * row + lane, mnew);
+        om[0] = mnew;
+      }
+    } else if (owner) {
       V w[3], mnew[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
@@ -939,7 +1121,9 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_persist(const SysDesc* __restr
       break;
     }
   }
-  if (owner) {
+  if (CL) {
+    if (comp) xv[3 * row + lane] = ox[0];
+  } else if (owner) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) xv[3 * row + i] = ox[i];
   }
