@@ -445,12 +445,13 @@ __global__ __launch_bounds__(64) void k_cg_update(const SysDesc* __restrict__ sd
 // batch are loaded first (unconditionally: slots past the row's end reload its
 // last block and are weighted 0, so no branch splits the loads), then all gathers are
 // issued, so a batch costs two dependent memory latencies instead of two per
-// block.
+// block.  The blocks are added in index order whatever U is; a smaller
+// batch only holds fewer registers (more waves per SIMD on large meshes).
 // The row's block range [rb, re) is passed in (re = rb for no row).
 template <typename T, typename V, int LPR>
 __device__ __forceinline__ void row_range_product(const SysDesc& S, const V* __restrict__ v, int rb, int re, int lane,
                                                   V acc[3]) {
-  constexpr int U = LPR >= 16 ? 1 : 16 / LPR;
+  constexpr int U = LPR >= 8 ? 1 : 8 / LPR;  // 8 blocks per row in flight (rows average about 15)
   acc[0] = acc[1] = acc[2] = (V)0;
   {
     const T* vals = (const T*)S.vals;
