@@ -155,6 +155,10 @@ __global__ __launch_bounds__(kBlock) void k_element(const SysDesc* __restrict__ 
 // contributions (no atomics); each contribution is one block of the tet's
 // record (transposed when a > b).  The diagonal slot of vertex r also adds
 // the pins of r, writes b_r and the inverse diagonal block (block Jacobi).
+// Contributions are taken in batches of kBatch: the batch's codes, then all
+// its blocks (and forces), are loaded before any is added, so a batch costs
+// two dependent memory latencies instead of two per contribution (a
+// diagonal slot has about twenty); they are still added in list order.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_assemble(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
@@ -166,28 +170,46 @@ __global__ __launch_bounds__(kBlock) void k_assemble(const SysDesc* __restrict__
   const T* blk = (const T*)S.blk;
   double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   double f[3] = {0, 0, 0};
-  const int c0 = S.slot_ptr[slot], c1 = S.slot_ptr[slot + 1];
+  const int c0 = S.slot_ptr[slot], c1 = S.slot_ptr[slot + 1];  // c1 > c0: every slot has a contribution
   const int code0 = S.contrib[c0];
   const int a0 = (code0 >> 2) & 3;
   const bool diag = a0 == (code0 & 3);
-  for (int ci = c0; ci < c1; ++ci) {
-    const int code = S.contrib[ci];
-    const int k = code >> 4, a = (code >> 2) & 3, b = code & 3;
-    if (a <= b) {
-      const T* bp = blk + 90 * (size_t)k + 9 * pair_index(a, b);
+  constexpr int kBatch = 4;
+  for (int cb = c0; cb < c1; cb += kBatch) {
+    int code[kBatch];
 #pragma unroll
-      for (int i = 0; i < 9; ++i) acc[i] += (double)bp[i];
-    } else {
-      const T* bp = blk + 90 * (size_t)k + 9 * pair_index(b, a);
+    for (int u = 0; u < kBatch; ++u) code[u] = S.contrib[cb + u < c1 ? cb + u : c1 - 1];  // past the end: reload the last
+    T v[kBatch][9];
+    double fr[kBatch][3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
+    for (int u = 0; u < kBatch; ++u) {
+      const int k = code[u] >> 4, a = (code[u] >> 2) & 3, b = code[u] & 3;
+      const T* bp = blk + 90 * (size_t)k + 9 * pair_index(a <= b ? a : b, a <= b ? b : a);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) acc[3 * i + j] += (double)bp[3 * j + i];
+      for (int i = 0; i < 9; ++i) v[u][i] = bp[i];
+      if (diag) {
+        const double* fp = S.frc + 12 * (size_t)k + 3 * a;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) fr[u][i] = fp[i];
+      }
     }
-    if (diag) {
-      const double* fr = S.frc + 12 * (size_t)k + 3 * a;
 #pragma unroll
-      for (int i = 0; i < 3; ++i) f[i] += fr[i];
+    for (int u = 0; u < kBatch; ++u) {
+      if (cb + u >= c1) break;
+      const int a = (code[u] >> 2) & 3, b = code[u] & 3;
+      if (a <= b) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) acc[i] += (double)v[u][i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) acc[3 * i + j] += (double)v[u][3 * j + i];
+      }
+      if (diag) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) f[i] += fr[u][i];
+      }
     }
   }
   if (diag) {
