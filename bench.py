@@ -277,9 +277,17 @@ def frame_bench(args, mfs, torch):
     _progress("roofline pass done")
 
     # ---- FP32 + refinement against the FP64 form of the same solve, both
-    # from the rest shape ----
-    lat64, tet_iters64, err = [], 0, []
+    # from the rest shape, and both against a tight FP64 solve (Newton step
+    # below 1e-12 bbox, PCG to 1e-10, up to 200 Newton iterations): the two
+    # forms stop on the same step test, which a slowly converging frame can
+    # pass far from its solution, so their difference alone does not say
+    # which of them is off ----
+    lat64, tet_iters64, err, err32, err64 = [], 0, [], [], []
     rest_opts = dict(opts, warm_start=mfs.WARM_REST)
+    tight_opts = dict(fp64_opts, warm_start=mfs.WARM_REST, step_tol=1e-12, cg_tol=1e-10, cg_adaptive=0,
+                      max_newton=200, fixed_newton=0)
+    if opts.get("fixed_newton"):  # a fixed iteration count is the workload itself: no tight reference
+        tight_opts = None
     for i in range(args.fp64_steps):
         poses = steps[nxt + i]
         s32, _ = frame(poses, rest_opts)
@@ -289,12 +297,22 @@ def frame_bench(args, mfs, torch):
         s64, _ = frame(poses, dict(fp64_opts, warm_start=mfs.WARM_REST))
         torch.cuda.synchronize()
         lat64.append(time.perf_counter() - ts)
+        x64 = [o.cpu().numpy().copy() for o in outs]
         tet_iters64 += sum(inf["n_tets"] * st["iterations"] for inf, st in zip(infos, s64))
-        # compared where both forms converged (a frame stopped by the Newton
+        if tight_opts is not None:
+            st_t, _ = frame(poses, tight_opts)
+            xt = [o.cpu().numpy().copy() for o in outs]
+        # compared where the forms converged (a frame stopped by the Newton
         # cap is an unconverged iterate in either precision)
-        for o, a, st32, st64, inf in zip(outs, x32, s32, s64, infos):
+        for j, (st32, st64, inf) in enumerate(zip(s32, s64, infos)):
+            d = lambda a, b: float(np.max(np.linalg.norm(a - b, axis=1))) / inf["bbox_diag"]
             if st32["status"] == 0 and st64["status"] == 0:
-                err.append(float(np.max(np.linalg.norm(a - o.cpu().numpy(), axis=1))) / inf["bbox_diag"])
+                err.append(d(x32[j], x64[j]))
+            if tight_opts is not None and st_t[j]["status"] == 0:
+                if st32["status"] == 0:
+                    err32.append(d(x32[j], xt[j]))
+                if st64["status"] == 0:
+                    err64.append(d(x64[j], xt[j]))
 
     spmv_ms, spmv_timed, spmv_launches, spmv_bytes = prof["spmv"]
     achieved = spmv_bytes / (spmv_ms * 1e-3) / 1e9 if spmv_ms > 0 else None
@@ -327,6 +345,9 @@ def frame_bench(args, mfs, torch):
             "frames_per_s": nchar * len(lat64) / sum(lat64) if lat64 else None,
             "tet_newton_iter_per_s": tet_iters64 / sum(lat64) if lat64 else None,
             "max_rel_diff_fp32_vs_fp64": (max(err) if err else None) if opts["precision"] else None,
+            "max_rel_err_vs_tight_fp64": {"fp32_refined": max(err32) if err32 else None,
+                                          "fp64": max(err64) if err64 else None,
+                                          "frames_compared": len(err32)},
         },
         "config": {"workload": wname, "characters": nchar, "tets": m_tot,
                    "vertices": sum(i["n_vertices"] for i in infos),
