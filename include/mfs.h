@@ -298,15 +298,19 @@ int mfs_solve_batch(mfs_context* ctx, int32_t count, mfs_character* const* chars
  * like this one and apply it to the context.  Each candidate solves the
  * given frames (as mfs_solve_batch with `opts`, but from the rest shape and
  * for exactly `newton_iterations` iterations, into scratch device memory)
- * twice, timing the second.  The winner is the fastest candidate whose
- * solves are as good as the default schedule's: no PCG solve left
+ * twice, timing the second.  A candidate's time is scaled by the default
+ * schedule's total PCG iteration count over its own (summation order alone
+ * moves the counts by a few percent), and the winner is the fastest
+ * candidate by that time whose solves are as good as the default
+ * schedule's: no PCG solve left
  * unconverged (or stopped by a breakdown) where the default had none, and
  * every final gradient norm within 10x the default's.  Choices are kept per
  * (GPU architecture, size class = bit length of the total vertex count):
  * in the context, and in the text file `cache_path` when it is not NULL
  * (read first, rewritten after tuning).  A cached choice is applied without
  * timing unless flags has MFS_AUTOTUNE_FORCE.  The characters end up holding
- * the solution of the last timed run.  best and best_ms may be NULL. */
+ * the solution of the last timed run.  best_ms is the winner's scaled
+ * time; best and best_ms may be NULL. */
 int mfs_autotune(mfs_context* ctx, int32_t count, mfs_character* const* chars,
                  const double* const* handle_R, const double* const* handle_t,
                  const mfs_solve_opts* opts, int32_t newton_iterations, const char* cache_path,

@@ -9,7 +9,11 @@
 // are timed on the caller's own systems: each runs the same fixed number of
 // Newton iterations from the rest shape (the same launches for every
 // candidate, up to summation order), timed on the host clock around the
-// synchronous solve.  The fastest is applied to the context and cached per
+// synchronous solve.  Summation order alone moves the PCG iteration counts of
+// a candidate's runs by a few percent either way, so a candidate's time is
+// scaled by the reference schedule's total PCG iteration count over its own
+// before it is compared: the ranking is by time per unit of the same PCG work,
+// which carries over to other frames.  The fastest is applied to the context and cached per
 // (GPU architecture, size class), where the size class is the bit length of
 // the total block-row count of the batch; a cache file keeps the choices
 // across processes.
@@ -148,6 +152,16 @@ extern "C" int mfs_autotune(mfs_context* ctx, int32_t count, mfs_character* cons
     }
     return MFS_OK;
   };
+  auto cg_total = [&](const std::vector<mfs_solve_stats>& st) {
+    double n = 0.0;
+    for (int i = 0; i < count; ++i) n += st[i].cg_iterations;
+    return n;
+  };
+  // time scaled to the reference schedule's PCG work (ref must be filled)
+  auto scaled = [&](double ms) {
+    const double r = cg_total(ref), g = cg_total(got);
+    return (r > 0.0 && g > 0.0) ? ms * r / g : ms;
+  };
   auto qualifies = [&]() {
     for (int i = 0; i < count; ++i) {
       if (got[i].cg_not_converged > ref[i].cg_not_converged) return false;
@@ -188,6 +202,7 @@ extern "C" int mfs_autotune(mfs_context* ctx, int32_t count, mfs_character* cons
         (void)mfs_context_set_tuning(ctx, &base);
         return rc;
       }
+      ms = scaled(ms);
       if (ms < win_ms && qualifies()) {
         win_ms = ms;
         win = t;
@@ -208,6 +223,7 @@ extern "C" int mfs_autotune(mfs_context* ctx, int32_t count, mfs_character* cons
         (void)mfs_context_set_tuning(ctx, &base);
         return rc;
       }
+      ms = scaled(ms);
       if (ms < win_ms && qualifies()) {
         win_ms = ms;
         win = t;
@@ -229,6 +245,7 @@ extern "C" int mfs_autotune(mfs_context* ctx, int32_t count, mfs_character* cons
         (void)mfs_context_set_tuning(ctx, &base);
         return rc;
       }
+      ms = scaled(ms);
       if (ms < win_ms && qualifies()) {
         win_ms = ms;
         win = t;
