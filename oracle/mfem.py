@@ -295,19 +295,38 @@ def polar_stretch(F):
 # Rig: rotation clusters (Section 3.1) and offset pin targets (Section 3.2).
 # ----------------------------------------------------------------------------
 
-def cluster_by_segments(X, T, seg_a, seg_b, seg_handle):
-    """Handle of the bone segment nearest each tet's barycenter (reading R8)."""
-    X = np.asarray(X, dtype=np.float64)
-    T = np.asarray(T, dtype=np.int64)
-    bary = X[T].mean(axis=1)
-    d2 = np.empty((T.shape[0], len(seg_a)))
+def _barycenters(X, T):
+    """((x0 + x1) + x2) + x3, times 1/4, per tet."""
+    return (((X[T[:, 0]] + X[T[:, 1]]) + X[T[:, 2]]) + X[T[:, 3]]) * 0.25
+
+
+def _segment_dist2(P, seg_a, seg_b):
+    """Squared distances (len(P), nseg) from points to segments, every sum
+    written out in one order with each product rounded on its own (no fused
+    multiply-adds, no library dot products): a point as far from two segments
+    as from their shared joint then ties exactly, and the tie goes to the lower
+    segment index however the arithmetic is carried out elsewhere."""
+    d2 = np.empty((P.shape[0], len(seg_a)))
     for s in range(len(seg_a)):
         a = np.asarray(seg_a[s], dtype=np.float64)
         d = np.asarray(seg_b[s], dtype=np.float64) - a
-        dd = float(d @ d)
-        u = np.zeros(len(bary)) if dd == 0.0 else np.clip((bary - a) @ d / dd, 0.0, 1.0)
-        q = a + u[:, None] * d
-        d2[:, s] = ((bary - q) ** 2).sum(axis=1)
+        dd = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
+        if dd == 0.0:
+            u = np.zeros(P.shape[0])
+        else:
+            r = P - a
+            u = np.clip(((r[:, 0] * d[0] + r[:, 1] * d[1]) + r[:, 2] * d[2]) / dd, 0.0, 1.0)
+        e = P - (a + u[:, None] * d)
+        d2[:, s] = (e[:, 0] * e[:, 0] + e[:, 1] * e[:, 1]) + e[:, 2] * e[:, 2]
+    return d2
+
+
+def cluster_by_segments(X, T, seg_a, seg_b, seg_handle):
+    """Handle of the bone segment nearest each tet's barycenter (reading R8;
+    ties to the lowest segment index)."""
+    X = np.asarray(X, dtype=np.float64)
+    T = np.asarray(T, dtype=np.int64)
+    d2 = _segment_dist2(_barycenters(X, T), seg_a, seg_b)
     return np.asarray(seg_handle, dtype=np.int32)[np.argmin(d2, axis=1)]
 
 
@@ -330,16 +349,8 @@ def blend_weights(X, T, seg_a, seg_b, seg_handle, width, kmax):
     X = np.asarray(X, dtype=np.float64)
     T = np.asarray(T, dtype=np.int64)
     seg_handle = np.asarray(seg_handle, dtype=np.int64)
-    bary = X[T].mean(axis=1)
     m = T.shape[0]
-    d2 = np.empty((m, len(seg_a)))
-    for s in range(len(seg_a)):
-        a = np.asarray(seg_a[s], dtype=np.float64)
-        d = np.asarray(seg_b[s], dtype=np.float64) - a
-        dd = float(d @ d)
-        u = np.zeros(m) if dd == 0.0 else np.clip((bary - a) @ d / dd, 0.0, 1.0)
-        q = a + u[:, None] * d
-        d2[:, s] = ((bary - q) ** 2).sum(axis=1)
+    d2 = _segment_dist2(_barycenters(X, T), seg_a, seg_b)
     handles = np.full((m, kmax), -1, dtype=np.int32)
     weights = np.zeros((m, kmax))
     hs = sorted(set(seg_handle.tolist()))

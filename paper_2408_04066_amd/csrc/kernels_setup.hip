@@ -49,8 +49,15 @@ __global__ __launch_bounds__(kBlock) void k_rest(const int4* __restrict__ tets, 
 
 // Tet barycenter ((X0 + X1) + X2) + X3) / 4 and squared distance to bone
 // segment sg (a zero-length segment is a point).
+// The barycenter and the segment distance are evaluated in one written-out
+// order with every product rounded on its own (contraction off): a tet as far
+// from two segments as from their shared joint must tie exactly, so that the
+// nearest-segment rule (ties to the lower segment) gives the same cluster as
+// any other evaluation in this order.  With fused multiply-adds the two
+// distances of such a tet can differ in the last bit either way.
 __device__ __forceinline__ void tet_barycenter(const double* __restrict__ X, const int32_t* __restrict__ tets,
                                                int64_t k, double c[3]) {
+#pragma clang fp contract(off)
 #pragma unroll
   for (int i = 0; i < 3; ++i)
     c[i] = (((X[3 * (int64_t)tets[4 * k] + i] + X[3 * (int64_t)tets[4 * k + 1] + i]) +
@@ -60,6 +67,7 @@ __device__ __forceinline__ void tet_barycenter(const double* __restrict__ X, con
 
 __device__ __forceinline__ double segment_dist2(const double c[3], const double* __restrict__ sa,
                                                 const double* __restrict__ sb, int sg) {
+#pragma clang fp contract(off)
   double a[3], d[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {

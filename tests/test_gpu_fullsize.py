@@ -1,0 +1,151 @@
+"""Parity at the benchmark's full sizes, in the launch configuration the bench
+times (its workload definitions and solve options, the autotuned PCG
+schedule), where the oracle cannot solve the frame itself in seconds.
+
+What the oracle checks there is what holds at any size: its energy and
+gradient evaluated at the GPU's solution equal the library's own evaluation
+of the same state (the full-size element pass); the solution is stationary
+(the oracle's largest residual force there is orders below the largest pin
+force at the rest shape, the load the elastic forces balance); and the
+FP32 + refinement solution lies within 1e-7 of the bbox diagonal of a tight
+FP64 solve continued from it, itself stationary by the oracle's gradient.  The batched workload is checked on a sample of its
+members after one batched solve of all of them.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# a tight FP64 solve continued from the character's last solution (a pose
+# far from the rest shape need not converge from there at all)
+TIGHT = dict(precision=0, cg_tol=1e-10, step_tol=1e-12, cg_adaptive=0, max_newton=200, warm_start=1)
+# largest per-vertex residual force at the solution over the applied force scale
+# (measured: at most 8e-15 for the tight solves and 1.1e-11 with the bench's
+# options, over the five solutions checked here)
+R_TIGHT = 1e-12  # tight FP64 solve
+R_BENCH = 1e-9  # the bench's options (Newton step below 1e-8 of the bbox)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mfs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2408_04066_amd as m
+    return m
+
+
+def _err(x, ref, bbox):
+    return float(np.max(np.linalg.norm(x - ref, axis=1))) / bbox
+
+
+def _force_scale(fr, prob):
+    """Largest pin force at the rest shape under the pose, k_s |P X - y|: the
+    applied load that the elastic forces balance at the solution."""
+    X = np.asarray(prob["X"], dtype=np.float64).reshape(-1)
+    return fr.ks * float(np.max(np.linalg.norm(fr.pin_residual(X), axis=1)))
+
+
+def _check_state(fr, scale, ch, pose, x, label):
+    """Oracle energy and gradient at x against the library's evaluation of the
+    same state; returns (E(x), max |grad E(x)| / scale) by the oracle."""
+    xf = x.reshape(-1)
+    E = fr.energy(xf)
+    g = fr.gradient(xf).reshape(-1, 3)
+    out = ch.evaluate(*pose, x, want_stretch=False)
+    rel_e = abs(out["energy"] - E) / abs(E)
+    rel_g = float(np.max(np.abs(out["grad"] - g))) / scale
+    ratio = float(np.max(np.linalg.norm(g, axis=1))) / scale
+    _say(f"  {label}: energy {E:.9e} (library rel diff {rel_e:.2e}), gradient diff / scale {rel_g:.2e}, "
+         f"max |grad E(x)| / scale {ratio:.2e}")
+    assert rel_e <= 1e-10
+    assert rel_g <= 1e-11
+    return E, ratio
+
+
+def test_large_character_at_full_size(mfs):
+    """The 505k-tet character of the warm-started animation as the bench runs
+    it (autotuned schedule, frames warm-started from the previous one): the
+    third frame, the first the bench times."""
+    from bench import make_workload
+    probs, pose_of, wname, opts = make_workload("c3")
+    prob = probs[0]
+    _say(f"{wname}: m={len(prob['T'])} n={len(prob['X'])}")
+    ctx = mfs.Context(0)
+    ch = mfs.Character(ctx, prob)
+    t, _ = mfs.autotune(ctx, [ch], [pose_of(0)[0]], newton_iterations=2, **opts)
+    _say(f"  schedule {t}")
+    for f in range(3):
+        pose = pose_of(f)[0]
+        x32, st32, rc32 = ch.solve(*pose, **opts)
+        _say(f"  frame {f}, FP32 + refinement: {st32}")
+    xt, stt, rct = ch.solve(*pose, **TIGHT)
+    _say(f"  tight FP64: {stt}")
+    assert rc32 == 0 and rct == 0
+    e = _err(x32, xt, prob["bbox_diag"])
+    _say(f"  |x32 - x_tight| / bbox = {e:.3e}")
+    assert e <= 1e-7
+    fr = oracle.Frame(prob, pose)
+    scale = _force_scale(fr, prob)
+    E_t, r_t = _check_state(fr, scale, ch, pose, xt, "tight FP64")
+    E_32, r_32 = _check_state(fr, scale, ch, pose, x32, "FP32 + refinement")
+    assert r_t <= R_TIGHT and r_32 <= R_BENCH
+    assert abs(E_32 - E_t) <= 1e-9 * abs(E_t)
+    ch.close()
+    ctx.close()
+
+
+def test_batched_characters_at_full_size(mfs):
+    """The 64-character batch in one batched run with the bench's options;
+    four members (smallest, largest and two between) checked by the oracle."""
+    from bench import make_workload
+    probs, pose_of, wname, opts = make_workload("c4")
+    poses = pose_of(0)
+    _say(f"{wname}: {len(probs)} characters, {sum(len(p['T']) for p in probs)} tets")
+    ctx = mfs.Context(0)
+    chars = [mfs.Character(ctx, p) for p in probs]
+    t, _ = mfs.autotune(ctx, chars, poses, newton_iterations=2, **opts)
+    _say(f"  schedule {t}")
+    xs, sts, rc = mfs.solve_batch(ctx, chars, poses, **opts)
+    sizes = np.array([len(p["T"]) for p in probs])
+    order = np.argsort(sizes)
+    conv = [k for k in order if sts[k]["status"] == 0]
+    assert len(conv) >= 0.8 * len(probs)
+    # four members spread over the sizes; a member whose tight solve does not
+    # converge either (a pose that leaves elements inverted) gives way to the
+    # next converged member in size order
+    checked = 0
+    for start in (0, len(conv) // 3, 2 * len(conv) // 3, len(conv) - 1):
+        for k in (conv[start:] if start < len(conv) - 1 else conv[::-1]):
+            prob, pose = probs[k], poses[k]
+            _say(f"  member {k}: m={sizes[k]} stats {sts[k]}")
+            xt, stt, rct = chars[k].solve(*pose, **TIGHT)
+            if rct != 0:
+                _say(f"  member {k}: tight FP64 did not converge ({stt}); next member")
+                continue
+            e = _err(xs[k], xt, prob["bbox_diag"])
+            _say(f"  member {k}: |x_batch - x_tight| / bbox = {e:.3e}")
+            assert e <= 1e-7
+            fr = oracle.Frame(prob, pose)
+            scale = _force_scale(fr, prob)
+            E_t, r_t = _check_state(fr, scale, chars[k], pose, xt, f"member {k} tight FP64")
+            E_b, r_b = _check_state(fr, scale, chars[k], pose, xs[k], f"member {k} batched FP32 + refinement")
+            assert r_t <= R_TIGHT and r_b <= R_BENCH
+            assert abs(E_b - E_t) <= 1e-9 * abs(E_t)
+            checked += 1
+            break
+    assert checked == 4
+    for c in chars:
+        c.close()
+    ctx.close()

@@ -49,13 +49,26 @@ def _small_humanoid(seed=21, tets=4000, bones=15):
 # helpers / standalone kernels
 # --------------------------------------------------------------------------
 def test_cluster_kernel_bit_exact(ctx):
-    for prob in (beam(), _small_humanoid()):
+    from oracle.mfem import _barycenters, _segment_dist2
+    from workloads.humanoid import _pool_member
+    # a member of the batched workload's pool with tets exactly as far from
+    # two segments of different handles (at shared joints): regression test
+    # of ties decided differently when the distances were fused-multiply-added
+    tied = _pool_member((27, 4001, (5000, 200000), (8, 30), (NH, COROT)))
+    d2 = _segment_dist2(_barycenters(np.asarray(tied["X"], dtype=np.float64), np.asarray(tied["T"])),
+                        tied["seg_a"], tied["seg_b"])
+    best = d2.min(axis=1, keepdims=True)
+    sh = np.asarray(tied["seg_handle"])
+    ties = [k for k in np.nonzero(np.sum(d2 == best, axis=1) > 1)[0]
+            if len(set(sh[d2[k] == best[k, 0]].tolist())) > 1]
+    assert len(ties) >= 1
+    for prob in (beam(), _small_humanoid(), tied):
         _say(f"cluster kernel: {prob['name']}")
         ref = oracle.cluster_by_segments(prob["X"], prob["T"], prob["seg_a"], prob["seg_b"],
                                          prob["seg_handle"])
         got = ctx.cluster_by_segments(prob["X"], prob["T"], prob["seg_a"], prob["seg_b"],
                                       prob["seg_handle"])
-        assert np.array_equal(ref, got)
+        assert np.array_equal(ref, got), f"{int(np.sum(ref != got))} tets differ (exact ties: {len(ties)})"
 
 
 def test_polar_kernel_matches_oracle(ctx):
