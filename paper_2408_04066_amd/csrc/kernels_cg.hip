@@ -193,7 +193,17 @@ __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict_
   const int rb = valid ? S.rowptr[row] : 0;
   const int re = valid ? S.rowptr[row + 1] : 0;
   T oz[3] = {0, 0, 0}, op0[3] = {0, 0, 0}, op1[3] = {0, 0, 0};
-  if (valid && lane == 0) {
+  // with LPR >= 4, lane i < 3 of the row's group keeps component i of z and
+  // both p buffers (entry 0) and writes component i of p and q
+  constexpr bool CL = LPR >= 4;
+  const bool comp = valid && lane < 3;
+  if (CL) {
+    if (comp) {
+      oz[0] = z[3 * row + lane];
+      op0[0] = ((const T*)S.p0)[3 * row + lane];
+      op1[0] = ((const T*)S.p1)[3 * row + lane];
+    }
+  } else if (valid && lane == 0) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       oz[i] = z[3 * row + i];
@@ -295,7 +305,16 @@ __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict_
   a1 = group_sum<LPR>(a1);
   a2 = group_sum<LPR>(a2);
   double dot = 0.0;
-  if (valid && lane == 0) {
+  if (CL) {
+    if (comp) {
+      T p = oz[0];
+      if (it) p += tb * ((it & 1) ? op0[0] : op1[0]);
+      const T qv = lane == 0 ? a0 : (lane == 1 ? a1 : a2);
+      pn[3 * row + lane] = p;
+      q[3 * row + lane] = qv;
+      dot = (double)p * (double)qv;
+    }
+  } else if (valid && lane == 0) {
     const T* pold = (it & 1) ? op0 : op1;
     T p0 = oz[0], p1 = oz[1], p2 = oz[2];
     if (it) {
