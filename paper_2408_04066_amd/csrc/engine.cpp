@@ -450,7 +450,6 @@ int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* fai
   const SysDesc* dsd = ctx->desc.as<SysDesc>();
   const int n = (int)slot_.size();
   const CgState* hg = ctx->h_cg.as<CgState>();
-  const Ctrl* hc = ctx->h_ctrl.data();
   int cit = 0;
   // launch set: the slots whose PCG still iterates.  It shrinks when stopped
   // systems hold a quarter of its tiles (or a system reaches its cap), so
