@@ -800,7 +800,9 @@ int Engine::step() {
   MFS_TRY(run_cg(act, fp32_, fp32_ ? &redo : nullptr));
   if (!redo.empty()) {
     // FP32 could not solve these Newton systems (ill-conditioned beyond
-    // single precision): element records, assembly and PCG again in FP64
+    // single precision): element records, assembly and PCG again in FP64,
+    // the PCG started from the FP32 iterate (left in dx by run_cg) rather
+    // than from zero
     MFS_TRY(tiles_for(redo));
     cg_epoch_ = ++ctx->cg_epoch;
     for (int i : redo) hc[i].cg_epoch = cg_epoch_;
@@ -815,7 +817,7 @@ int Engine::step() {
     }
     {
       ProfScope ps(ctx, MFS_K_OTHER);
-      launch_cg_init(st, dsd, ts_.dv, ts_.nv, 0);
+      launch_cg_init(st, dsd, ts_.dv, ts_.nv, 0, /*warm=*/1);
     }
     MFS_HIP(hipGetLastError());
     MFS_TRY(run_cg(redo, false, nullptr));

@@ -74,10 +74,13 @@ __device__ __forceinline__ Tile vertex_tile(const Tile* __restrict__ tiles, int 
 // r = b, x = 0, z = M^-1 r; partials r.z, r.r, b.b.  Ticket mode: the last
 // workgroup of a system sets its PCG state (and `done` when b is already
 // within tolerance).  All-read mode: tile 0 resets the state; the first SpMV
-// folds the partials and tests convergence.
+// folds the partials and tests convergence.  warm != 0: x starts from the
+// system's dx (the iterate an FP32 solve of the same Newton system left
+// there, non-finite entries read as 0) and r = b - K x, a sequential sum of
+// the row's blocks in block order; the tolerance stays relative to |b|.
 template <typename T, typename V = T>
 __global__ __launch_bounds__(64) void k_cg_init(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
-                                                int ntiles) {
+                                                int ntiles, int warm) {
   __shared__ int last;
   const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
   const SysDesc& S = sd[t.sys];
@@ -88,13 +91,32 @@ __global__ __launch_bounds__(64) void k_cg_init(const SysDesc* __restrict__ sd, 
     V* z = (V*)S.z;
     V* xc = (V*)S.xc;
     V rv[3], zv[3];
+    double kx[3] = {0.0, 0.0, 0.0}, x0[3] = {0.0, 0.0, 0.0};
+    if (warm) {
+      auto start = [&](int k) {
+        const double v = S.dx[k];
+        return isfinite(v) ? v : 0.0;
+      };
+      const T* vals = (const T*)S.vals;
+      const size_t nz = S.nnzb;
+      for (int blk = S.rowptr[row]; blk < S.rowptr[row + 1]; ++blk) {
+        const int c = S.colidx[blk];
+        const double g[3] = {start(3 * c), start(3 * c + 1), start(3 * c + 2)};
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          kx[i] += (double)vals[(3 * i) * nz + blk] * g[0] + (double)vals[(3 * i + 1) * nz + blk] * g[1] +
+                   (double)vals[(3 * i + 2) * nz + blk] * g[2];
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) x0[i] = start(3 * row + i);
+    }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const double bv = S.b[3 * row + i];
       bb += bv * bv;
-      rv[i] = (V)bv;
+      rv[i] = (V)(bv - kx[i]);
       r[3 * row + i] = rv[i];
-      xc[3 * row + i] = (V)0;
+      xc[3 * row + i] = (V)x0[i];
     }
     precondition((const T*)S.minv + 6 * row, rv, zv);
 #pragma unroll
@@ -1201,12 +1223,12 @@ static void cg_spmv_t(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv
   }
 }
 
-void launch_cg_init(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32) {
+void launch_cg_init(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, int warm) {
   if (!ntv) return;
   if (fp32)
-    MFS_LAUNCH(k_cg_init<float>, dim3(ntv), dim3(64), 0, st, sd, tv, ntv);
+    MFS_LAUNCH(k_cg_init<float>, dim3(ntv), dim3(64), 0, st, sd, tv, ntv, warm);
   else
-    MFS_LAUNCH(k_cg_init<double>, dim3(ntv), dim3(64), 0, st, sd, tv, ntv);
+    MFS_LAUNCH(k_cg_init<double>, dim3(ntv), dim3(64), 0, st, sd, tv, ntv, warm);
 }
 
 void launch_cg_spmv(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, int lpr,
@@ -1271,9 +1293,9 @@ static void pcg_iter_t(hipStream_t st, const SysDesc* sd, const Tile* tv, int nt
 void launch_pcg_init(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32) {
   if (!ntv) return;
   if (fp32)
-    MFS_LAUNCH((k_cg_init<float, double>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv);
+    MFS_LAUNCH((k_cg_init<float, double>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv, 0);
   else
-    MFS_LAUNCH((k_cg_init<double, double>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv);
+    MFS_LAUNCH((k_cg_init<double, double>), dim3(ntv), dim3(64), 0, st, sd, tv, ntv, 0);
 }
 
 void launch_pcg_start(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, int lpr,

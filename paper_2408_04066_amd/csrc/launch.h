@@ -65,7 +65,8 @@ void launch_stress(hipStream_t st, const SysDesc* sd, int m, const int32_t* tper
 void launch_finalize(hipStream_t st, const SysDesc* sd, const int32_t* sys_ids, int nsys);
 
 // PCG
-void launch_cg_init(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32);
+// warm != 0: start from each system's dx (see k_cg_init) instead of 0
+void launch_cg_init(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, int warm = 0);
 // `one`: non-null when the launch covers a single system, whose descriptor
 // is then passed by value and whose tiles are implicit.
 void launch_cg_spmv(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32, int lpr,
