@@ -67,3 +67,31 @@ def test_batch_pool_members():
         assert 0.8 * 5000 <= len(q["T"]) <= 1.2 * 200000
         assert 8 <= q["n_handles"] <= 30
         assert set(np.asarray(q["model"]).tolist()) <= {NH, COROT}
+
+
+def test_large_animation_workload():
+    """About 500k tets and 30 handles, frames warm-started from the previous
+    one, with the same FP32 + refinement options; consecutive frames of the
+    animation are close (smooth joint angles at 30 frames per second)."""
+    from bench import make_workload
+    probs, pose_of, name, opts = make_workload("c3")
+    p = probs[0]
+    assert 0.9 * 500000 <= len(p["T"]) <= 1.1 * 500000
+    assert p["n_handles"] == 30
+    assert opts["warm_start"] == 1 and opts["precision"] == 1
+    # each joint's rotation relative to its parent moves by at most three
+    # Euler angles of a 60-degree sinusoid with a period of at least 2 s over
+    # one frame at 30 frames per second: 3 * 60 * 2 pi / (2 * 30) degrees
+    parent = np.asarray(p["handle_parent"])
+
+    def local(R):
+        return [R[h] if parent[h] < 0 else R[parent[h]].T @ R[h] for h in range(len(R))]
+
+    def angle(a, b):
+        return np.degrees(np.arccos(np.clip((np.trace(a.T @ b) - 1.0) / 2.0, -1.0, 1.0)))
+
+    bound = 3 * 60.0 * 2 * np.pi / (2.0 * 30.0)
+    for f in range(3):
+        L0, L1 = local(pose_of(f)[0][0]), local(pose_of(f + 1)[0][0])
+        steps = [angle(a, b) for a, b in zip(L0, L1)]
+        assert 0.0 < max(steps) <= bound
