@@ -113,8 +113,9 @@ typedef struct mfs_solve_opts {
                                at most this many times and doubling it after each
                                intermediate pose converges (to a 1e-4 * bbox step) */
   int32_t fp32_cg_max;      /* FP32_REFINED: a Newton step whose FP32 PCG has not converged
-                               after this many iterations is solved again in FP64 (element
-                               records, assembly and PCG); 0 = 100 n^(1/3), at least 2000 */
+                               after this many iterations (or broke down) is solved again in
+                               FP64 (element records, assembly, and a PCG started from the
+                               FP32 iterate); 0 = 100 n^(1/3), at least 2000 */
 } mfs_solve_opts;
 
 typedef struct mfs_solve_stats {
