@@ -72,3 +72,32 @@ def test_struct_layouts_match_header(tmp_path):
         assert got == int(value), f"{pyname}.{field}: ctypes {got}, C {value}"
         seen += 1
     assert seen == sum(len(getattr(mfs, p)._fields_) + 1 for p in STRUCTS.values())
+
+
+def test_missing_library_and_missing_gpu_fail_loudly():
+    """No CPU fallback: without the built library a call into it raises
+    MfsUnavailable, and with it but without a GPU a context cannot be
+    created (an exception, never a context).  Each case runs in a fresh
+    interpreter."""
+    import subprocess
+    import sys
+    code_missing = (
+        "import paper_2408_04066_amd as m\n"
+        "m.LIB_PATH = '/nonexistent/libmfs.so'\n"
+        "try:\n"
+        "    m.default_opts()\n"
+        "except m.MfsUnavailable:\n"
+        "    print('unavailable')\n")
+    r = subprocess.run([sys.executable, "-c", code_missing], cwd=ROOT, capture_output=True, text=True, timeout=120)
+    assert r.stdout.strip() == "unavailable", r.stderr
+    code_nogpu = (
+        "import os\n"
+        "os.environ['HIP_VISIBLE_DEVICES'] = ''\n"
+        "import paper_2408_04066_amd as m\n"
+        "try:\n"
+        "    m.Context(0)\n"
+        "    print('created')\n"
+        "except Exception as e:\n"
+        "    print('error', type(e).__name__)\n")
+    r = subprocess.run([sys.executable, "-c", code_nogpu], cwd=ROOT, capture_output=True, text=True, timeout=120)
+    assert r.stdout.startswith("error"), (r.stdout, r.stderr)
