@@ -165,15 +165,16 @@ typedef struct mfs_tuning {
                                  queued one ahead of the running one; the kernels raise a
                                  host-mapped flag when a system stops, so the host never
                                  synchronises to check convergence */
-  int32_t pcg_pipelined;      /* 1: FP32_REFINED solves run the pipelined PCG of Ghysels and
-                                 Vanroose (one kernel per iteration, dot products overlapped
-                                 with the SpMV; FP32 matrix values, FP64 vectors and
-                                 recurrences); FP64 solves always run the two-kernel form */
+  int32_t pcg_pipelined;      /* 1: solves run the pipelined PCG of Ghysels and Vanroose (one
+                                 kernel per iteration, dot products overlapped with the SpMV;
+                                 FP64 vectors and recurrences, the matrix in the solve's
+                                 precision).  The FP64 re-solves inside an FP32_REFINED solve
+                                 always run the two-kernel form */
   int32_t allread_max_tiles;  /* PCG dot products of a system with at most this many 64-row
                                  tiles are folded by every workgroup of the next kernel
                                  (no fences); larger systems fold them in the last workgroup
                                  to finish (arrival ticket with a release fence) */
-  int32_t pcg_persistent;     /* 1: a pipelined PCG whose workgroups (one per 64-row tile of
+  int32_t pcg_persistent;     /* 1 (FP32_REFINED solves): a pipelined PCG whose workgroups (one per 64-row tile of
                                  every system in the batch, the tile's matrix rows held in
                                  LDS) all fit on the device at once runs as one cooperative
                                  launch with a barrier per iteration instead of one launch

@@ -1,7 +1,8 @@
 // Autotuner of the PCG launch schedule.
 //
-// The schedule knobs are the PCG form (two kernels per iteration, or the
-// pipelined one-kernel form for FP32 solves), the SpMV lanes per block row
+// The schedule knobs are the PCG form (two kernels per iteration, the
+// pipelined one-kernel form, or its persistent launch for FP32 solves), the
+// SpMV lanes per block row
 // (2, 4 or 8 lanes of a 64-row tile), the number of PCG iterations per
 // captured graph, the lengths of the first and shortest runs between host
 // convergence checks, and for large systems the reduction mode (all-read
@@ -184,9 +185,9 @@ extern "C" int mfs_autotune(mfs_context* ctx, int32_t count, mfs_character* cons
     }
     win_ms = ms;
   }
-  // stage 1: PCG form x lanes per row x graph length (the pipelined form
-  // only where it applies, FP32 solves; its persistent launch has no graphs)
-  const int forms = o.precision == MFS_FP32_REFINED ? 3 : 1;
+  // stage 1: PCG form x lanes per row x graph length (the persistent launch
+  // of the pipelined form, FP32 solves only, has no graphs)
+  const int forms = o.precision == MFS_FP32_REFINED ? 3 : 2;
   for (int form = 0; form < forms; ++form)
   for (int lpr : {2, 4, 8})
     for (int gi : {4, 8, 16}) {

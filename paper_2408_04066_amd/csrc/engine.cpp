@@ -458,7 +458,10 @@ int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* fai
   // arithmetic does not depend on the set.
   std::vector<int> live = act;
   const SysDesc* one = live.size() == 1 ? &hd_[live[0]] : nullptr;
-  const bool pipe = ctx->pipelined && fp32;
+  // the pipelined form runs FP32 solves and FP64 solves; the FP64 re-solves
+  // inside an FP32 solve keep the two-kernel form (started from the FP32
+  // iterate), and the persistent kernel exists in the FP32 form only
+  const bool pipe = ctx->pipelined && (fp32 || !fp32_);
   // per-slot iteration caps: the FP32 pass stops early where FP32 stalls
   std::vector<int> cap(slot_.size(), o_.cg_max);
   int max_cap = 0;
@@ -496,7 +499,7 @@ int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* fai
   // Persistent form: when the device holds every workgroup of the set at
   // once, the whole solve is one cooperative launch that stops each system
   // at its convergence, breakdown or cap (Ctrl::cg_cap) by itself.
-  if (pipe && ctx->persistent) {
+  if (pipe && fp32 && ctx->persistent) {
     int maxb = 0;
     for (int i : act) maxb = std::max(maxb, slot_[i].ch->max_tile_blocks);
     const size_t lds = pcg_persist_lds(maxb);

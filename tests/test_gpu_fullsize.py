@@ -46,6 +46,18 @@ def mfs():
     return m
 
 
+def _tight(ctx, ch, pose):
+    """The tight FP64 solve, continued from ch's last solution, in the
+    two-kernel PCG form (the pipelined recurrences can drift from the true
+    residual near a 1e-10 tolerance); the context's schedule is restored."""
+    saved = ctx.tuning()
+    ctx.set_tuning(pcg_pipelined=0, pcg_persistent=0)
+    try:
+        return ch.solve(*pose, **TIGHT)
+    finally:
+        ctx.set_tuning(**saved)
+
+
 def _err(x, ref, bbox):
     return float(np.max(np.linalg.norm(x - ref, axis=1))) / bbox
 
@@ -90,7 +102,7 @@ def test_large_character_at_full_size(mfs):
         pose = pose_of(f)[0]
         x32, st32, rc32 = ch.solve(*pose, **opts)
         _say(f"  frame {f}, FP32 + refinement: {st32}")
-    xt, stt, rct = ch.solve(*pose, **TIGHT)
+    xt, stt, rct = _tight(ctx, ch, pose)
     _say(f"  tight FP64: {stt}")
     assert rc32 == 0 and rct == 0
     e = _err(x32, xt, prob["bbox_diag"])
@@ -140,7 +152,7 @@ def test_batched_characters_at_full_size(mfs):
         for k in group:
             prob, pose = probs[k], poses[k]
             _say(f"  member {k}: m={sizes[k]} stats {sts[k]}")
-            xt, stt, rct = chars[k].solve(*pose, **TIGHT)
+            xt, stt, rct = _tight(ctx, chars[k], pose)
             if rct != 0:
                 _say(f"  member {k}: tight FP64 did not converge ({stt}); next member")
                 continue

@@ -161,6 +161,17 @@ def test_beam_fp64_ten_iterations(ctx):
     # the same solve twice is bitwise identical (fixed-order reductions)
     x2, _, _ = ch.solve(*pose, max_newton=10, fixed_newton=1, cg_tol=1e-10)
     assert np.array_equal(x, x2)
+    # the pipelined PCG form in FP64 (an autotuner candidate for FP64 solves)
+    base = ctx.tuning()
+    try:
+        for lpr in (2, 4, 8):
+            ctx.set_tuning(pcg_pipelined=1, pcg_persistent=0, pcg_lanes_per_row=lpr)
+            xp, stp, rcp = ch.solve(*pose, max_newton=10, fixed_newton=1, cg_tol=1e-10)
+            _say(f"  pipelined FP64, lanes {lpr}: stats {stp} err/bbox={_err(xp, ref['x'], prob):.3e}")
+            assert rcp == 0 and stp["iterations"] == 10 and stp["cg_not_converged"] == 0
+            assert _err(xp, ref["x"], prob) <= 1e-9
+    finally:
+        ctx.set_tuning(**base)
     ch.close()
 
 
@@ -199,6 +210,15 @@ def test_humanoid_frame(ctx, precision, tol):
     _say(f"  stats {st}  err/bbox={_err(x, ref['x'], prob):.3e}")
     assert rc == 0
     assert _err(x, ref["x"], prob) <= tol
+    if precision == mfs.FP64:  # the pipelined PCG form in FP64 as well
+        base = ctx.tuning()
+        try:
+            ctx.set_tuning(pcg_pipelined=1, pcg_persistent=0)
+            xp, stp, rcp = ch.solve(*pose, **kw)
+            _say(f"  pipelined FP64: stats {stp}  err/bbox={_err(xp, ref['x'], prob):.3e}")
+            assert rcp == 0 and _err(xp, ref["x"], prob) <= tol
+        finally:
+            ctx.set_tuning(**base)
     ch.close()
 
 
