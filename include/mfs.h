@@ -174,9 +174,10 @@ typedef struct mfs_tuning {
                                  tiles are folded by every workgroup of the next kernel
                                  (no fences); larger systems fold them in the last workgroup
                                  to finish (arrival ticket with a release fence) */
-  int32_t pcg_persistent;     /* 1 (FP32_REFINED solves): a pipelined PCG whose workgroups (one per 64-row tile of
-                                 every system in the batch, the tile's matrix rows held in
-                                 LDS) all fit on the device at once runs as one cooperative
+  int32_t pcg_persistent;     /* 1 (FP32_REFINED solves): a pipelined PCG whose workgroups
+                                 (one per 64-row tile of every system in the batch, the
+                                 tile's matrix rows held in LDS) all fit on the device at
+                                 once runs as one cooperative
                                  launch with a barrier per iteration instead of one launch
                                  per iteration; the iterates are the same bitwise.  Default
                                  0: it pays off for small systems, where the launch per
