@@ -177,11 +177,11 @@ typedef struct mfs_tuning {
   int32_t pcg_persistent;     /* 1 (FP32_REFINED solves): a pipelined PCG whose workgroups
                                  (one per 64-row tile of every system in the batch, the
                                  tile's matrix rows held in LDS) all fit on the device at
-                                 once runs as one cooperative
-                                 launch with a barrier per iteration instead of one launch
-                                 per iteration; the iterates are the same bitwise.  Default
-                                 0: it pays off for small systems, where the launch per
-                                 iteration dominates (the autotuner tries it) */
+                                 once runs as one cooperative launch with a barrier per
+                                 iteration instead of one launch per iteration; the
+                                 iterates are the same bitwise.  Default 0: it pays off for
+                                 small systems, where the launch per iteration dominates
+                                 (the autotuner tries it) */
 } mfs_tuning;
 
 int mfs_context_get_tuning(const mfs_context* ctx, mfs_tuning* out);
