@@ -42,14 +42,24 @@ Readings taken where the paper is silent, garbled or inconsistent:
       zero-length segment.
   R9  Neo-Hookean Hessian clamp: (mu - lam ln J) -> max(mu - lam ln J, 0) in
       the Hessian only, so every element block is positive semidefinite.
-  R10 Line search (absent from the paper): alpha = 1, 1/2, ... (40 halvings);
-      accept when every neo-Hookean S_k is positive definite and Armijo holds,
-      E(x + a dx) <= E(x) + 1e-4 a gradE.dx + 1e-12 |E(x)| (the last term
-      absorbs FP64 rounding of E).  The first (mixed predictor) step needs
-      only feasibility when E(x0) = +inf, else E(x1) <= E(x0) + 1e-12 |E(x0)|.
+  R10 Line search (absent from the paper): alpha = 1, 1/2, ... (40 halvings).
+      Newton phase (s = J x): accept when every neo-Hookean S_k(x + a dx) is
+      positive definite and Armijo holds, E(x + a dx) <= E(x) + 1e-4 a
+      gradE.dx + 1e-12 |E(x)| (the last term absorbs FP64 rounding of E).
+      Mixed phase (s != J x, the predictor steps): the largest halving for
+      which every neo-Hookean s_k + a ds_k is positive definite, with no
+      energy test.  The mixed step is a Newton step of the mixed problem in
+      (x, s) with the constraint linearised, not a descent step of E(x): at
+      an iterate with s != J x the condensed energy E(x) is not the function
+      being minimised, so asking E(x1) <= E(x0) would reject steps of the
+      method itself (a full step lands on the constraint s = J x, where the
+      Newton phase and its Armijo test take over).
   R11 Stop after a fixed iteration count (predictor counts as iteration 1),
       or when max_v ||alpha dx_v|| <= step_tol * bbox_diag.
-  R12 Load stepping for poses whose mixed phase stalls (see solve_frame).
+  R12 Mixed phase, then Newton phase: s starts at the polar stretch of F(x0)
+      (R1) and moves by alpha (J(x + dx) - s) under the mixed rule of R10;
+      alpha = 1 puts s on the constraint and starts the Newton phase.  Load
+      stepping for poses whose mixed phase stalls (see solve_frame).
 
 Extension beyond the paper's per-frame statement: external vertex forces
 f_ext (the local-perturbation experiment of Section 4) enter as the
@@ -83,7 +93,10 @@ class DegenerateElement(ValueError):
 
 
 def lame(youngs, poisson):
-    """Lame parameters (mu, lambda) from Young's modulus and Poisson ratio."""
+    """Lame parameters (mu, lambda) of isotropic linear elasticity from Young's
+    modulus E and Poisson ratio nu: mu = E / (2 (1 + nu)) and
+    lambda = E nu / ((1 + nu)(1 - 2 nu)) (reading R6; the paper gives
+    stiffnesses, not formulas)."""
     E = np.asarray(youngs, dtype=np.float64)
     nu = np.asarray(poisson, dtype=np.float64)
     return E / (2.0 * (1.0 + nu)), E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))

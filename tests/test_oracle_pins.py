@@ -560,3 +560,72 @@ def test_smoothed_rotations_rigid_pose_and_zero_width():
     assert np.array_equal(r0["x"], rc["x"])
     rs = oracle.solve_frame(pb, pose, iterations=3)
     assert np.max(np.abs(rs["x"] - rc["x"])) > 1e-6 * prob["bbox_diag"]  # smoothing changes the frame
+
+
+# --------------------------------------------------------------------------
+# Lame parameters (reading R6): the values of the 1536-tet beam's material
+# (E = 1e5, nu = 0.45), and a uniaxial-stress test through the co-rotated
+# element, whose small-strain response is isotropic linear elasticity: with
+# the lateral stresses zero, stress / axial strain must be E and the lateral
+# contraction nu.
+# --------------------------------------------------------------------------
+def test_lame_values_and_uniaxial_stress():
+    mu, lam = oracle.lame(np.array([1e5]), np.array([0.45]))
+    assert abs(mu[0] - 34482.75862068966) <= 1e-9 * 34482.75862068966
+    assert abs(lam[0] - 310344.8275862069) <= 1e-9 * 310344.8275862069
+    assert abs(lam[0] / mu[0] - 9.0) <= 1e-12
+    rng = np.random.default_rng(11)
+    E = rng.uniform(1e3, 1e7, 8)
+    nu = np.concatenate([[0.0, 0.25, 0.3, 0.49, 0.499], rng.uniform(-0.9, 0.49, 3)])
+    mu, lam = oracle.lame(E, nu)
+    mod = np.full(len(E), COROT, dtype=np.int32)
+    # diagonal strain e -> diagonal stress P_ii = g_i(I + diag(e)); linear for
+    # the co-rotated energy, so unit strains give its 3x3 stiffness columns
+    C = np.zeros((len(E), 3, 3))
+    for j in range(3):
+        s = np.tile([1.0, 1.0, 1.0, 0.0, 0.0, 0.0], (len(E), 1))
+        s[:, j] += 1.0
+        C[:, :, j] = oracle.stretch_gradient(s, mod, mu, lam)[:, :3]
+    for k in range(len(E)):
+        # axial strain 1, lateral strains (l, l) with zero lateral stress
+        lat = np.linalg.solve(C[k, 1:, 1:], -C[k, 1:, 0])
+        axial_stress = C[k, 0, 0] + C[k, 0, 1:] @ lat
+        assert abs(axial_stress - E[k]) <= 1e-11 * E[k]
+        assert np.allclose(-lat, nu[k], rtol=0, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Mixed-phase step rule (reading R10): the accepted step is the largest
+# halving of 1 that keeps every neo-Hookean s + alpha ds positive definite
+# (checked by eigenvalues, not the oracle's Sylvester test), and there is no
+# energy test: E(x) may even leave the feasible set during the mixed phase.
+# --------------------------------------------------------------------------
+def test_mixed_step_is_largest_feasible_halving():
+    prob = humanoid(21, target_tets=4000, n_bones=15)
+    for seed, finite_then_infinite in ((25, False), (22, True)):
+        pose = random_pose(prob, seed)
+        r = oracle.solve_frame(prob, pose, iterations=2)
+        assert r["phase"] == ["mixed", "mixed"]
+        fr = oracle.Frame(prob, pose)
+        nh = fr.model == NH
+        x = fr.X.reshape(-1).copy()
+        s = oracle.polar_stretch(fr.deformation_gradient(x))
+        for it in range(2):
+            dx = oracle.mfem._linear_solve(fr.hessian(s), -fr.gradient(x, s_lin=s), "splu")
+            ds = fr.stretch(x + dx) - s
+            a = r["alpha"][it]
+
+            def min_eig(alpha):
+                return np.linalg.eigvalsh(oracle.unvech((s + alpha * ds)[nh])).min()
+            assert a > 0.0 and math.log2(a) == round(math.log2(a))
+            assert min_eig(a) > 0.0
+            assert a == 1.0 or min_eig(2.0 * a) <= 0.0
+            x = x + a * dx
+            s = s + a * ds
+        assert np.allclose(x.reshape(-1, 3), r["x"], rtol=0, atol=1e-12 * prob["bbox_diag"])
+        # the step rule ignores E(x): the rest shape is infeasible for these
+        # poses, and in one of them the second mixed step goes from a finite
+        # E(x1) to E(x2) = +inf
+        assert r["energy"][0] == np.inf
+        if finite_then_infinite:
+            assert np.isfinite(r["energy"][1]) and r["energy"][2] == np.inf
