@@ -200,12 +200,26 @@ int mfs_context_set_tuning(mfs_context* ctx, const mfs_tuning* tuning);
 int mfs_character_create(mfs_context* ctx, const mfs_mesh_desc* desc, mfs_character** out);
 int mfs_character_destroy(mfs_character* ch);
 
-/* Device bytes the character keeps resident between frames (mesh data,
- * assembly map, positions and stretches) and the bytes of its solve
- * workspace (element state, matrix values, PCG vectors, reductions), for
- * admission by memory footprint.  Either output may be NULL. */
-int mfs_character_footprint(const mfs_character* ch, size_t* resident_bytes,
+/* Device bytes that mfs_character_create would allocate for this mesh,
+ * computed on the host before anything is uploaded, so that a caller can
+ * admit a character, or size a server's arena, by its memory footprint
+ * (Algorithm 1's inputs: the rest tet mesh and its pins).  resident_bytes:
+ * what the character keeps between frames (mesh data, assembly map,
+ * positions and stretches); workspace_bytes: one frame solve's workspace
+ * (element state, matrix values, PCG vectors, reductions), the amount a
+ * server lends a character whose workspace was released.  Reads n_vertices,
+ * n_tets, tets, n_pins and memory_space only (tets host or device); the
+ * matrix has one 3x3 block per vertex and two per mesh edge.  No GPU work
+ * for host arrays.  Either output may be NULL.  Errors: MFS_E_INVALID
+ * (sizes out of range, a vertex index out of range, a tet repeating a
+ * vertex, a vertex in no tet: the checks of mfs_character_create on these
+ * fields), MFS_E_HIP (device tets). */
+int mfs_character_footprint(const mfs_mesh_desc* desc, size_t* resident_bytes,
                             size_t* workspace_bytes);
+
+/* The same two byte counts for a created character, as allocated. */
+int mfs_character_get_footprint(const mfs_character* ch, size_t* resident_bytes,
+                                size_t* workspace_bytes);
 
 /* External vertex forces (the f_ext term of the next-step extensions: a
  * load b += f_ext on selected vertices, potential -f . x in E), used by
@@ -432,13 +446,16 @@ typedef struct mfs_profile {
   int64_t launches[MFS_K_FAMILIES];  /* all launches of the family */
   double bytes[MFS_K_FAMILIES];      /* algorithmic HBM bytes of the timed launches, counted
                                         for the systems a launch iterates (a system whose PCG
-                                        stopped earlier in the run costs nothing).  SpMV family:
-                                        every block value and column index and the row
-                                        pointers, plus per row the two gathered inputs and
-                                        two outputs (two-kernel PCG) or the gathered m, nine
-                                        FP64 vectors read and written and the 3x3
-                                        preconditioner block (pipelined PCG); 0 for families
-                                        without a byte model */
+                                        stopped earlier in the run costs nothing).  SpMV family,
+                                        per system with n block rows and nnzb blocks and w the
+                                        solve's word size: the least a block-sparse product
+                                        moves, nnzb (9 w + 4) + 4 (n + 1) + 6 w n (blocks,
+                                        column indices, row pointers, one input and one output
+                                        vector), plus 42 w n in the pipelined form, which fuses
+                                        the PCG vector work and the block-Jacobi
+                                        preconditioner (twelve passes over 3n values and six
+                                        preconditioner values per row); 0 for families without
+                                        a byte model */
 } mfs_profile;
 
 /* Time kernel launches of this context with HIP events on its stream:

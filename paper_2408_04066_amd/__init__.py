@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 __all__ = ["MfsError", "MfsUnavailable", "Context", "Character", "SolveOpts", "SolveStats",
-           "solve_batch", "autotune", "Server", "lib", "EXPORTED", "ARAP", "COROT", "NEOHOOKEAN", "FP64", "FP32_REFINED",
+           "solve_batch", "autotune", "mesh_footprint", "Server", "lib", "EXPORTED", "ARAP", "COROT", "NEOHOOKEAN", "FP64", "FP32_REFINED",
            "MEM_HOST", "MEM_DEVICE", "WARM_REST", "WARM_PREVIOUS"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmfs.so")
@@ -35,7 +35,7 @@ EXPORTED = ("mfs_default_opts", "mfs_status_string", "mfs_last_error", "mfs_cont
             "mfs_server_create", "mfs_server_destroy", "mfs_server_submit", "mfs_server_poll",
             "mfs_server_set_lane_tuning",
             "mfs_server_wait", "mfs_server_get_info", "mfs_autotune", "mfs_character_set_forces",
-            "mfs_stress")
+            "mfs_stress", "mfs_character_get_footprint")
 
 KERNEL_FAMILIES = ("warm_start", "element", "assemble", "spmv", "cg_update", "linesearch", "update",
                    "other")
@@ -131,7 +131,8 @@ def lib():
         "mfs_context_destroy": (ctypes.c_int, [c_vp]),
         "mfs_character_create": (ctypes.c_int, [c_vp, P(MeshDesc), P(c_vp)]),
         "mfs_character_destroy": (ctypes.c_int, [c_vp]),
-        "mfs_character_footprint": (ctypes.c_int, [c_vp, P(ctypes.c_size_t), P(ctypes.c_size_t)]),
+        "mfs_character_footprint": (ctypes.c_int, [P(MeshDesc), P(ctypes.c_size_t), P(ctypes.c_size_t)]),
+        "mfs_character_get_footprint": (ctypes.c_int, [c_vp, P(ctypes.c_size_t), P(ctypes.c_size_t)]),
         "mfs_cluster_by_segments": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_i32, c_vp, c_vp,
                                                    c_vp, c_vp, c_i32]),
         "mfs_solve_frame": (ctypes.c_int, [c_vp, c_vp, c_vp, P(SolveOpts), c_vp, P(SolveStats)]),
@@ -289,6 +290,21 @@ class Context:
         return U.reshape(c, 3, 3), P, s, routed
 
 
+def mesh_footprint(prob):
+    """(resident bytes, workspace bytes) that a Character of ``prob`` would
+    allocate, computed on the host before any upload
+    (``mfs_character_footprint``)."""
+    X = _host(prob["X"], np.float64)
+    T = _host(prob["T"], np.int32)
+    d = MeshDesc()
+    d.n_vertices, d.n_tets, d.tets = X.shape[0], T.shape[0], _ptr(T)
+    d.n_pins = len(prob["pin_vertex"])
+    d.memory_space = MEM_HOST
+    r, w = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().mfs_character_footprint(ctypes.byref(d), ctypes.byref(r), ctypes.byref(w)))
+    return r.value, w.value
+
+
 def autotune(ctx, chars, poses, newton_iterations=4, cache_path=None, force=False, **opts):
     """Pick and apply the PCG launch schedule for a batch like ``chars``
     (``mfs_autotune``).  Returns (tuning dict, best milliseconds)."""
@@ -359,8 +375,9 @@ class Character:
         return {name: getattr(i, name) for name, _ in i._fields_ if name != "reserved"}
 
     def footprint(self):
+        """(resident bytes, workspace bytes) as allocated."""
         r, w = ctypes.c_size_t(), ctypes.c_size_t()
-        _check(lib().mfs_character_footprint(self.handle, ctypes.byref(r), ctypes.byref(w)))
+        _check(lib().mfs_character_get_footprint(self.handle, ctypes.byref(r), ctypes.byref(w)))
         return r.value, w.value
 
     def set_rotation_blend(self, handles=None, weights=None):

@@ -197,19 +197,25 @@ using namespace mfs;
 namespace mfs {
 
 namespace {
+// Tiles per system: the partial-result stride of a character of these sizes.
+int64_t partial_tiles(int64_t n, int64_t m, int64_t nnzb) {
+  const int64_t ntv = (n + kVTile - 1) / kVTile, ntt = (m + kTTile - 1) / kTTile, nts = (nnzb + kSTile - 1) / kSTile;
+  return std::max(ntv, std::max(ntt, nts));
+}
+
 // Byte sizes of the workspace pieces, in carving order.
-int workspace_pieces(const mfs_character* ch, size_t* sz) {
-  const size_t n3 = 3 * sizeof(double) * (size_t)ch->n;
-  const size_t m = (size_t)ch->m;
+int workspace_pieces(int64_t n, int64_t m_, int64_t nnzb, size_t* sz) {
+  const size_t n3 = 3 * sizeof(double) * (size_t)n;
+  const size_t m = (size_t)m_;
   int k = 0;
   sz[k++] = 90 * sizeof(double) * m;                          // blk
   sz[k++] = 12 * sizeof(double) * m;                          // frc
   sz[k++] = n3;                                               // b
   sz[k++] = n3;                                               // dx
-  sz[k++] = 9 * sizeof(double) * (size_t)ch->nnzb;            // vals
-  sz[k++] = 6 * sizeof(double) * (size_t)ch->n;               // minv
+  sz[k++] = 9 * sizeof(double) * (size_t)nnzb;                // vals
+  sz[k++] = 6 * sizeof(double) * (size_t)n;                   // minv
   for (int v = 0; v < 10; ++v) sz[k++] = n3;                  // r z p0 p1 q xc v0 v1 v2 v3
-  sz[k++] = sizeof(double) * P_COUNT * (size_t)ch->ptile;     // part
+  sz[k++] = sizeof(double) * P_COUNT * (size_t)partial_tiles(n, m_, nnzb);  // part
   sz[k++] = sizeof(double) * P_COUNT;                         // red
   return k;
 }
@@ -217,17 +223,32 @@ constexpr size_t kWsAlign = 256;
 size_t align_up(size_t v) { return (v + kWsAlign - 1) / kWsAlign * kWsAlign; }
 }  // namespace
 
-size_t workspace_layout(const mfs_character* ch) {
+size_t workspace_bytes_of(int64_t n, int64_t m, int64_t nnzb) {
   size_t sz[24];
-  const int k = workspace_pieces(ch, sz);
+  const int k = workspace_pieces(n, m, nnzb, sz);
   size_t total = 0;
   for (int i = 0; i < k; ++i) total += align_up(sz[i]);
   return total;
 }
 
+// Every resident device buffer of mfs_character_create, by its exact size.
+// Per tet: tets 16, G 72, W mu 8, W lambda 8, info 4, tet order 4, s 48 and
+// the 16 slot contributions 64 bytes.  Per vertex: X 24, diagonal slot 4,
+// vertex order 4, x 24 and its backup 24, plus row pointers and pin pointers
+// (4 per vertex and one more each).  Per block: column index 4 and slot
+// pointer 4 (one more).  Per pin: its handle 4.  And the pose tables for the
+// largest handle count.
+size_t resident_bytes_of(int64_t n_, int64_t m_, int64_t nnzb_, int64_t np_) {
+  const size_t n = (size_t)n_, m = (size_t)m_, nnzb = (size_t)nnzb_, np = (size_t)np_;
+  return m * (16 + 72 + 8 + 8 + 4 + 4 + 48 + 64) + n * (24 + 4 + 4 + 24 + 24) + 4 * (n + 1) * 2 +
+         4 * nnzb + 4 * (nnzb + 1) + 4 * np + (9 + 3) * sizeof(double) * kMaxHandles;
+}
+
+size_t workspace_layout(const mfs_character* ch) { return workspace_bytes_of(ch->n, ch->m, ch->nnzb); }
+
 void bind_workspace(const mfs_character* ch, char* base, SysDesc* d) {
   size_t sz[24];
-  const int k = workspace_pieces(ch, sz);
+  const int k = workspace_pieces(ch->n, ch->m, ch->nnzb, sz);
   void* ptr[24];
   size_t off = 0;
   for (int i = 0; i < k; ++i) {
@@ -556,6 +577,8 @@ extern "C" int mfs_character_create(mfs_context* ctx, const mfs_mesh_desc* d, mf
   s.s = ch->s.as<double>();
   bind_workspace(ch, ch->ws.as<char>(), &s);
 
+  // the sizes actually allocated (mfs_character_footprint predicts them from
+  // a descriptor with resident_bytes_of)
   ch->resident_bytes = ch->tets.bytes + ch->G.bytes + ch->wmu.bytes + ch->wlam.bytes + ch->info.bytes + ch->X.bytes +
                        ch->rowptr.bytes + ch->colidx.bytes + ch->slot_ptr.bytes + ch->contrib.bytes +
                        ch->diag.bytes + ch->vpin_ptr.bytes + ch->vpin_h.bytes + ch->perm_d.bytes +
@@ -675,10 +698,50 @@ extern "C" int mfs_character_release_workspace(mfs_character* ch) {
   return MFS_OK;
 }
 
-extern "C" int mfs_character_footprint(const mfs_character* ch, size_t* resident, size_t* workspace) {
+extern "C" int mfs_character_get_footprint(const mfs_character* ch, size_t* resident, size_t* workspace) {
   clear_error();
   if (!ch) return set_error(MFS_E_INVALID, "null character");
   if (resident) *resident = ch->resident_bytes;
   if (workspace) *workspace = ch->workspace_bytes;
+  return MFS_OK;
+}
+
+// The byte counts of mfs_character_create for a mesh not yet uploaded: the
+// block count of the condensed matrix is one diagonal block per vertex plus
+// two per mesh edge (both triangles), the edges being the distinct vertex
+// pairs of the tets.
+extern "C" int mfs_character_footprint(const mfs_mesh_desc* d, size_t* resident, size_t* workspace) {
+  clear_error();
+  if (!d) return set_error(MFS_E_INVALID, "null descriptor");
+  if (d->n_vertices < 4 || d->n_vertices > (1LL << 30)) return set_error(MFS_E_INVALID, "n_vertices out of range");
+  if (d->n_tets < 1 || d->n_tets > (1LL << 27)) return set_error(MFS_E_INVALID, "n_tets out of range");
+  if (d->n_pins < 1 || d->n_pins > (1LL << 30)) return set_error(MFS_E_INVALID, "n_pins out of range");
+  if (!d->tets) return set_error(MFS_E_INVALID, "null tets");
+  const int64_t n = d->n_vertices, m = d->n_tets;
+  std::vector<int32_t> T;
+  MFS_TRY(fetch(d->tets, 4 * (size_t)m, d->memory_space, T));
+  std::vector<char> used((size_t)n, 0);
+  std::vector<int64_t> edges;
+  edges.reserve(6 * (size_t)m);
+  for (int64_t k = 0; k < m; ++k) {
+    const int32_t* t = &T[4 * (size_t)k];
+    for (int a = 0; a < 4; ++a) {
+      if (t[a] < 0 || t[a] >= n)
+        return set_error(MFS_E_INVALID, "tet %lld: vertex index %d out of range", (long long)k, t[a]);
+      used[t[a]] = 1;
+      for (int b = 0; b < a; ++b) {
+        if (t[a] == t[b]) return set_error(MFS_E_INVALID, "tet %lld repeats vertex %d", (long long)k, t[a]);
+        const int64_t lo = std::min(t[a], t[b]), hi = std::max(t[a], t[b]);
+        edges.push_back(lo * n + hi);
+      }
+    }
+  }
+  for (int64_t v = 0; v < n; ++v)
+    if (!used[v]) return set_error(MFS_E_INVALID, "vertex %lld belongs to no tet", (long long)v);
+  std::sort(edges.begin(), edges.end());
+  const int64_t ne = std::unique(edges.begin(), edges.end()) - edges.begin();
+  const int64_t nnzb = n + 2 * ne;
+  if (resident) *resident = resident_bytes_of(n, m, nnzb, d->n_pins);
+  if (workspace) *workspace = workspace_bytes_of(n, m, nnzb);
   return MFS_OK;
 }

@@ -470,13 +470,16 @@ int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* fai
     max_cap = std::max(max_cap, cap[i]);
   }
   std::vector<int> stopped_at(slot_.size(), -1);
-  // algorithmic bytes of one SpMV launch over the slots still in PCG, for
-  // the profiler's roofline figures: blocks + column indices + row pointers,
-  // and per row 2 gathered inputs and 2 outputs (standard form), or the
-  // gathered m, 9 vectors read and 9 written (FP64) and the 3x3
-  // preconditioner block (pipelined form, which fuses the vector updates)
+  // algorithmic bytes of one SpMV-family launch over the slots still in
+  // PCG, for the profiler's roofline figures: the least a block-sparse
+  // product must move, every block value and column index, the row
+  // pointers, one input and one output vector (nnzb (9w + 4) + 4 (n + 1) +
+  // 6 w n, w the solve's word size); the pipelined form fuses the PCG
+  // vector work and the block-Jacobi preconditioner into the same launch,
+  // which adds twelve passes over 3n values and the 6 preconditioner values
+  // per row (42 w n)
   const double word = fp32 ? 4.0 : 8.0;
-  const double per_row = pipe ? (3.0 + 27.0 + 27.0) * 8.0 + 6.0 * word : 12.0 * word;
+  const double per_row = pipe ? (6.0 + 42.0) * word : 6.0 * word;
   // A launch at iteration index `it` does work for a slot whose PCG had not
   // stopped before it (a stopped slot's launches return at once).
   auto attribute_bytes = [&]() {
@@ -515,15 +518,15 @@ int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* fai
         MFS_HIP(launch_pcg_persist(ctx->stream, dsd, ts_.dv, ts_.nv, ctx->lpr, lds));
       }
       MFS_TRY(read_cg(ctx, n, false));
-      // algorithmic bytes: the matrix, the rows' vectors and preconditioner
-      // blocks once; per iteration the gathered m_i and the stored m_i+1
+      // algorithmic bytes: those of one pipelined launch (FP32, above) per
+      // iteration, as for the per-launch form (the persistent kernel keeps
+      // the matrix rows in LDS and moves less)
       for (ProfPending& p : ctx->pending) {
         if (p.fam != MFS_K_SPMV || p.tag != kPersistTag) continue;
         double by = 0.0;
         for (int i : act) {
           const mfs_character* c = slot_[i].ch;
-          by += c->nnzb * (9.0 * 4.0 + 4.0) + (c->n + 1) * 4.0 + c->n * (9.0 * 24.0 + 24.0 + 24.0) +
-                (double)hg[i].iters * c->n * 48.0;
+          by += (double)hg[i].iters * (c->nnzb * (9.0 * 4.0 + 4.0) + (c->n + 1) * 4.0 + c->n * 48.0 * 4.0);
         }
         p.bytes = by;
         p.tag = -1;

@@ -185,6 +185,10 @@ int check_pose(const mfs_character* ch, const double* R, const double* t);
 // Workspace of one frame solve of `ch`: total bytes (pieces 256-byte
 // aligned), and the SysDesc workspace pointers carved from `base`.
 size_t workspace_layout(const mfs_character* ch);
+// Device bytes of a character with n vertices, m tets, nnzb matrix blocks and
+// np pins: its resident data, and one frame solve's workspace.
+size_t resident_bytes_of(int64_t n, int64_t m, int64_t nnzb, int64_t np);
+size_t workspace_bytes_of(int64_t n, int64_t m, int64_t nnzb);
 void bind_workspace(const mfs_character* ch, char* base, SysDesc* d);
 // Re-allocates the character's own workspace after a release.
 int ensure_workspace(mfs_character* ch);

@@ -222,3 +222,33 @@ def test_zero_loads_equal_no_loads(ctx):
     x1, _, rc = ch.solve(*pose, precision=mfs.FP64)
     assert rc == 0 and np.array_equal(x0, x1)
     ch.close()
+
+
+def test_footprint_from_descriptor_matches_created_character(ctx):
+    """The descriptor form of mfs_character_footprint, computed before any
+    upload, equals the bytes a created character allocated (resident data and
+    workspace), on meshes from one tet to the 50k-tet humanoid; the device-
+    array form of the descriptor gives the same numbers."""
+    mfs = _mfs()
+    probs = [tiny_mesh("tet"), tiny_mesh("cube"), beam(), humanoid(21, target_tets=4000, n_bones=15),
+             humanoid(2001, target_tets=50000, n_bones=20)]
+    for prob in probs:
+        if "cluster" not in prob and "seg_a" not in prob:
+            prob["cluster"] = np.zeros(len(prob["T"]), dtype=np.int32)
+        want = mfs.mesh_footprint(prob)
+        ch = mfs.Character(ctx, prob)
+        got = ch.footprint()
+        info = ch.info()
+        _say(f"m={len(prob['T'])}: descriptor {want}, created {got}, blocks {info['n_blocks']}")
+        assert want == got
+        ch.close()
+    # tets in device memory
+    prob = probs[2]
+    T = torch.as_tensor(np.asarray(prob["T"], dtype=np.int32), device="cuda")
+    import ctypes
+    d = mfs.MeshDesc()
+    d.n_vertices, d.n_tets, d.tets = len(prob["X"]), len(prob["T"]), T.data_ptr()
+    d.n_pins, d.memory_space = len(prob["pin_vertex"]), mfs.MEM_DEVICE
+    r, w = ctypes.c_size_t(), ctypes.c_size_t()
+    assert mfs.lib().mfs_character_footprint(ctypes.byref(d), ctypes.byref(r), ctypes.byref(w)) == 0
+    assert (r.value, w.value) == mfs.mesh_footprint(prob)

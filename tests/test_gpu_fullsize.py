@@ -8,10 +8,13 @@ of the same state (the full-size element pass); the solution is stationary
 (the oracle's largest residual force there is orders below the largest pin
 force at the rest shape, the load the elastic forces balance); and the
 FP32 + refinement solution lies within 1e-7 of the bbox diagonal of a tight
-FP64 solve continued from it, itself stationary by the oracle's gradient.  The batched workload is checked on a sample of its
-members after one batched solve of all of them.
+FP64 solve continued from it, itself stationary by the oracle's gradient.
+The batched workload is checked on a sample of its members after one
+batched solve of all of them, and its positions are compared with the
+oracle's own solutions of a size-stratified subset of the members.
 """
 
+import os
 import sys
 
 import numpy as np
@@ -118,9 +121,13 @@ def test_large_character_at_full_size(mfs):
     ctx.close()
 
 
-def test_batched_characters_at_full_size(mfs):
-    """The 64-character batch in one batched run with the bench's options;
-    four members (smallest, largest and two between) checked by the oracle."""
+GOLDEN_C4 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c4_oracle_subset.npz")
+
+
+@pytest.fixture(scope="module")
+def c4_batch(mfs):
+    """The 64-character batch, autotuned and solved once in one batched run
+    with the bench's options: (probs, poses, ctx, chars, xs, stats, opts)."""
     import bench
     # the pool does not depend on the worker count; this process already
     # holds the GPU, so its forked builders stay well inside the box's limit
@@ -133,6 +140,46 @@ def test_batched_characters_at_full_size(mfs):
     t, _ = mfs.autotune(ctx, chars, poses, newton_iterations=2, **opts)
     _say(f"  schedule {t}")
     xs, sts, rc = mfs.solve_batch(ctx, chars, poses, **opts)
+    yield probs, poses, ctx, chars, [x.copy() for x in xs], sts, opts
+    for c in chars:
+        c.close()
+    ctx.close()
+
+
+def test_batched_positions_match_oracle_solutions(c4_batch):
+    """The oracle's solved positions x* of a size-stratified subset of the
+    batch's members (smallest, quartiles, largest and three random ones,
+    written by tests/golden/make_golden_c4.py from the oracle alone) against
+    the batched FP32 + refinement result, within 1e-7 of the bbox diagonal,
+    and a tight FP64 solve continued from it, within 1e-9 (Algorithm 1's
+    output: the deformed positions)."""
+    probs, poses, ctx, chars, xs, sts, _ = c4_batch
+    sys.path.insert(0, os.path.dirname(GOLDEN_C4))
+    from make_golden_c4 import input_hash
+    gold = np.load(GOLDEN_C4, allow_pickle=False)
+    for k in gold["members"]:
+        k = int(k)
+        prob, pose = probs[k], poses[k]
+        assert str(gold[f"hash_{k}"]) == input_hash(prob, pose), f"member {k}: inputs differ from the golden's"
+        idx = gold[f"idx_{k}"]
+        xo = gold[f"x_{k}"]
+        bbox = prob["bbox_diag"]
+        _say(f"  member {k}: m={len(prob['T'])} oracle {int(gold[f'iterations_{k}'])} iterations, "
+             f"batch {sts[k]}")
+        assert sts[k]["status"] == 0, f"member {k} did not converge in the batch"
+        e32 = _err(xs[k][idx], xo, bbox)
+        xt, stt, rct = _tight(ctx, chars[k], pose)
+        e64 = _err(xt[idx], xo, bbox)
+        _say(f"  member {k}: |x_batch - x*| / bbox = {e32:.3e}, |x_tight_fp64 - x*| / bbox = {e64:.3e}")
+        assert rct == 0
+        assert e32 <= 1e-7
+        assert e64 <= 1e-9
+
+
+def test_batched_characters_at_full_size(c4_batch):
+    """Members of the same batched run (smallest, largest and two between)
+    checked by the oracle's energy and gradient against a tight FP64 solve."""
+    probs, poses, ctx, chars, xs, sts, _ = c4_batch
     sizes = np.array([len(p["T"]) for p in probs])
     order = np.argsort(sizes)
     conv = [k for k in order if sts[k]["status"] == 0]
@@ -168,6 +215,3 @@ def test_batched_characters_at_full_size(mfs):
             checked += 1
             break
     assert checked == len(groups)
-    for c in chars:
-        c.close()
-    ctx.close()

@@ -101,3 +101,30 @@ def test_missing_library_and_missing_gpu_fail_loudly():
         "    print('error', type(e).__name__)\n")
     r = subprocess.run([sys.executable, "-c", code_nogpu], cwd=ROOT, capture_output=True, text=True, timeout=120)
     assert r.stdout.startswith("error"), (r.stdout, r.stderr)
+
+
+def _fp(T, n, n_pins=3):
+    import numpy as np
+    T = np.asarray(T, dtype=np.int32)
+    prob = {"X": np.zeros((n, 3)), "T": T, "pin_vertex": np.arange(n_pins)}
+    return mfs.mesh_footprint(prob)
+
+
+def test_footprint_from_descriptor_on_the_host():
+    """mfs_character_footprint reads only the tets and sizes (host arrays, no
+    GPU work): the matrix has one block per vertex and two per distinct
+    edge, 8 resident bytes per block (column index and slot pointer), and a
+    pin costs 4 resident bytes."""
+    # three tets on six vertices: around one face (12 distinct edges) or in a
+    # ring (15 distinct edges); the same n, m and pins
+    fan = [(0, 1, 2, 3), (0, 1, 2, 4), (0, 1, 2, 5)]
+    ring = [(0, 1, 2, 3), (2, 3, 4, 5), (0, 1, 4, 5)]
+    r_fan, w_fan = _fp(fan, 6)
+    r_ring, w_ring = _fp(ring, 6)
+    assert r_ring - r_fan == 8 * 2 * (15 - 12)
+    assert w_ring >= w_fan
+    assert _fp(ring, 6, n_pins=4)[0] - r_ring == 4
+    for T, n in (([(0, 1, 2, 6)], 6), ([(0, 1, 1, 2)], 4), ([(0, 1, 2, 3)], 5)):
+        with pytest.raises(mfs.MfsError) as e:
+            _fp(T, n)
+        assert e.value.code == -1

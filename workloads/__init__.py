@@ -15,11 +15,11 @@ A problem is a plain dict (see ``problem_keys``); a pose is a pair of arrays
 from .common import (ARAP, COROT, NH, MODEL_NAMES, problem_keys,
                      rot_x, rot_y, rot_z, euler_xyz, mean_edge_length)
 from .beam import beam, beam_pose, tiny_mesh
-from .humanoid import humanoid, random_pose, animation_pose, character_pool
+from .humanoid import humanoid, random_pose, animation_pose, character_pool, pool_member
 
 __all__ = [
     "ARAP", "COROT", "NH", "MODEL_NAMES", "problem_keys",
     "rot_x", "rot_y", "rot_z", "euler_xyz", "mean_edge_length",
     "beam", "beam_pose", "tiny_mesh",
-    "humanoid", "random_pose", "animation_pose", "character_pool",
+    "humanoid", "random_pose", "animation_pose", "character_pool", "pool_member",
 ]

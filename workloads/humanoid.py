@@ -295,6 +295,11 @@ def _pool_member(args):
     return humanoid(seed0 + i, target_tets=m, n_bones=nh, models=models, name=f"char{i}_s{seed0 + i}")
 
 
+def pool_member(i, seed0, tets_range, handles_range, models):
+    """Member i of ``character_pool(count, seed0, ...)`` built on its own."""
+    return _pool_member((i, seed0, tets_range, handles_range, tuple(models)))
+
+
 def character_pool(count, seed0, tets_range, handles_range, models, workers=1):
     """Characters with log-uniform sizes and uniform handle counts.
 
