@@ -501,6 +501,26 @@ int mfs_evaluate(mfs_character* ch, const double* handle_R, const double* handle
 int mfs_stress(mfs_character* ch, const double* handle_R, const double* handle_t, const double* x,
                int32_t memory_space, double* stress_out, double* multiplier_out);
 
+/* mfs_evaluate without allocating: for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and memory spaces as
+ * mfs_evaluate; it calls no hipMalloc, hipFree or other allocating routine.
+ * Every buffer the evaluation needs beyond the caller's inputs and outputs
+ * (the descriptor, the tile list, host staging, and the element records,
+ * matrix values, right-hand side and partial sums of the evaluation) is
+ * carved from one fixed array of 32 MiB in device memory that each GPU holds
+ * from the first context created on it until the process ends; the
+ * character's own workspace is neither used nor allocated.  A character
+ * whose evaluation needs more than that (about 30k tets) is MFS_E_INVALID,
+ * checked before any GPU work.  Calls on one GPU share the array: calls that
+ * overlap on one GPU (from two streams or threads) race on it and must be
+ * serialised by the caller.  The caller's arrays are read during the call
+ * only, and the call synchronises the context's stream before returning. */
+int mfs_evaluate_noalloc(mfs_character* ch, const double* handle_R, const double* handle_t,
+                         const double* x, const double* v, int32_t memory_space,
+                         double* energy_out, double* grad_out, double* stretch_out,
+                         double* Kv_out);
+
 /* Polar decomposition F = U P (U proper rotation, P symmetric) of `count`
  * 3x3 matrices by Higham's scaled Newton iteration, as the solver's warm
  * start uses it.  F, U: count x 9; P: count x 6 (S00,S11,S22,S12,S02,S01);

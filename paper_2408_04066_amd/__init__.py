@@ -35,7 +35,7 @@ EXPORTED = ("mfs_default_opts", "mfs_status_string", "mfs_last_error", "mfs_cont
             "mfs_server_create", "mfs_server_destroy", "mfs_server_submit", "mfs_server_poll",
             "mfs_server_set_lane_tuning",
             "mfs_server_wait", "mfs_server_get_info", "mfs_autotune", "mfs_character_set_forces",
-            "mfs_stress", "mfs_character_get_footprint")
+            "mfs_stress", "mfs_character_get_footprint", "mfs_evaluate_noalloc")
 
 KERNEL_FAMILIES = ("warm_start", "element", "assemble", "spmv", "cg_update", "linesearch", "update",
                    "other")
@@ -139,6 +139,7 @@ def lib():
         "mfs_solve_batch": (ctypes.c_int, [c_vp, c_i32, c_vp, c_vp, c_vp, P(SolveOpts), c_vp,
                                            P(SolveStats)]),
         "mfs_evaluate": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),
+        "mfs_evaluate_noalloc": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),
         "mfs_polar": (ctypes.c_int, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, c_vp, c_i32]),
         "mfs_blend_weights": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, c_i32,
                                              c_dbl, c_i32, c_vp, c_vp, c_i32]),
@@ -439,8 +440,10 @@ class Character:
         _check(lib().mfs_stress(self.handle, _ptr(R), _ptr(t), _ptr(x), MEM_HOST, _ptr(P), _ptr(L)))
         return P, L
 
-    def evaluate(self, R, t, x, v=None, want_grad=True, want_stretch=True):
-        """Energy, gradient, stretches and K v at positions x (host arrays)."""
+    def evaluate(self, R, t, x, v=None, want_grad=True, want_stretch=True, noalloc=False):
+        """Energy, gradient, stretches and K v at positions x (host arrays);
+        ``noalloc`` calls the allocation-free entry point."""
+        fn = lib().mfs_evaluate_noalloc if noalloc else lib().mfs_evaluate
         R, t = self._pose(R, t)
         x = _host(x, np.float64).reshape(self.n, 3)
         E = ctypes.c_double()
@@ -448,8 +451,8 @@ class Character:
         s = np.empty((self.m, 6)) if want_stretch else None
         vv = _host(v, np.float64).reshape(self.n, 3) if v is not None else None
         kv = np.empty((self.n, 3)) if v is not None else None
-        _check(lib().mfs_evaluate(self.handle, _ptr(R), _ptr(t), _ptr(x), _ptr(vv), MEM_HOST,
-                                  ctypes.byref(E), _ptr(g), _ptr(s), _ptr(kv)))
+        _check(fn(self.handle, _ptr(R), _ptr(t), _ptr(x), _ptr(vv), MEM_HOST, ctypes.byref(E), _ptr(g), _ptr(s),
+                  _ptr(kv)))
         return {"energy": E.value, "grad": g, "stretch": s, "Kv": kv}
 
 

@@ -48,6 +48,7 @@ extern "C" int mfs_context_create(int device, void* hip_stream, mfs_context** ou
   MFS_HIP(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return set_error(MFS_E_INVALID, "device %d not present (%d devices)", device, ndev);
   MFS_HIP(hipSetDevice(device));
+  MFS_TRY(scratch_init(device));
   auto ctx = new mfs_context();
   ctx->device = device;
   if (hip_stream) {

@@ -188,6 +188,11 @@ size_t workspace_layout(const mfs_character* ch);
 // Device bytes of a character with n vertices, m tets, nnzb matrix blocks and
 // np pins: its resident data, and one frame solve's workspace.
 size_t resident_bytes_of(int64_t n, int64_t m, int64_t nnzb, int64_t np);
+
+// The allocation-free evaluation's per-device scratch array: its device
+// address on `device` (which must be current), taken once per process by
+// context creation.
+int scratch_init(int device);
 size_t workspace_bytes_of(int64_t n, int64_t m, int64_t nnzb);
 void bind_workspace(const mfs_character* ch, char* base, SysDesc* d);
 // Re-allocates the character's own workspace after a release.
