@@ -230,7 +230,7 @@ def test_footprint_from_descriptor_matches_created_character(ctx):
     workspace), on meshes from one tet to the 50k-tet humanoid; the device-
     array form of the descriptor gives the same numbers."""
     mfs = _mfs()
-    probs = [tiny_mesh("tet"), tiny_mesh("cube"), beam(), humanoid(21, target_tets=4000, n_bones=15),
+    probs = [tiny_mesh("one"), tiny_mesh("cube"), beam(), humanoid(21, target_tets=4000, n_bones=15),
              humanoid(2001, target_tets=50000, n_bones=20)]
     for prob in probs:
         if "cluster" not in prob and "seg_a" not in prob:
