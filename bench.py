@@ -274,6 +274,8 @@ def frame_bench(args, mfs, torch):
             tuned.append(t)
             _progress(f"class {g}: autotuned PCG schedule {t} ({tms:.1f} ms per 4 Newton iterations)")
         tuned = tuned[0] if K == 1 else tuned
+    for c in ctxs:  # batches: each character's Newton steps on its own (1) or in lockstep (0)
+        c.set_tuning(batch_async=args.batch_async)
     pool = None
     if K > 1:
         from concurrent.futures import ThreadPoolExecutor
@@ -633,6 +635,9 @@ def main():
     ap.add_argument("--roofline-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default PCG schedule")
+    ap.add_argument("--batch-async", type=int, default=1, choices=(0, 1),
+                    help="batches with the two-kernel PCG: each character runs its own Newton steps (1) or "
+                         "all run the same Newton iteration (0)")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file: reuse a choice made for this GPU and size class")
     ap.add_argument("--copy-mb", type=int, default=0,

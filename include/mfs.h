@@ -182,6 +182,15 @@ typedef struct mfs_tuning {
                                  iterates are the same bitwise.  Default 0: it pays off for
                                  small systems, where the launch per iteration dominates
                                  (the autotuner tries it) */
+  int32_t batch_async;        /* 1 (default): a batch (mfs_solve_batch, a server lane) whose
+                                 solves run the two-kernel PCG lets each character run its
+                                 own Newton steps: a character whose PCG solve has stopped
+                                 takes its line search, update and next element pass and
+                                 assembly while the others' solves go on, and every PCG
+                                 launch covers the characters solving at that moment; 0:
+                                 every character of the batch runs the same Newton
+                                 iteration, which waits for the slowest PCG solve.  Results
+                                 are the same bitwise either way */
 } mfs_tuning;
 
 int mfs_context_get_tuning(const mfs_context* ctx, mfs_tuning* out);

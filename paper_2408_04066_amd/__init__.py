@@ -88,7 +88,7 @@ class CharacterInfo(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("pcg_lanes_per_row", c_i32), ("use_graphs", c_i32), ("graph_iterations", c_i32),
                 ("first_check", c_i32), ("min_run", c_i32), ("max_run", c_i32), ("pcg_pipelined", c_i32),
-                ("allread_max_tiles", c_i32), ("pcg_persistent", c_i32)]
+                ("allread_max_tiles", c_i32), ("pcg_persistent", c_i32), ("batch_async", c_i32)]
 
 
 class Profile(ctypes.Structure):

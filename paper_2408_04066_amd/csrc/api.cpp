@@ -217,6 +217,7 @@ extern "C" int mfs_context_get_tuning(const mfs_context* ctx, mfs_tuning* out) {
   out->pcg_pipelined = ctx->pipelined ? 1 : 0;
   out->allread_max_tiles = ctx->allread_tiles;
   out->pcg_persistent = ctx->persistent ? 1 : 0;
+  out->batch_async = ctx->batch_async ? 1 : 0;
   return MFS_OK;
 }
 
@@ -232,6 +233,7 @@ int mfs::check_tuning(const mfs_tuning* t) {
   if (t->allread_max_tiles < 0) return set_error(MFS_E_INVALID, "allread_max_tiles must be >= 0");
   if (t->pcg_persistent != 0 && t->pcg_persistent != 1)
     return set_error(MFS_E_INVALID, "pcg_persistent must be 0 or 1");
+  if (t->batch_async != 0 && t->batch_async != 1) return set_error(MFS_E_INVALID, "batch_async must be 0 or 1");
   return MFS_OK;
 }
 
@@ -252,5 +254,6 @@ extern "C" int mfs_context_set_tuning(mfs_context* ctx, const mfs_tuning* t) {
   ctx->pipelined = t->pcg_pipelined != 0;
   ctx->allread_tiles = t->allread_max_tiles;
   ctx->persistent = t->pcg_persistent != 0;
+  ctx->batch_async = t->batch_async != 0;
   return MFS_OK;
 }

@@ -54,11 +54,23 @@ std::vector<Entry> read_cache(const char* path) {
   if (!path) return out;
   FILE* f = std::fopen(path, "r");
   if (!f) return out;
-  char arch[128];
-  Entry e{};
-  while (std::fscanf(f, "%127s %d %d %d %d %d %d %d %d %d %d %lf", arch, &e.size_class, &e.t.pcg_lanes_per_row,
-                     &e.t.use_graphs, &e.t.graph_iterations, &e.t.first_check, &e.t.min_run, &e.t.max_run,
-                     &e.t.pcg_pipelined, &e.t.allread_max_tiles, &e.t.pcg_persistent, &e.ms) == 12) {
+  char line[512], arch[128];
+  while (std::fgets(line, sizeof line, f)) {
+    Entry e{};
+    e.t.batch_async = 1;
+    double v[12];
+    const int k = std::sscanf(line, "%127s %d %d %d %d %d %d %d %d %d %d %lf %lf", arch, &e.size_class,
+                              &e.t.pcg_lanes_per_row, &e.t.use_graphs, &e.t.graph_iterations, &e.t.first_check,
+                              &e.t.min_run, &e.t.max_run, &e.t.pcg_pipelined, &e.t.allread_max_tiles,
+                              &e.t.pcg_persistent, &v[0], &v[1]);
+    if (k == 12) {  // written before the batch_async field
+      e.ms = v[0];
+    } else if (k == 13) {  // ... batch_async ms
+      e.t.batch_async = (int)v[0];
+      e.ms = v[1];
+    } else {
+      continue;
+    }
     e.arch = arch;
     out.push_back(e);
   }
@@ -71,9 +83,9 @@ int write_cache(const char* path, const std::vector<Entry>& entries) {
   FILE* f = std::fopen(tmp.c_str(), "w");
   if (!f) return set_error(MFS_E_INVALID, "cannot write tuning cache %s", tmp.c_str());
   for (const Entry& e : entries)
-    std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %.6f\n", e.arch.c_str(), e.size_class, e.t.pcg_lanes_per_row,
-                 e.t.use_graphs, e.t.graph_iterations, e.t.first_check, e.t.min_run, e.t.max_run,
-                 e.t.pcg_pipelined, e.t.allread_max_tiles, e.t.pcg_persistent, e.ms);
+    std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d %.6f\n", e.arch.c_str(), e.size_class,
+                 e.t.pcg_lanes_per_row, e.t.use_graphs, e.t.graph_iterations, e.t.first_check, e.t.min_run,
+                 e.t.max_run, e.t.pcg_pipelined, e.t.allread_max_tiles, e.t.pcg_persistent, e.t.batch_async, e.ms);
   std::fclose(f);
   if (std::rename(tmp.c_str(), path) != 0) return set_error(MFS_E_INVALID, "cannot replace tuning cache %s", path);
   return MFS_OK;

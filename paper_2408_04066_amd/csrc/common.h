@@ -80,6 +80,11 @@ struct CgState {
   uint32_t bar;         // persistent form: barrier arrivals of this solve
   int32_t abort;        // persistent form: set when a barrier wait timed out
   int32_t pad1;
+  // two-kernel PCG, all-read mode: r . z of iteration it, as the SpMV kernel
+  // of that iteration folded it (tile 0 stores it in slot it & 1; the update
+  // kernel of iteration it and the SpMV kernel of it + 1 read it instead of
+  // folding the plane again)
+  double rz_par[2];
 };
 
 // Per-system control block, written by the host driver each iteration.

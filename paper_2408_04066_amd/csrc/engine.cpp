@@ -83,6 +83,10 @@ int build_tile_list(mfs_context* ctx, const std::vector<mfs_character*>& by_slot
   size_t total = 0;
   for (int i : ids) total += by_slot[i]->ntv + by_slot[i]->ntt + by_slot[i]->nts;
   ctx->h_tiles.resize(std::max<size_t>(total, 1));
+  // growing a buffer frees the old one: no queued launch may still read it
+  if (std::max<size_t>(total, 1) * sizeof(Tile) > ctx->tiles.bytes ||
+      std::max<size_t>(ids.size(), 1) * sizeof(int32_t) > ctx->sys_ids.bytes)
+    MFS_HIP(hipStreamSynchronize(ctx->stream));
   MFS_TRY(ctx->tiles.reserve(std::max<size_t>(total, 1) * sizeof(Tile)));
   Tile* h = ctx->h_tiles.data();
   size_t pos = 0;
@@ -347,6 +351,16 @@ int Engine::reserve(int n) {
   hd_.assign(n, SysDesc{});
   desc_dirty_ = true;
   tiles_valid_ = false;
+  for (int p = 0; p < 2; ++p) {
+    live_[p].clear();
+    launched_[p] = 0;
+    gen_[p] = -1;
+  }
+  for (hipEvent_t e : queued_) ctx_->sync_events.push_back(e);
+  queued_.clear();
+  spans_.clear();
+  gens_.clear();
+  timed_.clear();
   return MFS_OK;
 }
 
@@ -830,70 +844,79 @@ int Engine::step() {
     for (int i : redo) slot_[i].resolves++;
   }
   MFS_TRY(linesearch(act));
+  MFS_TRY(apply_update(act));
+  for (int i : act) MFS_TRY(finish_newton(i));
+  return MFS_OK;
+}
 
-  // updates
+int Engine::apply_update(const std::vector<int>& act) {
+  mfs_context* ctx = ctx_;
+  Ctrl* hc = ctx->h_ctrl.data();
   for (int i : act) {
     hc[i].alpha = slot_[i].alpha;
     hc[i].update_s = (slot_[i].phase == 0 && slot_[i].alpha > 0.0 && slot_[i].alpha < 1.0) ? 1 : 0;
     hc[i].phase = slot_[i].phase;
   }
   MFS_TRY(tiles_for(act));
-  MFS_TRY(upload_ctrl(ctx, n));
+  MFS_TRY(upload_ctrl(ctx, (int)slot_.size()));
   {
     ProfScope ps(ctx, MFS_K_UPDATE);
-    launch_update(st, dsd, dctrl, ts_.dt, ts_.nt, ts_.dv, ts_.nv);
+    launch_update(ctx->stream, ctx->desc.as<SysDesc>(), ctx->ctrl.as<Ctrl>(), ts_.dt, ts_.nt, ts_.dv, ts_.nv);
   }
   MFS_HIP(hipGetLastError());
+  return MFS_OK;
+}
 
+int Engine::finish_newton(int i) {
+  Ctrl* hc = ctx_->h_ctrl.data();
   const bool loadstep = o_.load_bisections > 0 && !o_.fixed_newton;
-  for (int i : act) {
-    SlotState& S = slot_[i];
-    const bool was_newton = S.phase == 1;
-    S.iters++;
-    S.step = S.alpha * S.step;
-    if (!was_newton) {
-      S.mixed++;
-      S.load_mixed++;
-      S.E_known = false;
-    }
-    const bool stalled = S.alpha == 0.0 || (!was_newton && S.alpha < 1.0 && S.load_mixed > 6);
-    if (stalled && loadstep && S.bisections < o_.load_bisections && S.iters < o_.max_newton) {
-      // back to the last converged pose; approach the target in a shorter step
-      S.bisections++;
-      S.delta *= 0.5;
+  SlotState& S = slot_[i];
+  const bool was_newton = S.phase == 1;
+  S.iters++;
+  S.step = S.alpha * S.step;
+  if (!was_newton) {
+    S.mixed++;
+    S.load_mixed++;
+    S.E_known = false;
+  }
+  const bool stalled = S.alpha == 0.0 || (!was_newton && S.alpha < 1.0 && S.load_mixed > 6);
+  if (stalled && loadstep && S.bisections < o_.load_bisections && S.iters < o_.max_newton) {
+    // back to the last converged pose; approach the target in a shorter step
+    S.bisections++;
+    S.delta *= 0.5;
+    MFS_TRY(restart_load_step(i));
+    MFS_TRY(set_pose(i, S.tau_done + S.delta));
+    return MFS_OK;
+  }
+  if (S.alpha == 0.0) {  // line search failed: keep the iterate
+    S.done = true;
+    S.status = MFS_W_NOT_CONVERGED;
+    return MFS_OK;
+  }
+  if (!was_newton && S.alpha == 1.0) {
+    S.phase = 1;
+    hc[i].cg_g2prev = 0.0;  // forcing restarts at the first Newton-phase step
+    hc[i].cg_eta_min = 0.0;
+  }
+  const bool final_pose = S.tau >= 1.0;
+  const double tol = final_pose ? o_.step_tol : 1e-4;
+  if (o_.fixed_newton) {
+    if (S.iters >= o_.max_newton) S.done = true;
+  } else if (was_newton && S.step <= tol * S.ch->bbox_diag) {
+    if (final_pose) {
+      S.done = true;
+    } else {  // intermediate pose reached: keep it, lengthen the next step
+      MFS_HIP(hipMemcpyAsync(S.ch->xb.p, S.ch->x.p, 3 * sizeof(double) * S.ch->n, hipMemcpyDeviceToDevice,
+                             ctx_->stream));
+      S.tau_done = S.tau;
+      S.delta *= 2.0;
       MFS_TRY(restart_load_step(i));
-      MFS_TRY(set_pose(i, S.tau_done + S.delta));
-      continue;
+      MFS_TRY(set_pose(i, std::min(1.0, S.tau_done + S.delta)));
     }
-    if (S.alpha == 0.0) {  // line search failed: keep the iterate
-      S.done = true;
-      S.status = MFS_W_NOT_CONVERGED;
-      continue;
-    }
-    if (!was_newton && S.alpha == 1.0) {
-      S.phase = 1;
-      hc[i].cg_g2prev = 0.0;  // forcing restarts at the first Newton-phase step
-      hc[i].cg_eta_min = 0.0;
-    }
-    const bool final_pose = S.tau >= 1.0;
-    const double tol = final_pose ? o_.step_tol : 1e-4;
-    if (o_.fixed_newton) {
-      if (S.iters >= o_.max_newton) S.done = true;
-    } else if (was_newton && S.step <= tol * S.ch->bbox_diag) {
-      if (final_pose) {
-        S.done = true;
-      } else {  // intermediate pose reached: keep it, lengthen the next step
-        MFS_HIP(hipMemcpyAsync(S.ch->xb.p, S.ch->x.p, 3 * sizeof(double) * S.ch->n, hipMemcpyDeviceToDevice, st));
-        S.tau_done = S.tau;
-        S.delta *= 2.0;
-        MFS_TRY(restart_load_step(i));
-        MFS_TRY(set_pose(i, std::min(1.0, S.tau_done + S.delta)));
-      }
-    }
-    if (!S.done && S.iters >= o_.max_newton) {
-      S.done = true;
-      S.status = MFS_W_NOT_CONVERGED;
-    }
+  }
+  if (!S.done && S.iters >= o_.max_newton) {
+    S.done = true;
+    S.status = MFS_W_NOT_CONVERGED;
   }
   return MFS_OK;
 }

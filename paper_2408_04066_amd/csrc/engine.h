@@ -34,6 +34,14 @@ struct SlotState {
   std::vector<double> R0, t0, R1, t1, Rc, tc;
   double tau = 1.0, tau_done = 0.0, delta = 1.0;
   int bisections = 0, load_mixed = 0;
+  // asynchronous batch form: where the slot is in its own Newton step, and
+  // its running PCG solve (global iteration index of its first iteration in
+  // its precision's launch sequence, iteration cap, stop-flag epoch, span)
+  int stage = 0;  // Engine::Stage
+  int64_t pcg_base = 0;
+  int pcg_cap = 0;
+  int32_t epoch = 0;
+  int span = -1;
 };
 
 struct TileSet {
@@ -43,6 +51,22 @@ struct TileSet {
   Tile* ds = nullptr;
 };
 
+// Asynchronous batch form: one PCG solve of one slot, [base, end) in its
+// precision's global launch sequence (end < 0 while it runs), with the
+// algorithmic bytes one SpMV launch moves for it.
+struct SolveSpan {
+  int prec;
+  int64_t base, end;
+  double bytes;
+};
+// A timed SpMV launch of the asynchronous form: its global index, precision
+// and the live set (span ids) it covered.
+struct TimedLaunch {
+  int64_t g;
+  int prec;
+  int gen;
+};
+
 int upload_ctrl(mfs_context* ctx, int count);
 // Host-mapped PCG stop flags for `slots` slots (grow-only; zeroed when made).
 int ensure_stop_flags(mfs_context* ctx, int slots);
@@ -50,9 +74,9 @@ int ensure_stop_flags(mfs_context* ctx, int slots);
 int sync_event(mfs_context* ctx, hipEvent_t* out);
 int read_cg(mfs_context* ctx, int count, bool resolve = true);
 int read_red(mfs_context* ctx, int count);
-// Tiles of the listed slots (indices into by_slot), uploaded to the
-// context's tile buffer, plus the slot-id list of the finalize kernel.  The
-// caller has synchronised the stream since the staging buffers were last used.
+// Tiles of the listed slots (indices into by_slot), uploaded in stream order
+// to the context's tile buffer, plus the slot-id list of the finalize kernel
+// (a buffer that must grow is replaced only after the stream drains).
 int build_tile_list(mfs_context* ctx, const std::vector<mfs_character*>& by_slot, const std::vector<int>& ids,
                     TileSet* ts);
 
@@ -74,6 +98,24 @@ class Engine {
   int bind_workspace(int slot, char* base);
   // One Newton iteration for every occupied, unfinished slot.
   int step();
+  // Asynchronous batch form (two-kernel PCG): each slot runs its own Newton
+  // steps.  One call is one scheduling event: slots at the start of a Newton
+  // step get their element pass, assembly and PCG start; PCG chunks run over
+  // every slot then solving, in each precision, until enough of them stop;
+  // stopped FP32 solves that stalled are queued for an FP64 re-solve, and the
+  // others take their line search and update and start their next step (or
+  // finish).  A slot's arithmetic is the same as in step() and as alone; only
+  // which slots share a launch changes.
+  int advance();
+  // advance() applies: the context runs the two-kernel PCG with the
+  // asynchronous batch form enabled.
+  bool async_mode() const;
+  // Some slot is inside an asynchronous Newton step (solving, or waiting for
+  // its FP64 re-solve): advance() must run until none is, even after the
+  // context left the asynchronous form.
+  bool async_pending() const;
+  // The driver's next scheduling call: advance() or step().
+  int run_once() { return (async_mode() || async_pending()) ? advance() : step(); }
   // E(x) for finished slots whose last step did not produce it.
   int finish_energies();
   bool busy(int slot) const { return slot_[slot].used && !slot_[slot].done; }
@@ -90,8 +132,21 @@ class Engine {
   }
   const SlotState& state(int slot) const { return slot_[slot]; }
 
+  enum Stage { kHead = 0, kPcg32 = 1, kPcg64 = 2, kRedo = 3, kTail = 4 };
+
  private:
   int upload_desc();
+  // the end of a Newton step for slot i after its update: counters, stop
+  // test, load stepping; sets done/status
+  int finish_newton(int i);
+  // x (and s in the mixed phase) updated by each listed slot's accepted step
+  int apply_update(const std::vector<int>& act);
+  // asynchronous form
+  int async_head(const std::vector<int>& ids, int prec, bool redo);
+  int async_pcg();
+  int async_enqueue(int prec, int run);
+  void async_attribute();
+  int vertex_tiles(int prec, const std::vector<int>& ids);
   int set_pose(int slot, double tau);
   int restart_load_step(int slot);
   int tiles_for(const std::vector<int>& ids);
@@ -113,6 +168,18 @@ class Engine {
   std::vector<int> tile_ids_;
   std::vector<const mfs_character*> tile_chars_;
   bool tiles_valid_ = false;
+  // asynchronous form: per precision (0 FP64, 1 FP32) the live set, its
+  // vertex tiles, the launches enqueued so far, the queued chunks' completion
+  // events; solve spans and timed launches for the profiler
+  std::vector<int> live_[2];
+  TileSet lts_[2];
+  DevBuf ltiles_[2];
+  int64_t launched_[2] = {0, 0};
+  std::vector<hipEvent_t> queued_;
+  std::vector<SolveSpan> spans_;
+  std::vector<std::vector<int>> gens_;
+  int gen_[2] = {-1, -1};
+  std::vector<TimedLaunch> timed_;
 };
 
 }  // namespace mfs

@@ -190,16 +190,41 @@ __device__ __forceinline__ void share_sums4(const double* a, const double* b, co
   }
 }
 
+// share_sums4 for two planes.
+template <int W>
+__device__ __forceinline__ void share_sums2(const double* a, const double* b, int count, double s[4]) {
+  s[0] = s[1] = s[2] = s[3] = 0.0;
+  for (int i0 = (threadIdx.x & 63) + 64 * (threadIdx.x >> 6); i0 < count; i0 += 256 * W) {
+    double v[2][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + 64 * W * u < count ? i0 + 64 * W * u : i0;
+      v[0][u] = a[i];
+      v[1][u] = b[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (i0 + 64 * W * u < count) {
+        s[0] += v[0][u];
+        s[1] += v[1][u];
+      }
+    }
+  }
+}
+
 // Search direction p_it = z + beta p_{it-1} and q = K p_it: one pass of 64
 // rows, LPR lanes per row; partial p.q.  What the launch reads and no
 // workgroup of it writes (the PCG state, the row's block range, the row's z
-// and both p buffers, the partial sums of the previous launches) is loaded
-// at its head, so those loads overlap.  In all-read mode the LPR waves of a
-// workgroup fold the sums together: wave w adds the tiles of its share in
-// sequence (share_sums4), the shares meet in LDS in wave order and each wave
-// sums the 64 lanes itself.  Every workgroup takes the same order, so all
-// of them reach the same beta and convergence decision; each reads 1/LPR of
-// the partials a wave folding alone would read.
+// and both p buffers, the partial sums of the previous launch) is loaded at
+// its head, so those loads overlap, before a system whose PCG has stopped
+// returns.  In all-read mode the LPR waves of a workgroup fold the sums
+// together: wave w adds the tiles of its share in sequence (share_sums4), the
+// shares meet in LDS in wave order and each wave sums the 64 lanes itself.
+// Every workgroup takes the same order, so all of them reach the same beta
+// and convergence decision.  Only the planes the previous update wrote are
+// folded (r.r and the new r.z; b.b too in the first iteration): b.b and the
+// previous r.z come from the PCG state, where tile 0 of the launch that
+// folded them stored them.
 template <typename T, int LPR, bool ONE>
 __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
                                                       int ntiles, const SysDesc one) {
@@ -214,6 +239,9 @@ __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict_
   const T* z = (const T*)S.z;
   const int rb = valid ? S.rowptr[row] : 0;
   const int re = valid ? S.rowptr[row + 1] : 0;
+  const int stopped = st->done;
+  const int it_t = st->it, it_all = st->it_a;
+  const int it = S.ticket ? it_t : it_all;
   T oz[3] = {0, 0, 0}, op0[3] = {0, 0, 0}, op1[3] = {0, 0, 0};
   // with LPR >= 4, lane i < 3 of the row's group keeps component i of z and
   // both p buffers (entry 0) and writes component i of p and q
@@ -233,40 +261,46 @@ __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict_
       op1[i] = ((const T*)S.p1)[3 * row + i];
     }
   }
-  double ls[4] = {0.0, 0.0, 0.0, 0.0};  // rr, bb, rz0, rz1: this lane's share
-  if (!S.ticket)
-    share_sums4<LPR>(S.part + P_RR * S.ptile, S.part + P_BB * S.ptile, S.part + P_RZ0 * S.ptile,
-                     S.part + P_RZ1 * S.ptile, S.ntv, ls);
-  const int stopped = st->done;
-  const int it_t = st->it, it_all = st->it_a;
-  const double rz_t = st->rz, rzp_t = st->rz_prev;
-  const Ctrl ctrl = *S.ctrl;
-  int it;
   double beta;
+  const Ctrl ctrl = *S.ctrl;
   if (S.ticket) {
+    const double rz_t = st->rz, rzp_t = st->rz_prev;
     if (stopped) return;
-    it = it_t;
     beta = it == 0 ? 0.0 : rz_t / rzp_t;
   } else {
-    it = it_all;
-    __shared__ double share[4][LPR][64];
+    // it = 0: r.r, r.z and b.b from the start kernel; later: r.r and the new
+    // r.z (plane it & 1), with b.b and the previous r.z from the state
+    double ls[4] = {0.0, 0.0, 0.0, 0.0};
+    const double* prr = S.part + P_RR * S.ptile;
+    const double* prz = S.part + (P_RZ0 + (it & 1)) * S.ptile;
+    if (it == 0)
+      share_sums4<LPR>(prr, prz, S.part + P_BB * S.ptile, prr, S.ntv, ls);
+    else
+      share_sums2<LPR>(prr, prz, S.ntv, ls);
+    const double bb_s = st->bb, rzo_s = st->rz_par[(it + 1) & 1];
+    if (stopped) return;  // this system's PCG has stopped
+    __shared__ double share[3][LPR][64];
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const int nf = it == 0 ? 3 : 2;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) share[k][wv][ln] = ls[k];
+    for (int k = 0; k < 3; ++k)
+      if (k < nf) share[k][wv][ln] = ls[k];
     __syncthreads();
-    double f[4];
+    double f[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 3; ++k) {
+      if (k >= nf) continue;
       f[k] = share[k][0][ln];
 #pragma unroll
       for (int j = 1; j < LPR; ++j) f[k] += share[k][j][ln];
       f[k] = wave_sum(f[k]);
     }
-    const double rr = f[0], bb = f[1], rz0 = f[2], rz1 = f[3];
+    const double rr = f[0], rz = f[1], bb = it == 0 ? f[2] : bb_s;
     const bool conv = rr <= pcg_tol2(ctrl, bb) * bb;
     if (t.local == 0 && threadIdx.x == 0) {
       st->rr = rr;
-      st->bb = bb;
+      if (it == 0) st->bb = bb;
+      st->rz_par[it & 1] = rz;
       if (conv && st->done == 0) {
         st->done = 1;
         st->iters = it;
@@ -275,8 +309,7 @@ __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict_
       if (!conv) st->it_b = it;
     }
     if (conv) return;
-    beta = 0.0;
-    if (it > 0) beta = (it & 1 ? rz1 : rz0) / (it & 1 ? rz0 : rz1);
+    beta = it == 0 ? 0.0 : rz / rzo_s;
   }
   const T tb = (T)beta;
   T* pn = (T*)((it & 1) ? S.p1 : S.p0);
@@ -366,9 +399,9 @@ __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict_
 // alpha = r.z / p.q; x += alpha p; r -= alpha q; z = M^-1 r; partials r.z
 // and r.r.  Ticket mode: the last workgroup folds them, advances the
 // iteration and decides convergence with this Newton step's tolerance.  The
-// row's vectors, its preconditioner block, the PCG state and (all-read) the
-// partial sums are loaded at the head, before the convergence flag is
-// tested.
+// row's vectors, its preconditioner block and the PCG state are loaded at
+// the head, before the convergence flag is tested; in all-read mode the
+// workgroup folds p.q and takes r.z from the state.
 template <typename T, bool ONE>
 __global__ __launch_bounds__(64) void k_cg_update(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
                                                   int ntiles, const SysDesc one) {
@@ -396,9 +429,6 @@ __global__ __launch_bounds__(64) void k_cg_update(const SysDesc* __restrict__ sd
 #pragma unroll
     for (int i = 0; i < 6; ++i) mb[i] = ((const T*)S.minv)[6 * row + i];
   }
-  double lpq = 0.0, lz0 = 0.0, lz1 = 0.0;
-  if (!S.ticket)
-    lane_sums3(S.part + P_PQ * S.ptile, S.part + P_RZ0 * S.ptile, S.part + P_RZ1 * S.ptile, S.ntv, lpq, lz0, lz1);
   const int stopped = st->done;
   const int it_t = st->it, it_all = st->it_b;
   const double rz_t = st->rz, pq_t = st->pq;
@@ -410,10 +440,11 @@ __global__ __launch_bounds__(64) void k_cg_update(const SysDesc* __restrict__ sd
     rz_old = rz_t;
     pq = pq_t;
   } else {
+    // p.q from this iteration's SpMV partials; r.z of the iterate as the
+    // SpMV kernel folded it
     it = it_all;
-    pq = wave_sum(lpq);
-    const double rz0 = wave_sum(lz0), rz1 = wave_sum(lz1);
-    rz_old = (it & 1) ? rz1 : rz0;
+    pq = sys_sum(S.part + P_PQ * S.ptile, S.ntv);
+    rz_old = st->rz_par[it & 1];
   }
   const T alpha = (T)(rz_old / pq);
   double rzn = 0.0, rrn = 0.0;

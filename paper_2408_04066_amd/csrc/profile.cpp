@@ -58,8 +58,15 @@ ProfScope::~ProfScope() {
   c->pending.push_back(ProfPending{fam, bytes, a, b, tag});
 }
 
+// Launches whose algorithmic bytes are not known yet (tag >= 0: the PCG
+// solves they served have not all ended) stay pending.
 void prof_resolve(mfs_context* c) {
+  std::vector<ProfPending> keep;
   for (const ProfPending& p : c->pending) {
+    if (p.tag >= 0) {
+      keep.push_back(p);
+      continue;
+    }
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       c->prof_ms[p.fam] += ms;
@@ -69,7 +76,7 @@ void prof_resolve(mfs_context* c) {
     c->ev_pool.push_back(p.a);
     c->ev_pool.push_back(p.b);
   }
-  c->pending.clear();
+  c->pending.swap(keep);
 }
 
 }  // namespace mfs

@@ -263,7 +263,7 @@ void ServerLane::run() {
       slot_steps += occupied;
       ++steps;
     }
-    int rc = eng.step();
+    int rc = eng.run_once();
     if (rc >= 0) rc = complete_finished();
     if (rc < 0) {
       const std::string msg = last_error_text();

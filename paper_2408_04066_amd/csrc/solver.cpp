@@ -74,7 +74,7 @@ int solve_systems(mfs_context* ctx, int count, mfs_character* const* chars, cons
     MFS_TRY(ensure_workspace(chars[i]));
     MFS_TRY(eng.attach(i, chars[i], R[i], t[i]));
   }
-  while (eng.any_busy()) MFS_TRY(eng.step());
+  while (eng.any_busy()) MFS_TRY(eng.run_once());
   if (stats) MFS_TRY(eng.finish_energies());
   mfs_solve_opts o;
   mfs_default_opts(&o);

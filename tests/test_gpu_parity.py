@@ -223,23 +223,54 @@ def test_humanoid_frame(ctx, precision, tol):
 
 
 def test_batch_equals_alone(ctx):
+    """A batch's frames are bitwise those of the same frames solved alone,
+    with the same statistics, whether the batch runs each character's Newton
+    steps on its own (batch_async) or every character through the same
+    Newton iteration; with a small FP32 PCG cap (FP64 re-solves in most
+    Newton steps) the asynchronous batch still equals the solves alone."""
     mfs = _mfs()
     probs = [humanoid(100 + i, target_tets=t, n_bones=b, models=(NH, COROT))
              for i, (t, b) in enumerate([(1500, 8), (3000, 12), (800, 10)])]
     poses = [random_pose(p, 200 + i) for i, p in enumerate(probs)]
     chars = [mfs.Character(ctx, p) for p in probs]
-    alone = []
-    for ch, pose in zip(chars, poses):
-        _say(f"solve alone: n={ch.n}")
-        x, st, rc = ch.solve(*pose, precision=mfs.FP32_REFINED, cg_tol=1e-5, step_tol=1e-9)
-        assert rc == 0
-        alone.append(x)
-    _say("solve batch of 3")
-    xs, sts, rc = mfs.solve_batch(ctx, chars, poses, precision=mfs.FP32_REFINED, cg_tol=1e-5,
-                                  step_tol=1e-9)
-    assert rc == 0
-    for a, b in zip(alone, xs):
-        assert np.array_equal(a, b)
+    keys = ("status", "iterations", "mixed_iterations", "cg_iterations", "halvings", "fp64_resolves")
+    base = ctx.tuning()
+    assert base["pcg_pipelined"] == 0 and base["batch_async"] == 1
+    opts = dict(precision=mfs.FP32_REFINED, cg_tol=1e-5, step_tol=1e-9)
+    try:
+        runs = {}
+        for mode in (1, 0):
+            ctx.set_tuning(batch_async=mode)
+            alone = []
+            for ch, pose in zip(chars, poses):
+                _say(f"batch_async={mode}: solve alone n={ch.n}")
+                x, st, rc = ch.solve(*pose, **opts)
+                assert rc == 0
+                alone.append((x, st))
+            _say(f"batch_async={mode}: solve batch of 3")
+            xs, sts, rc = mfs.solve_batch(ctx, chars, poses, **opts)
+            assert rc == 0
+            runs[mode] = (alone, list(zip(xs, sts)))
+        ref = runs[1][0]
+        for mode in (1, 0):
+            for which in (0, 1):
+                for (xa, sa), (xb, sb) in zip(ref, runs[mode][which]):
+                    assert np.array_equal(xa, xb)
+                    assert all(sa[k] == sb[k] for k in keys), (mode, which, sa, sb)
+        ctx.set_tuning(batch_async=1)
+        capped = dict(opts, fp32_cg_max=30)
+        alone = []
+        for ch, pose in zip(chars, poses):
+            x, st, rc = ch.solve(*pose, **capped)
+            alone.append((x, st))
+        _say(f"FP32 cap 30 alone: {[st for _, st in alone]}")
+        assert any(st["fp64_resolves"] > 0 for _, st in alone)
+        xs, sts, rc = mfs.solve_batch(ctx, chars, poses, **capped)
+        for (xa, sa), xb, sb in zip(alone, xs, sts):
+            assert np.array_equal(xa, xb)
+            assert all(sa[k] == sb[k] for k in keys), (sa, sb)
+    finally:
+        ctx.set_tuning(**base)
     for ch in chars:
         ch.close()
 
