@@ -212,7 +212,7 @@ int workspace_pieces(int64_t n, int64_t m_, int64_t nnzb, size_t* sz) {
   sz[k++] = 12 * sizeof(double) * m;                          // frc
   sz[k++] = n3;                                               // b
   sz[k++] = n3;                                               // dx
-  sz[k++] = 9 * sizeof(double) * (size_t)nnzb;                // vals
+  sz[k++] = (size_t)kBlockRecBytes * (size_t)nnzb;              // vals (block records, either precision)
   sz[k++] = 6 * sizeof(double) * (size_t)n;                   // minv
   for (int v = 0; v < 10; ++v) sz[k++] = n3;                  // r z p0 p1 q xc v0 v1 v2 v3
   sz[k++] = sizeof(double) * P_COUNT * (size_t)partial_tiles(n, m_, nnzb);  // part

@@ -122,6 +122,71 @@ __host__ __device__ inline double pcg_tol2(const Ctrl& C, double bb) {
   return tol2;
 }
 
+// A 3x3 matrix block of the condensed system is stored as one record: its
+// nine values row-major, then its column (block-row index of the gathered
+// vector) as the bits of the tenth word, then zero padding.  FP32: 12 floats
+// (48 bytes, read as two 16-byte loads and one 8-byte load); FP64: 10 doubles
+// (80 bytes, five 16-byte loads).  A lane reads a whole block, column included, in a few wide loads
+// instead of ten single-word loads from ten arrays.
+template <typename T>
+struct BlockRec;
+template <>
+struct BlockRec<float> {
+  static constexpr int kWords = 12;
+};
+template <>
+struct BlockRec<double> {
+  static constexpr int kWords = 10;
+};
+constexpr int kBlockRecBytes = 80;  // the larger record: a workspace holds either precision
+
+__device__ __forceinline__ void load_block(const float* __restrict__ recs, size_t slot, float a[9], int& col) {
+  const float4* p = reinterpret_cast<const float4*>(recs + 12 * slot);
+  const float4 r0 = p[0], r1 = p[1];
+  const float2 r2 = *reinterpret_cast<const float2*>(recs + 12 * slot + 8);  // the padding is not read
+  a[0] = r0.x;
+  a[1] = r0.y;
+  a[2] = r0.z;
+  a[3] = r0.w;
+  a[4] = r1.x;
+  a[5] = r1.y;
+  a[6] = r1.z;
+  a[7] = r1.w;
+  a[8] = r2.x;
+  col = __float_as_int(r2.y);
+}
+
+__device__ __forceinline__ void load_block(const double* __restrict__ recs, size_t slot, double a[9], int& col) {
+  const double2* p = reinterpret_cast<const double2*>(recs + 10 * slot);
+  const double2 r0 = p[0], r1 = p[1], r2 = p[2], r3 = p[3], r4 = p[4];
+  a[0] = r0.x;
+  a[1] = r0.y;
+  a[2] = r1.x;
+  a[3] = r1.y;
+  a[4] = r2.x;
+  a[5] = r2.y;
+  a[6] = r3.x;
+  a[7] = r3.y;
+  a[8] = r4.x;
+  col = (int)__double_as_longlong(r4.y);
+}
+
+__device__ __forceinline__ void store_block(float* recs, size_t slot, const double v[9], int col) {
+  float4* p = reinterpret_cast<float4*>(recs + 12 * slot);
+  p[0] = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+  p[1] = make_float4((float)v[4], (float)v[5], (float)v[6], (float)v[7]);
+  p[2] = make_float4((float)v[8], __int_as_float(col), 0.0f, 0.0f);
+}
+
+__device__ __forceinline__ void store_block(double* recs, size_t slot, const double v[9], int col) {
+  double2* p = reinterpret_cast<double2*>(recs + 10 * slot);
+  p[0] = make_double2(v[0], v[1]);
+  p[1] = make_double2(v[2], v[3]);
+  p[2] = make_double2(v[4], v[5]);
+  p[3] = make_double2(v[6], v[7]);
+  p[4] = make_double2(v[8], __longlong_as_double((long long)col));
+}
+
 struct Tile {
   int32_t sys;     // system (descriptor) index
   int32_t begin;   // first vertex / tet / slot
@@ -162,7 +227,7 @@ struct SysDesc {
   double* b;     // 3n right-hand side (-grad)
   double* dx;    // 3n step (double)
   // state (precision T of the linear solve)
-  void* vals;    // 9 planes of nnzb
+  void* vals;    // nnzb block records (BlockRec<T>: nine values and the column)
   void* minv;    // 6 n: inverse diagonal blocks (symmetric)
   void* r;
   void* z;

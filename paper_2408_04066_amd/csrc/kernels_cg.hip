@@ -98,14 +98,14 @@ __global__ __launch_bounds__(64) void k_cg_init(const SysDesc* __restrict__ sd, 
         return isfinite(v) ? v : 0.0;
       };
       const T* vals = (const T*)S.vals;
-      const size_t nz = S.nnzb;
       for (int blk = S.rowptr[row]; blk < S.rowptr[row + 1]; ++blk) {
-        const int c = S.colidx[blk];
+        T a[9];
+        int c;
+        load_block(vals, blk, a, c);
         const double g[3] = {start(3 * c), start(3 * c + 1), start(3 * c + 2)};
 #pragma unroll
         for (int i = 0; i < 3; ++i)
-          kx[i] += (double)vals[(3 * i) * nz + blk] * g[0] + (double)vals[(3 * i + 1) * nz + blk] * g[1] +
-                   (double)vals[(3 * i + 2) * nz + blk] * g[2];
+          kx[i] += (double)a[3 * i] * g[0] + (double)a[3 * i + 1] * g[1] + (double)a[3 * i + 2] * g[2];
       }
 #pragma unroll
       for (int i = 0; i < 3; ++i) x0[i] = start(3 * row + i);
@@ -226,7 +226,7 @@ __device__ __forceinline__ void share_sums2(const double* a, const double* b, in
 // previous r.z come from the PCG state, where tile 0 of the launch that
 // folded them stored them.
 template <typename T, int LPR, bool ONE>
-__global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
+__global__ __launch_bounds__(64 * LPR, sizeof(T) == 4 && LPR >= 4 ? 6 : 1) void k_cg_spmv(const SysDesc* __restrict__ sd, const Tile* __restrict__ tiles,
                                                       int ntiles, const SysDesc one) {
   __shared__ double red[LPR];
   __shared__ int last;
@@ -316,7 +316,6 @@ __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict_
   const T* po = (const T*)((it & 1) ? S.p0 : S.p1);
   const T* vals = (const T*)S.vals;
   T* q = (T*)S.q;
-  const size_t nz = S.nnzb;
   T a0 = 0, a1 = 0, a2 = 0;
   {
     // batches of U blocks per lane: indices and values first, then the
@@ -329,10 +328,7 @@ __global__ __launch_bounds__(64 * LPR) void k_cg_spmv(const SysDesc* __restrict_
 #pragma unroll
       for (int u = 0; u < U; ++u) {  // past the row's end: reload its last block, weight 0
         const int sl = base + u * LPR;
-        const int sc = sl < e ? sl : e - 1;
-        c[u] = S.colidx[sc];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) a[u][k] = vals[k * nz + sc];
+        load_block(vals, sl < e ? sl : e - 1, a[u], c[u]);
       }
 
       T g[U][3];
@@ -527,7 +523,6 @@ __device__ __forceinline__ void row_range_product(const SysDesc& S, const V* __r
   acc[0] = acc[1] = acc[2] = (V)0;
   {
     const T* vals = (const T*)S.vals;
-    const size_t nz = S.nnzb;
     const int e = re;
     for (int base = rb + lane; base < e; base += U * LPR) {
       int c[U];
@@ -535,10 +530,7 @@ __device__ __forceinline__ void row_range_product(const SysDesc& S, const V* __r
 #pragma unroll
       for (int u = 0; u < U; ++u) {  // past the row's end: reload its last block, weight 0
         const int sl = base + u * LPR;
-        const int sc = sl < e ? sl : e - 1;
-        c[u] = S.colidx[sc];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) a[u][k] = vals[k * nz + sc];
+        load_block(vals, sl < e ? sl : e - 1, a[u], c[u]);
       }
 
       V g[U][3];
@@ -994,12 +986,12 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_persist(const SysDesc* __restr
   T* lval = (T*)((unsigned char*)lcol + ((size_t)nbt * 4 + 15) / 16 * 16);
   {
     const T* vals = (const T*)S.vals;
-    const size_t nz = S.nnzb;
     for (int i = threadIdx.x; i <= rows; i += blockDim.x) lrow[i] = S.rowptr[t.begin + i] - base;
     for (int i = threadIdx.x; i < nbt; i += blockDim.x) {
-      lcol[i] = S.colidx[base + i];
+      T a[9];
+      load_block(vals, base + i, a, lcol[i]);
 #pragma unroll
-      for (int k = 0; k < 9; ++k) lval[k * nbt + i] = vals[k * nz + base + i];
+      for (int k = 0; k < 9; ++k) lval[k * nbt + i] = a[k];
     }
   }
   const int lane = threadIdx.x % LPR;
@@ -1220,19 +1212,22 @@ __global__ __launch_bounds__(64) void k_cg_finish(const SysDesc* __restrict__ sd
   for (int i = 0; i < 3; ++i) S.dx[3 * row + i] = (double)xc[3 * row + i];
 }
 
-// y = K v for one system (FP64 values and vectors), one thread per block row.
-__global__ __launch_bounds__(kBlock) void k_spmv_plain(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
-                                                       const double* __restrict__ vals, int nnzb, int n,
+// y = K v for one system (FP64 block records and vectors), one thread per
+// block row.
+__global__ __launch_bounds__(kBlock) void k_spmv_plain(const int32_t* __restrict__ rowptr,
+                                                       const double* __restrict__ vals, int n,
                                                        const double* __restrict__ v, double* __restrict__ y) {
   const int row = blockIdx.x * kBlock + threadIdx.x;
   if (row >= n) return;
   double a[3] = {0, 0, 0};
   for (int sl = rowptr[row]; sl < rowptr[row + 1]; ++sl) {
-    const int c = colidx[sl];
+    double b[9];
+    int c;
+    load_block(vals, sl, b, c);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) a[i] += vals[(size_t)(3 * i + j) * nnzb + sl] * v[3 * c + j];
+      for (int j = 0; j < 3; ++j) a[i] += b[3 * i + j] * v[3 * c + j];
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i) y[3 * row + i] = a[i];
@@ -1405,10 +1400,9 @@ void launch_cg_finish(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv
     MFS_LAUNCH(k_cg_finish<double>, dim3(ntv), dim3(64), 0, st, sd, tv, ntv);
 }
 
-void launch_spmv_plain(hipStream_t st, const int32_t* rowptr, const int32_t* colidx, const double* vals, int nnzb,
-                       int n, const double* v, double* y) {
-  MFS_LAUNCH(k_spmv_plain, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, rowptr, colidx, vals, nnzb,
-                     n, v, y);
+void launch_spmv_plain(hipStream_t st, const int32_t* rowptr, const double* vals, int n, const double* v,
+                       double* y) {
+  MFS_LAUNCH(k_spmv_plain, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, rowptr, vals, n, v, y);
 }
 
 }  // namespace mfs

@@ -244,9 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(const SysDesc* __restrict__
 #pragma unroll
     for (int i = 0; i < 6; ++i) mi[6 * row + i] = (T)inv[i];
   }
-  T* vals = (T*)S.vals;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) vals[(size_t)i * S.nnzb + slot] = (T)acc[i];
+  store_block((T*)S.vals, slot, acc, S.colidx[slot]);
 }
 
 // ---------------------------------------------------------------------------

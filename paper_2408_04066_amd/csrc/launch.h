@@ -88,7 +88,7 @@ size_t pcg_persist_lds(int max_tile_blocks);
 int pcg_persist_capacity(int lpr, size_t lds_bytes);
 hipError_t launch_pcg_persist(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int lpr, size_t lds_bytes);
 void launch_cg_finish(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32);
-void launch_spmv_plain(hipStream_t st, const int32_t* rowptr, const int32_t* colidx, const double* vals, int nnzb,
-                       int n, const double* v, double* y);
+// y = K v for one system with FP64 block records (v, y: 3n in the internal order)
+void launch_spmv_plain(hipStream_t st, const int32_t* rowptr, const double* vals, int n, const double* v, double* y);
 
 }  // namespace mfs

@@ -176,8 +176,8 @@ extern "C" int mfs_evaluate(mfs_character* ch, const double* handle_R, const dou
       vs = tmp;
     }
     launch_gather_rows(st, vs, ch->perm_d.as<int32_t>(), ch->n, 3, static_cast<double*>(ch->desc.p0));
-    launch_spmv_plain(st, ch->rowptr.as<int32_t>(), ch->colidx.as<int32_t>(), static_cast<const double*>(ch->desc.vals), ch->nnzb,
-                      ch->n, static_cast<const double*>(ch->desc.p0), static_cast<double*>(ch->desc.q));
+    launch_spmv_plain(st, ch->rowptr.as<int32_t>(), static_cast<const double*>(ch->desc.vals), ch->n,
+                      static_cast<const double*>(ch->desc.p0), static_cast<double*>(ch->desc.q));
     double* dst = host ? tmp : Kv_out;
     launch_scatter_rows(st, static_cast<const double*>(ch->desc.q), ch->perm_d.as<int32_t>(), ch->n, 3, 1.0, dst);
     if (host) MFS_HIP(hipMemcpyAsync(Kv_out, tmp, n3, hipMemcpyDeviceToHost, st));
