@@ -122,6 +122,26 @@ __host__ __device__ inline double pcg_tol2(const Ctrl& C, double bb) {
   return tol2;
 }
 
+// Global-memory views of the generic pointers the descriptors carry: loads
+// and stores through them compile to global_* instructions (a scalar base
+// plus a 32-bit lane offset where the base is uniform) instead of flat_*
+// ones, which also test the LDS and scratch apertures and wait on both
+// memory counters.  Every buffer of the solver is device memory.
+// (Host compilation, which never runs these functions, keeps plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define MFS_GLOBAL __attribute__((address_space(1)))
+#else
+#define MFS_GLOBAL
+#endif
+template <typename T>
+__device__ __forceinline__ const MFS_GLOBAL T* gld(const T* p) {
+  return (const MFS_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ MFS_GLOBAL T* gst(T* p) {
+  return (MFS_GLOBAL T*)p;
+}
+
 // A 3x3 matrix block of the condensed system is stored as one record: its
 // nine values row-major, then its column (block-row index of the gathered
 // vector) as the bits of the tenth word, then zero padding.  FP32: 12 floats
@@ -141,9 +161,9 @@ struct BlockRec<double> {
 constexpr int kBlockRecBytes = 80;  // the larger record: a workspace holds either precision
 
 __device__ __forceinline__ void load_block(const float* __restrict__ recs, size_t slot, float a[9], int& col) {
-  const float4* p = reinterpret_cast<const float4*>(recs + 12 * slot);
+  const MFS_GLOBAL float4* p = (const MFS_GLOBAL float4*)(recs + 12 * slot);
   const float4 r0 = p[0], r1 = p[1];
-  const float2 r2 = *reinterpret_cast<const float2*>(recs + 12 * slot + 8);  // the padding is not read
+  const float2 r2 = *(const MFS_GLOBAL float2*)(recs + 12 * slot + 8);  // the padding is not read
   a[0] = r0.x;
   a[1] = r0.y;
   a[2] = r0.z;
@@ -157,7 +177,7 @@ __device__ __forceinline__ void load_block(const float* __restrict__ recs, size_
 }
 
 __device__ __forceinline__ void load_block(const double* __restrict__ recs, size_t slot, double a[9], int& col) {
-  const double2* p = reinterpret_cast<const double2*>(recs + 10 * slot);
+  const MFS_GLOBAL double2* p = (const MFS_GLOBAL double2*)(recs + 10 * slot);
   const double2 r0 = p[0], r1 = p[1], r2 = p[2], r3 = p[3], r4 = p[4];
   a[0] = r0.x;
   a[1] = r0.y;
@@ -172,19 +192,40 @@ __device__ __forceinline__ void load_block(const double* __restrict__ recs, size
 }
 
 __device__ __forceinline__ void store_block(float* recs, size_t slot, const double v[9], int col) {
-  float4* p = reinterpret_cast<float4*>(recs + 12 * slot);
+  MFS_GLOBAL float4* p = (MFS_GLOBAL float4*)(recs + 12 * slot);
   p[0] = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
   p[1] = make_float4((float)v[4], (float)v[5], (float)v[6], (float)v[7]);
   p[2] = make_float4((float)v[8], __int_as_float(col), 0.0f, 0.0f);
 }
 
 __device__ __forceinline__ void store_block(double* recs, size_t slot, const double v[9], int col) {
-  double2* p = reinterpret_cast<double2*>(recs + 10 * slot);
+  MFS_GLOBAL double2* p = (MFS_GLOBAL double2*)(recs + 10 * slot);
   p[0] = make_double2(v[0], v[1]);
   p[1] = make_double2(v[2], v[3]);
   p[2] = make_double2(v[4], v[5]);
   p[3] = make_double2(v[6], v[7]);
   p[4] = make_double2(v[8], __longlong_as_double((long long)col));
+}
+
+// The three components of block row `row` of a 3n vector, gathered (or
+// stored) as one triple: one 12-byte access for FP32, a 16-byte and an 8-byte
+// one for FP64, instead of three single-word accesses.
+template <typename T>
+struct Triple {
+  T x, y, z;
+};
+template <typename T>
+__device__ __forceinline__ Triple<T> gather3(const T* __restrict__ v, int row) {
+  const MFS_GLOBAL T* p = gld(v) + 3 * (size_t)row;
+  return Triple<T>{p[0], p[1], p[2]};
+}
+
+template <typename T>
+__device__ __forceinline__ void scatter3(T* __restrict__ v, int row, T x, T y, T z) {
+  MFS_GLOBAL T* p = gst(v) + 3 * (size_t)row;
+  p[0] = x;
+  p[1] = y;
+  p[2] = z;
 }
 
 struct Tile {
@@ -383,7 +424,7 @@ __device__ __forceinline__ double sys_sum(const double* plane, int count) {
   for (int i0 = threadIdx.x & 63; i0 < count; i0 += 256) {
     double v[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = plane[i0 + 64 * u < count ? i0 + 64 * u : i0];
+    for (int u = 0; u < 4; ++u) v[u] = gld(plane)[i0 + 64 * u < count ? i0 + 64 * u : i0];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       if (i0 + 64 * u < count) acc += v[u];

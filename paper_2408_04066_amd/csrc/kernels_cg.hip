@@ -175,10 +175,10 @@ __device__ __forceinline__ void share_sums4(const double* a, const double* b, co
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int i = i0 + 64 * W * u < count ? i0 + 64 * W * u : i0;
-      v[0][u] = a[i];
-      v[1][u] = b[i];
-      v[2][u] = c[i];
-      v[3][u] = d[i];
+      v[0][u] = gld(a)[i];
+      v[1][u] = gld(b)[i];
+      v[2][u] = gld(c)[i];
+      v[3][u] = gld(d)[i];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -199,8 +199,8 @@ __device__ __forceinline__ void share_sums2(const double* a, const double* b, in
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int i = i0 + 64 * W * u < count ? i0 + 64 * W * u : i0;
-      v[0][u] = a[i];
-      v[1][u] = b[i];
+      v[0][u] = gld(a)[i];
+      v[1][u] = gld(b)[i];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -237,8 +237,8 @@ __global__ __launch_bounds__(64 * LPR, sizeof(T) == 4 && LPR >= 4 ? 6 : 1) void 
   const int row = t.begin + threadIdx.x / LPR;
   const bool valid = row < t.end;
   const T* z = (const T*)S.z;
-  const int rb = valid ? S.rowptr[row] : 0;
-  const int re = valid ? S.rowptr[row + 1] : 0;
+  const int rb = valid ? gld(S.rowptr)[row] : 0;
+  const int re = valid ? gld(S.rowptr)[row + 1] : 0;
   const int stopped = st->done;
   const int it_t = st->it, it_all = st->it_a;
   const int it = S.ticket ? it_t : it_all;
@@ -249,9 +249,9 @@ __global__ __launch_bounds__(64 * LPR, sizeof(T) == 4 && LPR >= 4 ? 6 : 1) void 
   const bool comp = valid && lane < 3;
   if (CL) {
     if (comp) {
-      oz[0] = z[3 * row + lane];
-      op0[0] = ((const T*)S.p0)[3 * row + lane];
-      op1[0] = ((const T*)S.p1)[3 * row + lane];
+      oz[0] = gld(z)[3 * row + lane];
+      op0[0] = gld((const T*)S.p0)[3 * row + lane];
+      op1[0] = gld((const T*)S.p1)[3 * row + lane];
     }
   } else if (valid && lane == 0) {
 #pragma unroll
@@ -334,13 +334,15 @@ __global__ __launch_bounds__(64 * LPR, sizeof(T) == 4 && LPR >= 4 ? 6 : 1) void 
       T g[U][3];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        g[u][0] = z[3 * c[u]];
-        g[u][1] = z[3 * c[u] + 1];
-        g[u][2] = z[3 * c[u] + 2];
+        const Triple<T> zc = gather3(z, c[u]);
+        g[u][0] = zc.x;
+        g[u][1] = zc.y;
+        g[u][2] = zc.z;
         if (it) {
-          g[u][0] += tb * po[3 * c[u]];
-          g[u][1] += tb * po[3 * c[u] + 1];
-          g[u][2] += tb * po[3 * c[u] + 2];
+          const Triple<T> pc = gather3(po, c[u]);
+          g[u][0] += tb * pc.x;
+          g[u][1] += tb * pc.y;
+          g[u][2] += tb * pc.z;
         }
       }
 #pragma unroll
@@ -361,8 +363,8 @@ __global__ __launch_bounds__(64 * LPR, sizeof(T) == 4 && LPR >= 4 ? 6 : 1) void 
       T p = oz[0];
       if (it) p += tb * ((it & 1) ? op0[0] : op1[0]);
       const T qv = lane == 0 ? a0 : (lane == 1 ? a1 : a2);
-      pn[3 * row + lane] = p;
-      q[3 * row + lane] = qv;
+      gst(pn)[3 * row + lane] = p;
+      gst(q)[3 * row + lane] = qv;
       dot = (double)p * (double)qv;
     }
   } else if (valid && lane == 0) {
@@ -414,16 +416,14 @@ __global__ __launch_bounds__(64) void k_cg_update(const SysDesc* __restrict__ sd
   T oq[3] = {0, 0, 0}, orr[3] = {0, 0, 0}, ox[3] = {0, 0, 0}, op0[3] = {0, 0, 0}, op1[3] = {0, 0, 0};
   T mb[6] = {0, 0, 0, 0, 0, 0};
   if (valid) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      oq[i] = q[3 * row + i];
-      orr[i] = r[3 * row + i];
-      ox[i] = xc[3 * row + i];
-      op0[i] = ((const T*)S.p0)[3 * row + i];
-      op1[i] = ((const T*)S.p1)[3 * row + i];
-    }
-#pragma unroll
-    for (int i = 0; i < 6; ++i) mb[i] = ((const T*)S.minv)[6 * row + i];
+    const Triple<T> tq = gather3(q, row), tr = gather3((const T*)r, row), tx = gather3((const T*)xc, row);
+    const Triple<T> t0 = gather3((const T*)S.p0, row), t1 = gather3((const T*)S.p1, row);
+    oq[0] = tq.x, oq[1] = tq.y, oq[2] = tq.z;
+    orr[0] = tr.x, orr[1] = tr.y, orr[2] = tr.z;
+    ox[0] = tx.x, ox[1] = tx.y, ox[2] = tx.z;
+    op0[0] = t0.x, op0[1] = t0.y, op0[2] = t0.z;
+    op1[0] = t1.x, op1[1] = t1.y, op1[2] = t1.z;
+    __builtin_memcpy(mb, (const T*)S.minv + 6 * (size_t)row, sizeof mb);
   }
   const int stopped = st->done;
   const int it_t = st->it, it_all = st->it_b;
@@ -446,17 +446,18 @@ __global__ __launch_bounds__(64) void k_cg_update(const SysDesc* __restrict__ sd
   double rzn = 0.0, rrn = 0.0;
   if (valid) {
     const T* pn = (it & 1) ? op1 : op0;
-    T rv[3], zv[3];
+    T rv[3], zv[3], xv[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      xc[3 * row + i] = ox[i] + alpha * pn[i];
+      xv[i] = ox[i] + alpha * pn[i];
       rv[i] = orr[i] - alpha * oq[i];
-      r[3 * row + i] = rv[i];
     }
+    scatter3(xc, row, xv[0], xv[1], xv[2]);
+    scatter3(r, row, rv[0], rv[1], rv[2]);
     precondition(mb, rv, zv);
+    scatter3(z, row, zv[0], zv[1], zv[2]);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      z[3 * row + i] = zv[i];
       rzn += (double)rv[i] * (double)zv[i];
       rrn += (double)rv[i] * (double)rv[i];
     }
@@ -536,9 +537,10 @@ __device__ __forceinline__ void row_range_product(const SysDesc& S, const V* __r
       V g[U][3];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        g[u][0] = v[3 * c[u]];
-        g[u][1] = v[3 * c[u] + 1];
-        g[u][2] = v[3 * c[u] + 2];
+        const Triple<V> vc = gather3(v, c[u]);
+        g[u][0] = vc.x;
+        g[u][1] = vc.y;
+        g[u][2] = vc.z;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {  // weight 1 (exact) or 0 for slots past the row's end
