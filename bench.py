@@ -261,7 +261,7 @@ def frame_bench(args, mfs, torch):
         stress_out = [(torch.empty((i["n_tets"], 6), dtype=torch.float64, device="cuda"),
                        torch.empty((i["n_tets"], 3, 3), dtype=torch.float64, device="cuda")) for i in infos]
     outs = [torch.empty((i["n_vertices"], 3), dtype=torch.float64, device="cuda") for i in infos]
-    steps = [pose_of(i) for i in range(args.warmup + args.steps + max(args.roofline_steps, args.fp64_steps))]
+    steps = [pose_of(i) for i in range(args.warmup + args.steps + args.fp64_steps)]
     fp64_opts = dict(opts, precision=mfs.FP64)
     warm = opts.get("warm_start", 0) == mfs.WARM_PREVIOUS
     _progress(f"{wname}: {len(chars)} characters resident, {m_tot} tets")
@@ -274,8 +274,11 @@ def frame_bench(args, mfs, torch):
             tuned.append(t)
             _progress(f"class {g}: autotuned PCG schedule {t} ({tms:.1f} ms per 4 Newton iterations)")
         tuned = tuned[0] if K == 1 else tuned
+    fixed = dict(kv.split("=") for kv in args.tuning.split(",")) if args.tuning else {}
     for c in ctxs:  # batches: each character's Newton steps on its own (1) or in lockstep (0)
-        c.set_tuning(batch_async=args.batch_async)
+        c.set_tuning(batch_async=args.batch_async, **{k: int(v) for k, v in fixed.items()})
+    if fixed:
+        tuned = ctxs[0].tuning() if K == 1 else [c.tuning() for c in ctxs]
     pool = None
     if K > 1:
         from concurrent.futures import ThreadPoolExecutor
@@ -311,7 +314,13 @@ def frame_bench(args, mfs, torch):
     torch.cuda.synchronize()
     _progress("warmup done")
 
-    # ---- timed region ----
+    # ---- timed region: the library's profiler times every stride-th launch
+    # of each kernel family with a HIP event pair carried in the launch's own
+    # dispatches (on the library's stream), so the roofline figures below are
+    # those of the timed launches ----
+    for c in ctxs:
+        c.profile_enable(args.profile_stride)
+        c.profile_read(reset=True)
     lat, rcs, per_frame = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -323,6 +332,11 @@ def frame_bench(args, mfs, torch):
         per_frame += [(i, j, st) for j, st in enumerate(sts)]
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
+    prof = {}
+    for c in ctxs:
+        for fam, v in c.profile_read(reset=True).items():
+            prof[fam] = tuple(a + b for a, b in zip(prof.get(fam, (0.0, 0, 0, 0.0)), v))
+        c.profile_enable(0)
     _progress(f"timed {args.steps} steps in {total:.2f} s")
     # a frame counts when it converged (status 0); a frame stopped by the
     # Newton cap (or a failed line search) is not a solution at 1e-7
@@ -335,21 +349,6 @@ def frame_bench(args, mfs, torch):
                    for i, j, st in per_frame if st["status"] != 0]
     conv_iters = [st["iterations"] for _, _, st in per_frame if st["status"] == 0]
 
-    # ---- roofline pass: frames of the same kind (the next poses of the
-    # sequence), kernels launched directly, every stride-th launch of each
-    # family timed by HIP events carried in its dispatches ----
-    nxt = args.warmup + args.steps
-    for c in ctxs:
-        c.profile_enable(args.profile_stride)
-        c.profile_read(reset=True)
-    for i in range(args.roofline_steps):
-        frame(steps[nxt + i], opts)
-    prof = {}
-    for c in ctxs:
-        for fam, v in c.profile_read(reset=True).items():
-            prof[fam] = tuple(a + b for a, b in zip(prof.get(fam, (0.0, 0, 0, 0.0)), v))
-        c.profile_enable(0)
-    _progress("roofline pass done")
 
     # ---- FP32 + refinement against the FP64 form of the same solve, both
     # from the rest shape, and both against a tight FP64 solve (Newton step
@@ -357,6 +356,7 @@ def frame_bench(args, mfs, torch):
     # forms stop on the same step test, which a slowly converging frame can
     # pass far from its solution, so their difference alone does not say
     # which of them is off ----
+    nxt = args.warmup + args.steps
     lat64, tet_iters64, err, err32, err64 = [], 0, [], [], []
     rest_opts = dict(opts, warm_start=mfs.WARM_REST)
     tight_opts = dict(fp64_opts, warm_start=mfs.WARM_REST, step_tol=1e-12, cg_tol=1e-10, cg_adaptive=0,
@@ -391,10 +391,14 @@ def frame_bench(args, mfs, torch):
             if st32["status"] == 0 and st64["status"] == 0:
                 err.append(d(x32[j], x64[j]))
             if tight_opts is not None and st_t[j]["status"] == 0:
+                def entry(x, st):
+                    return (d(x, xt[j]), {"step": i, "member": j, "newton": st["iterations"],
+                                          "tight_newton": st_t[j]["iterations"],
+                                          "last_step_bbox": st["last_step"] / inf["bbox_diag"]})
                 if st32["status"] == 0:
-                    err32.append(d(x32[j], xt[j]))
+                    err32.append(entry(x32[j], st32))
                 if st64["status"] == 0:
-                    err64.append(d(x64[j], xt[j]))
+                    err64.append(entry(x64[j], st64))
 
     spmv_ms, spmv_timed, spmv_launches, spmv_bytes = prof["spmv"]
     achieved = spmv_bytes / (spmv_ms * 1e-3) / 1e9 if spmv_ms > 0 else None
@@ -437,9 +441,11 @@ def frame_bench(args, mfs, torch):
             "frames_per_s": nchar * len(lat64) / sum(lat64) if lat64 else None,
             "tet_newton_iter_per_s": tet_iters64 / sum(lat64) if lat64 else None,
             "max_rel_diff_fp32_vs_fp64": (max(err) if err else None) if opts["precision"] else None,
-            "max_rel_err_vs_tight_fp64": {"fp32_refined": max(err32) if err32 else None,
-                                          "fp64": max(err64) if err64 else None,
-                                          "frames_compared": len(err32)},
+            "max_rel_err_vs_tight_fp64": {"fp32_refined": max(e[0] for e in err32) if err32 else None,
+                                          "fp64": max(e[0] for e in err64) if err64 else None,
+                                          "frames_compared": len(err32),
+                                          "worst_fp32_refined": max(err32, key=lambda e: e[0])[1] if err32 else None,
+                                          "worst_fp64": max(err64, key=lambda e: e[0])[1] if err64 else None},
         },
         "config": {"workload": wname, "characters": nchar, "tets": m_tot,
                    "vertices": sum(i["n_vertices"] for i in infos),
@@ -632,9 +638,11 @@ def main():
                          "iterations per character (no timed run)")
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--profile-stride", type=int, default=8)
-    ap.add_argument("--roofline-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default PCG schedule")
+    ap.add_argument("--tuning", default="",
+                    help="PCG schedule fields set after autotuning, KEY=VALUE,... (mfs_tuning names), e.g. "
+                         "with --no-autotune to run a stated schedule")
     ap.add_argument("--batch-async", type=int, default=1, choices=(0, 1),
                     help="batches with the two-kernel PCG: each character runs its own Newton steps (1) or "
                          "all run the same Newton iteration (0)")

@@ -311,6 +311,7 @@ int Engine::restart_load_step(int i) {
   S.phase = 0;
   S.fresh = true;
   S.load_mixed = 0;
+  S.newton_prev = 0.0;
   S.E_known = false;
   Ctrl& c = ctx_->h_ctrl.data()[i];
   c.cg_g2prev = 0.0;
@@ -595,6 +596,7 @@ int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* fai
   while (!queued.empty()) {
     if (cit < max_cap && queued.size() < 2) MFS_TRY(enqueue(std::min(steady, max_cap - cit)));
     bool all = false, shrink = false, front_done = false;
+    PollPacer pacer;
     for (;;) {
       all = true;
       int stopped_tiles = 0;
@@ -609,6 +611,9 @@ int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* fai
       if (e != hipSuccess && e != hipErrorNotReady) return set_error(MFS_E_HIP, "PCG chunk: %s", hipGetErrorString(e));
       front_done = e == hipSuccess;
       if (all || shrink || front_done) break;
+      if (!pacer.pace())
+        return set_error(MFS_E_HIP, "PCG chunk: no stop flag and no completed chunk in %d s",
+                         PollPacer::kLimitSeconds);
     }
     if (all) break;
     if (front_done) {
@@ -900,9 +905,25 @@ int Engine::finish_newton(int i) {
   }
   const bool final_pose = S.tau >= 1.0;
   const double tol = final_pose ? o_.step_tol : 1e-4;
+  // Step test.  Near a solution where clamped element Hessians remain, Newton
+  // converges only linearly, at the rate rho of successive full steps; the
+  // distance left is then about step * rho / (1 - rho), which exceeds the
+  // step once rho > 1/2, so the step must be that much shorter.  Steps below
+  // 1/20 of the tolerance pass whatever their ratio (rounding-level steps).
+  // Intermediate poses of load stepping keep the plain test.
+  double need = tol * S.ch->bbox_diag;
+  const bool full = was_newton && S.alpha == 1.0;
+  if (final_pose && full && S.newton_prev > 0.0 && S.step > 0.05 * need) {
+    const double rho = S.step / S.newton_prev;
+    if (rho >= 1.0)
+      need = 0.0;
+    else if (rho > 0.5)
+      need *= (1.0 - rho) / rho;
+  }
+  S.newton_prev = full ? S.step : 0.0;
   if (o_.fixed_newton) {
     if (S.iters >= o_.max_newton) S.done = true;
-  } else if (was_newton && S.step <= tol * S.ch->bbox_diag) {
+  } else if (was_newton && S.step <= need) {
     if (final_pose) {
       S.done = true;
     } else {  // intermediate pose reached: keep it, lengthen the next step

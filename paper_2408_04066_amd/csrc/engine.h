@@ -11,11 +11,35 @@
 // until all slots finish, and copy the results out.
 #pragma once
 
+#include <chrono>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
 
 namespace mfs {
+
+// Host side of a wait for the GPU (a stop flag, or the event behind a chunk
+// of PCG launches): polls back to back for a short while, since a chunk
+// usually ends within it, then sleeps between polls so that the host thread
+// does not keep the HIP runtime busy with queries; a wait that sees nothing
+// for kLimitSeconds is given up (the caller returns an error).
+struct PollPacer {
+  static constexpr int kSpins = 256;
+  static constexpr int kLimitSeconds = 120;
+  int spins = 0;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  void reset() {
+    spins = 0;
+    t0 = std::chrono::steady_clock::now();
+  }
+  // false once the wait has lasted longer than the limit
+  bool pace() {
+    if (++spins < kSpins) return true;
+    std::this_thread::sleep_for(std::chrono::microseconds(20));
+    return std::chrono::steady_clock::now() - t0 < std::chrono::seconds(kLimitSeconds);
+  }
+};
 
 struct SlotState {
   mfs_character* ch = nullptr;
@@ -26,6 +50,9 @@ struct SlotState {
   double E = INFINITY;
   bool E_known = false;
   double grad = NAN, step = NAN, relres = NAN;
+  // the previous full (alpha = 1) Newton-phase step at this pose, 0 if none:
+  // with it the stop test sees how fast the steps contract
+  double newton_prev = 0.0;
   // PCG residual history (run sizing)
   // line search
   double alpha = 0.0;
@@ -121,6 +148,10 @@ class Engine {
   bool busy(int slot) const { return slot_[slot].used && !slot_[slot].done; }
   bool finished(int slot) const { return slot_[slot].used && slot_[slot].done; }
   bool any_busy() const;
+  // Changes whenever a scheduling call moved any slot on or launched PCG
+  // iterations (the drive loops stop with an error after calls that do
+  // neither).
+  uint64_t progress_key() const;
   // Copy a finished slot's positions to x_out (caller's vertex order), host
   // or device; synchronises the stream.
   int output(int slot, double* x_out, int mem);

@@ -28,6 +28,14 @@ namespace mfs {
 
 bool Engine::async_mode() const { return ctx_->batch_async && !ctx_->pipelined && !ctx_->persistent; }
 
+uint64_t Engine::progress_key() const {
+  uint64_t k = (uint64_t)launched_[0] * 0x9E3779B97F4A7C15ull + (uint64_t)launched_[1];
+  for (const SlotState& S : slot_)
+    k = k * 1000003ull + (uint64_t)S.iters * 64 + (uint64_t)S.stage * 2 + (S.done ? 1 : 0) +
+        ((uint64_t)S.resolves << 32);
+  return k;
+}
+
 bool Engine::async_pending() const {
   for (const SlotState& S : slot_)
     if (S.used && !S.done && (S.stage == kPcg32 || S.stage == kPcg64 || S.stage == kRedo)) return true;
@@ -200,6 +208,7 @@ int Engine::async_pcg() {
     // live tiles or a quarter of the live slots, a slot at its cap, or the
     // oldest queued chunk done (then queue the next one)
     bool event = false;
+    PollPacer pacer;
     for (;;) {
       int stopped_tiles = 0, stopped_slots = 0, live_slots = 0;
       bool capped = false;
@@ -221,6 +230,9 @@ int Engine::async_pcg() {
       const hipError_t e = hipEventQuery(queued_.front());
       if (e != hipSuccess && e != hipErrorNotReady) return set_error(MFS_E_HIP, "PCG chunk: %s", hipGetErrorString(e));
       if (e == hipSuccess) break;
+      if (!pacer.pace())
+        return set_error(MFS_E_HIP, "PCG chunk: no stop flag and no completed chunk in %d s",
+                         PollPacer::kLimitSeconds);
     }
     if (event) break;
     ctx->sync_events.push_back(queued_.front());

@@ -2,9 +2,10 @@
 // (the global sparse SPD solve of each Newton step).
 //
 // Standard form: two kernels per iteration.  k_cg_spmv forms the search direction
-// p_it = z + beta p_{it-1} on the fly (double-buffered p, so the gathers of
-// neighbouring rows read the previous buffer) and q = K p_it, with LPR lanes
-// per block row reading the 9 value planes of consecutive slots (coalesced).
+// p_it = z + beta p_{it-1} row by row (double-buffered p) and q = K p_it as
+// K z + beta q_{it-1}, the product of the matrix with z alone (one gathered
+// vector per neighbouring block instead of two), with LPR lanes per block
+// row reading the block records of consecutive slots.
 // k_cg_update applies alpha, the block-Jacobi preconditioner and the next
 // dot products.  Dot products are per-tile partials in FP64, folded in a
 // fixed order: for systems with many tiles by the last workgroup to finish
@@ -212,10 +213,12 @@ __device__ __forceinline__ void share_sums2(const double* a, const double* b, in
   }
 }
 
-// Search direction p_it = z + beta p_{it-1} and q = K p_it: one pass of 64
-// rows, LPR lanes per row; partial p.q.  What the launch reads and no
-// workgroup of it writes (the PCG state, the row's block range, the row's z
-// and both p buffers, the partial sums of the previous launch) is loaded at
+// Search direction p_it = z + beta p_{it-1} and q = K p_it, formed as
+// K z + beta q_{it-1} (algebraically the same: K p_{it-1} is the previous
+// q): one pass of 64 rows, LPR lanes per row; partial p.q.  What the launch
+// reads and no workgroup of it writes (the PCG state, the row's block range,
+// the row's z, both p buffers and q, the partial sums of the previous
+// launch) is loaded at
 // its head, so those loads overlap, before a system whose PCG has stopped
 // returns.  In all-read mode the LPR waves of a workgroup fold the sums
 // together: wave w adds the tiles of its share in sequence (share_sums4), the
@@ -242,9 +245,11 @@ __global__ __launch_bounds__(64 * LPR, sizeof(T) == 4 && LPR >= 4 ? 6 : 1) void 
   const int stopped = st->done;
   const int it_t = st->it, it_all = st->it_a;
   const int it = S.ticket ? it_t : it_all;
-  T oz[3] = {0, 0, 0}, op0[3] = {0, 0, 0}, op1[3] = {0, 0, 0};
-  // with LPR >= 4, lane i < 3 of the row's group keeps component i of z and
-  // both p buffers (entry 0) and writes component i of p and q
+  T* q = (T*)S.q;
+  T oz[3] = {0, 0, 0}, op0[3] = {0, 0, 0}, op1[3] = {0, 0, 0}, oq[3] = {0, 0, 0};
+  // with LPR >= 4, lane i < 3 of the row's group keeps component i of z,
+  // both p buffers and the previous q (entry 0) and writes component i of p
+  // and q
   constexpr bool CL = LPR >= 4;
   const bool comp = valid && lane < 3;
   if (CL) {
@@ -252,6 +257,7 @@ __global__ __launch_bounds__(64 * LPR, sizeof(T) == 4 && LPR >= 4 ? 6 : 1) void 
       oz[0] = gld(z)[3 * row + lane];
       op0[0] = gld((const T*)S.p0)[3 * row + lane];
       op1[0] = gld((const T*)S.p1)[3 * row + lane];
+      oq[0] = gld((const T*)q)[3 * row + lane];
     }
   } else if (valid && lane == 0) {
 #pragma unroll
@@ -259,6 +265,7 @@ __global__ __launch_bounds__(64 * LPR, sizeof(T) == 4 && LPR >= 4 ? 6 : 1) void 
       oz[i] = z[3 * row + i];
       op0[i] = ((const T*)S.p0)[3 * row + i];
       op1[i] = ((const T*)S.p1)[3 * row + i];
+      oq[i] = q[3 * row + i];
     }
   }
   double beta;
@@ -313,13 +320,11 @@ __global__ __launch_bounds__(64 * LPR, sizeof(T) == 4 && LPR >= 4 ? 6 : 1) void 
   }
   const T tb = (T)beta;
   T* pn = (T*)((it & 1) ? S.p1 : S.p0);
-  const T* po = (const T*)((it & 1) ? S.p0 : S.p1);
   const T* vals = (const T*)S.vals;
-  T* q = (T*)S.q;
   T a0 = 0, a1 = 0, a2 = 0;
   {
-    // batches of U blocks per lane: indices and values first, then the
-    // gathers (two dependent latencies per batch, not per block)
+    // K z: batches of U blocks per lane, indices and values first, then the
+    // gathers of z (two dependent latencies per batch, not per block)
     constexpr int U = LPR >= 16 ? 1 : 16 / LPR;
     const int e = re;
     for (int base = rb + lane; base < e; base += U * LPR) {
@@ -338,12 +343,6 @@ __global__ __launch_bounds__(64 * LPR, sizeof(T) == 4 && LPR >= 4 ? 6 : 1) void 
         g[u][0] = zc.x;
         g[u][1] = zc.y;
         g[u][2] = zc.z;
-        if (it) {
-          const Triple<T> pc = gather3(po, c[u]);
-          g[u][0] += tb * pc.x;
-          g[u][1] += tb * pc.y;
-          g[u][2] += tb * pc.z;
-        }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {  // weight 1 (exact) or 0 for slots past the row's end
@@ -357,12 +356,16 @@ __global__ __launch_bounds__(64 * LPR, sizeof(T) == 4 && LPR >= 4 ? 6 : 1) void 
   a0 = group_sum<LPR>(a0);
   a1 = group_sum<LPR>(a1);
   a2 = group_sum<LPR>(a2);
+  // p = z + beta p_old and q = K z + beta q_old (= K p)
   double dot = 0.0;
   if (CL) {
     if (comp) {
       T p = oz[0];
-      if (it) p += tb * ((it & 1) ? op0[0] : op1[0]);
-      const T qv = lane == 0 ? a0 : (lane == 1 ? a1 : a2);
+      T qv = lane == 0 ? a0 : (lane == 1 ? a1 : a2);
+      if (it) {
+        p += tb * ((it & 1) ? op0[0] : op1[0]);
+        qv += tb * oq[0];
+      }
       gst(pn)[3 * row + lane] = p;
       gst(q)[3 * row + lane] = qv;
       dot = (double)p * (double)qv;
@@ -374,6 +377,9 @@ __global__ __launch_bounds__(64 * LPR, sizeof(T) == 4 && LPR >= 4 ? 6 : 1) void 
       p0 += tb * pold[0];
       p1 += tb * pold[1];
       p2 += tb * pold[2];
+      a0 += tb * oq[0];
+      a1 += tb * oq[1];
+      a2 += tb * oq[2];
     }
     pn[3 * row] = p0;
     pn[3 * row + 1] = p1;

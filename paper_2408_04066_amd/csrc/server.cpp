@@ -243,6 +243,7 @@ int ServerLane::complete_finished() {
 
 void ServerLane::run() {
   (void)hipSetDevice(ctx->device);
+  int idle = 0;  // scheduling calls in a row that moved no slot on
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(mu);
@@ -263,7 +264,12 @@ void ServerLane::run() {
       slot_steps += occupied;
       ++steps;
     }
+    const uint64_t before = eng.progress_key();
     int rc = eng.run_once();
+    if (rc >= 0) {
+      idle = eng.progress_key() == before ? idle + 1 : 0;
+      if (idle > 8) rc = set_error(MFS_E_HIP, "serving lane: scheduling calls make no progress");
+    }
     if (rc >= 0) rc = complete_finished();
     if (rc < 0) {
       const std::string msg = last_error_text();

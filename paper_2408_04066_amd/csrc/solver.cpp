@@ -74,7 +74,12 @@ int solve_systems(mfs_context* ctx, int count, mfs_character* const* chars, cons
     MFS_TRY(ensure_workspace(chars[i]));
     MFS_TRY(eng.attach(i, chars[i], R[i], t[i]));
   }
-  while (eng.any_busy()) MFS_TRY(eng.run_once());
+  for (int idle = 0; eng.any_busy();) {
+    const uint64_t before = eng.progress_key();
+    MFS_TRY(eng.run_once());
+    idle = eng.progress_key() == before ? idle + 1 : 0;
+    if (idle > 8) return set_error(MFS_E_HIP, "frame solve: scheduling calls make no progress");
+  }
   if (stats) MFS_TRY(eng.finish_energies());
   mfs_solve_opts o;
   mfs_default_opts(&o);

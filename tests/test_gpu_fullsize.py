@@ -176,14 +176,37 @@ def test_batched_positions_match_oracle_solutions(c4_batch):
         assert e64 <= 1e-9
 
 
+# Members of the 64-character batch (first poses) that are known not to
+# converge, with the reason.  The oracle's own solve (exact sparse LU solves,
+# up to 100 Newton iterations, tests/golden/c4_oracle_summary.json) does not
+# converge on these poses either.  Each uses all six load-step bisections:
+# in the mixed phase a few tens of neo-Hookean tets keep the stretch step
+# below 1/4 (the poses turn some element clusters by more than 90 degrees
+# against their neighbours, where the neo-Hookean energy of the rig-fixed
+# rotations is infinite).
+KNOWN_UNCONVERGED_C4 = {
+    26: "reaches the final pose after 78 iterations (67 mixed), then converges "
+        "linearly (step ratio about 0.56) past the iteration cap",
+    29: "mixed phase stalls at 28% of the pose (78 of 100 iterations mixed)",
+    50: "mixed phase stalls at 72% of the pose (87 of 100 iterations mixed)",
+    52: "mixed phase stalls at 97% of the pose (90 of 100 iterations mixed)",
+    53: "mixed phase stalls at the final pose (77 of 100 iterations mixed)",
+    59: "mixed phase stalls at 81% of the pose (89 of 100 iterations mixed)",
+}
+
+
 def test_batched_characters_at_full_size(c4_batch):
     """Members of the same batched run (smallest, largest and two between)
-    checked by the oracle's energy and gradient against a tight FP64 solve."""
+    checked by the oracle's energy and gradient against a tight FP64 solve;
+    every member outside the known unconverged ones converges."""
     probs, poses, ctx, chars, xs, sts, _ = c4_batch
     sizes = np.array([len(p["T"]) for p in probs])
     order = np.argsort(sizes)
     conv = [k for k in order if sts[k]["status"] == 0]
-    assert len(conv) >= 0.8 * len(probs)
+    unconv = sorted(int(k) for k in range(len(probs)) if sts[k]["status"] != 0)
+    _say(f"  unconverged: {[(k, sts[k]['iterations'], sts[k]['mixed_iterations']) for k in unconv]}")
+    surprise = [k for k in unconv if k not in KNOWN_UNCONVERGED_C4]
+    assert not surprise, f"members {surprise} did not converge: {[sts[k] for k in surprise]}"
     # four members spread over the sizes; a member whose tight solve does not
     # converge either (a pose that leaves elements inverted) gives way to the
     # next converged member in size order.  A converged member whose Newton
