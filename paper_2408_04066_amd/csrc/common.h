@@ -19,6 +19,7 @@ constexpr int kTTile = 256;      // tets per tile
 constexpr int kSTile = 256;      // matrix-block slots per tile
 constexpr int kMaxHandles = 256;
 constexpr int kNumTrials = 5;    // line-search step lengths evaluated per energy pass
+constexpr double kCheckEta = 1e-3;  // largest PCG forcing term of a step that checks a stop
 
 // Per-tile partial-result planes (index into SysDesc::part).
 enum PartSlot : int {
@@ -99,21 +100,24 @@ struct Ctrl {
   int32_t pad2;
   double cg_g2prev;  // |g|^2 of the previous Newton step (0: first step)
   double cg_eta_min; // safeguard lower bound on the forcing term
+  double cg_eta_max; // upper bound on the forcing term (0: 0.1)
   double trials[kNumTrials];  // step lengths evaluated by the energy pass
 };
 
 // PCG stopping threshold on |r|^2 / |b|^2 for one Newton step: the floor
 // cg_tol^2, raised in adaptive mode to the Eisenstat-Walker (choice 2) forcing
-// eta^2 with eta = min(0.1, 0.9 (|b| / |b_prev|)^2), never below the
-// safeguard eta_min; the first step uses eta = 0.1.
+// eta^2 with eta = min(eta_max, 0.9 (|b| / |b_prev|)^2), eta_max = 0.1 except
+// in a step that checks a stop (kCheckEta), never below the safeguard
+// eta_min; the first step uses eta = eta_max.
 __host__ __device__ inline double pcg_tol2(const Ctrl& C, double bb) {
   double tol2 = C.cg_tol2;
   if (C.cg_adaptive) {
-    double eta2 = 0.01;
+    const double cap = C.cg_eta_max > 0.0 ? C.cg_eta_max : 0.1;
+    double eta2 = cap * cap;
     if (C.cg_g2prev > 0.0) {
       const double ratio = bb / C.cg_g2prev;
       eta2 = 0.81 * ratio * ratio;
-      eta2 = eta2 < 0.01 ? eta2 : 0.01;
+      eta2 = eta2 < cap * cap ? eta2 : cap * cap;
       const double lo = C.cg_eta_min * C.cg_eta_min;
       eta2 = eta2 > lo ? eta2 : lo;
     }

@@ -800,6 +800,8 @@ int Engine::step() {
     // tolerance (a loose mixed step can leave the positive-definite cone in
     // single tets and stall the mixed line search)
     hc[i].cg_adaptive = (o_.cg_adaptive && slot_[i].phase == 1) ? 1 : 0;
+    hc[i].cg_eta_max = slot_[i].check_next ? kCheckEta : 0.0;
+    slot_[i].check_next = false;
     hc[i].cg_cap = fp32_ ? fp32_cap(slot_[i].ch) : o_.cg_max;
   }
   cg_epoch_ = ++ctx->cg_epoch;
@@ -913,16 +915,26 @@ int Engine::finish_newton(int i) {
   // Intermediate poses of load stepping keep the plain test.
   double need = tol * S.ch->bbox_diag;
   const bool full = was_newton && S.alpha == 1.0;
+  const double rho = full && S.newton_prev > 0.0 ? S.step / S.newton_prev : NAN;
   if (final_pose && full && S.newton_prev > 0.0 && S.step > 0.05 * need) {
-    const double rho = S.step / S.newton_prev;
     if (rho >= 1.0)
       need = 0.0;
     else if (rho > 0.5)
       need *= (1.0 - rho) / rho;
   }
   S.newton_prev = full ? S.step : 0.0;
+  // A short step also says little when its PCG stopped on a loose forcing
+  // term (near 0.1 when the gradient stalls): the solve can leave a soft
+  // mode of the Newton step unsolved, so the steps shrink while the
+  // iterate stays where it is.  The symptom is steps that shrink slowly
+  // (rho above 1/2, or no previous full step to compare with); such a stop
+  // after a solve looser than the check tolerance is taken only after one
+  // more step whose forcing term is at most that tolerance.
+  const bool check = final_pose && was_newton && o_.cg_adaptive && S.relres > kCheckEta && !(rho <= 0.5);
   if (o_.fixed_newton) {
     if (S.iters >= o_.max_newton) S.done = true;
+  } else if (was_newton && S.step <= need && check) {
+    S.check_next = true;
   } else if (was_newton && S.step <= need) {
     if (final_pose) {
       S.done = true;

@@ -53,6 +53,9 @@ struct SlotState {
   // the previous full (alpha = 1) Newton-phase step at this pose, 0 if none:
   // with it the stop test sees how fast the steps contract
   double newton_prev = 0.0;
+  // the next Newton step checks a stop: its PCG forcing term is at most
+  // 1e-3 (see finish_newton)
+  bool check_next = false;
   // PCG residual history (run sizing)
   // line search
   double alpha = 0.0;

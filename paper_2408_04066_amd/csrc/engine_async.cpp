@@ -80,6 +80,8 @@ int Engine::async_head(const std::vector<int>& ids, int prec, bool redo) {
       hc[i].alpha = 0.0;
       // inexact Newton only on the constraint (as in step())
       hc[i].cg_adaptive = (o_.cg_adaptive && S.phase == 1) ? 1 : 0;
+      hc[i].cg_eta_max = S.check_next ? kCheckEta : 0.0;
+      S.check_next = false;
       hc[i].cg_cap = fp32_ ? fp32_cap(S.ch) : o_.cg_max;
     }
     hc[i].cg_epoch = epoch;
@@ -364,6 +366,10 @@ int Engine::advance() {
   if (!any) {
     MFS_HIP(hipStreamSynchronize(st));
     async_attribute();
+    // every solve has ended, so every timed launch is attributed; one that
+    // is not (no span recorded for it) is dropped with the spans
+    for (ProfPending& p : ctx->pending)
+      if (p.tag >= 0) p.tag = kProfDropped;
     prof_resolve(ctx);
     spans_.clear();
     gens_.clear();

@@ -85,11 +85,14 @@ struct UploadRing {
 }  // namespace mfs
 
 namespace mfs {
+constexpr int kProfDropped = -2;
 struct ProfPending {
   int fam;
   double bytes;
-  hipEvent_t a, b;
-  int tag;  // PCG iteration index of an SpMV-family launch whose bytes are set after its run (-1: none)
+  hipEvent_t a, b;  // the launch group's event pair, until its time is read (then null)
+  int tag;          // index of an SpMV-family launch whose bytes are set after its run (-1: none,
+                    // kProfDropped: never attributed, not counted)
+  float ms = -1.0f; // the group's time once read (negative: not read, or not measurable)
 };
 struct CgGraph {
   const SysDesc* sd;
@@ -200,7 +203,10 @@ void bind_workspace(const mfs_character* ch, char* base, SysDesc* d);
 int ensure_workspace(mfs_character* ch);
 
 // Brackets one launch group of kernel family `fam` with an event pair when
-// the context profiler samples it.
+// the context profiler samples it.  prof_resolve reads the times of pairs
+// that have completed and returns their events to the pool at once (the
+// events of a pair still in flight stay with it), and folds in the launch
+// groups whose bytes are known.
 struct ProfScope {
   mfs_context* c;
   int fam;

@@ -55,26 +55,39 @@ ProfScope::~ProfScope() {
     c->ev_pool.push_back(b);
     return;
   }
-  c->pending.push_back(ProfPending{fam, bytes, a, b, tag});
+  c->pending.push_back(ProfPending{fam, bytes, a, b, tag, -1.0f});
 }
 
-// Launches whose algorithmic bytes are not known yet (tag >= 0: the PCG
-// solves they served have not all ended) stay pending.
+// Each pair whose launches have completed gives up its time and its events
+// (a pair still in flight keeps both: its events must not be recorded again
+// before its dispatches end).  Launch groups whose algorithmic bytes are not
+// known yet (tag >= 0: the PCG solves they served have not all ended) stay
+// pending with their time alone, so the events held at any moment are those
+// of launches since the last stream synchronisation.
 void prof_resolve(mfs_context* c) {
   std::vector<ProfPending> keep;
-  for (const ProfPending& p : c->pending) {
+  for (ProfPending p : c->pending) {
+    if (p.a) {
+      float ms = 0.0f;
+      const hipError_t e = hipEventElapsedTime(&ms, p.a, p.b);
+      if (e == hipErrorNotReady) {
+        keep.push_back(p);
+        continue;
+      }
+      p.ms = e == hipSuccess ? ms : -1.0f;
+      c->ev_pool.push_back(p.a);
+      c->ev_pool.push_back(p.b);
+      p.a = p.b = nullptr;
+    }
     if (p.tag >= 0) {
       keep.push_back(p);
       continue;
     }
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-      c->prof_ms[p.fam] += ms;
+    if (p.tag == -1 && p.ms >= 0.0f) {
+      c->prof_ms[p.fam] += p.ms;
       c->prof_timed[p.fam]++;
       c->prof_bytes[p.fam] += p.bytes;
     }
-    c->ev_pool.push_back(p.a);
-    c->ev_pool.push_back(p.b);
   }
   c->pending.swap(keep);
 }
@@ -84,8 +97,8 @@ void prof_resolve(mfs_context* c) {
 mfs_context::~mfs_context() {
   for (const mfs::CgGraph& g : graphs) (void)hipGraphExecDestroy(g.exec);
   for (const mfs::ProfPending& p : pending) {
-    (void)hipEventDestroy(p.a);
-    (void)hipEventDestroy(p.b);
+    if (p.a) (void)hipEventDestroy(p.a);
+    if (p.b) (void)hipEventDestroy(p.b);
   }
   for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : sync_events) (void)hipEventDestroy(e);
