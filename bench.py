@@ -164,6 +164,12 @@ def host_cpu():
     return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0))}
 
 
+# Newton iterations per autotuning run of a frame workload: about a
+# converged frame's length (4 misjudged the asynchronous batch, whose first
+# iterations are mostly long mixed-phase solves; whole frames take minutes
+# on the 64-character batch, where unconverged frames run 60 iterations)
+TUNE_NEWTON = 12
+SERVE_STALL_S = 120.0  # a serving run that completes no request for this long is reported as stalled
 CPU_BASELINE_MAX_TETS = 200_000  # largest single character whose oracle frame is a bounded sample
 
 
@@ -234,6 +240,10 @@ def counter_pass(args, mfs, torch, ctxs, chars, probs, infos, steps, opts, frame
 
 def frame_bench(args, mfs, torch):
     probs, pose_of, wname, opts = make_workload(args.workload)
+    if args.opts:  # stated solve options over the workload's (mfs_solve_opts names)
+        for kv in args.opts.split(","):
+            k, v = kv.split("=")
+            opts[k] = float(v) if ("." in v or "e" in v) else int(v)
     # size classes (batches only): each class is solved as its own batch on its
     # own context (HIP stream) from its own host thread, so a small
     # character's Newton steps do not wait for a large one's PCG runs
@@ -264,7 +274,7 @@ def frame_bench(args, mfs, torch):
         stress_out = [(torch.empty((i["n_tets"], 6), dtype=torch.float64, device="cuda"),
                        torch.empty((i["n_tets"], 3, 3), dtype=torch.float64, device="cuda")) for i in infos]
     outs = [torch.empty((i["n_vertices"], 3), dtype=torch.float64, device="cuda") for i in infos]
-    steps = [pose_of(i) for i in range(args.warmup + args.steps + args.fp64_steps)]
+    steps = [pose_of(i) for i in range(args.warmup + args.steps + args.roofline_steps + args.fp64_steps)]
     fp64_opts = dict(opts, precision=mfs.FP64)
     warm = opts.get("warm_start", 0) == mfs.WARM_PREVIOUS
     _progress(f"{wname}: {len(chars)} characters resident, {m_tot} tets")
@@ -273,9 +283,9 @@ def frame_bench(args, mfs, torch):
         tuned = []
         for g in range(K):
             t, tms = mfs.autotune(ctxs[g], [chars[i] for i in members[g]], [steps[0][i] for i in members[g]],
-                                  newton_iterations=4, cache_path=args.tune_cache, **opts)
+                                  newton_iterations=TUNE_NEWTON, cache_path=args.tune_cache, **opts)
             tuned.append(t)
-            _progress(f"class {g}: autotuned PCG schedule {t} ({tms:.1f} ms per 4 Newton iterations)")
+            _progress(f"class {g}: autotuned PCG schedule {t} ({tms:.1f} ms per {TUNE_NEWTON} Newton iterations)")
         tuned = tuned[0] if K == 1 else tuned
     fixed = dict(kv.split("=") for kv in args.tuning.split(",")) if args.tuning else {}
     for c in ctxs:  # batches: each character's Newton steps on its own (1) or in lockstep (0)
@@ -317,13 +327,21 @@ def frame_bench(args, mfs, torch):
     torch.cuda.synchronize()
     _progress("warmup done")
 
-    # ---- timed region: the library's profiler times every stride-th launch
+    # ---- timed region.  The library's profiler times every stride-th launch
     # of each kernel family with a HIP event pair carried in the launch's own
-    # dispatches (on the library's stream), so the roofline figures below are
-    # those of the timed launches ----
-    for c in ctxs:
-        c.profile_enable(args.profile_stride)
-        c.profile_read(reset=True)
+    # dispatches (on the library's stream).  Where every launch is direct (the
+    # asynchronous batch form) it samples the timed launches themselves;
+    # where PCG runs replay as HIP graphs (single characters, the pipelined
+    # form) sampling needs direct launches, so it runs on the next frames of
+    # the same kind after the timed region and the timed frames keep their
+    # graphs ----
+    def graphs_replayed(t):
+        return bool(t["use_graphs"]) and (bool(t["pcg_pipelined"]) or not t["batch_async"] or len(chars) == 1)
+    sample_timed = not any(graphs_replayed(c.tuning()) for c in ctxs)
+    if sample_timed:
+        for c in ctxs:
+            c.profile_enable(args.profile_stride)
+            c.profile_read(reset=True)
     lat, rcs, per_frame = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -337,12 +355,21 @@ def frame_bench(args, mfs, torch):
         per_frame += [(i, j, st) for j, st in enumerate(sts)]
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
+    _progress(f"timed {args.steps} steps in {total:.2f} s")
+    nxt = args.warmup + args.steps
+    if not sample_timed:  # sampled pass over the next frames, direct launches
+        for c in ctxs:
+            c.profile_enable(args.profile_stride)
+            c.profile_read(reset=True)
+        for i in range(args.roofline_steps):
+            frame(steps[nxt + i], opts)
+        nxt += args.roofline_steps
+        _progress("sampled roofline pass done")
     prof = {}
     for c in ctxs:
         for fam, v in c.profile_read(reset=True).items():
             prof[fam] = tuple(a + b for a, b in zip(prof.get(fam, (0.0, 0, 0, 0.0)), v))
         c.profile_enable(0)
-    _progress(f"timed {args.steps} steps in {total:.2f} s")
     # a frame counts when it converged (status 0); a frame stopped by the
     # Newton cap (or a failed line search) is not a solution at 1e-7
     conv = [st["status"] == 0 for _, _, st in per_frame]
@@ -361,7 +388,6 @@ def frame_bench(args, mfs, torch):
     # forms stop on the same step test, which a slowly converging frame can
     # pass far from its solution, so their difference alone does not say
     # which of them is off ----
-    nxt = args.warmup + args.steps
     lat64, tet_iters64, err, err32, err64 = [], 0, [], [], []
     rest_opts = dict(opts, warm_start=mfs.WARM_REST)
     tight_opts = dict(fp64_opts, warm_start=mfs.WARM_REST, step_tol=1e-12, cg_tol=1e-10, cg_adaptive=0,
@@ -457,6 +483,9 @@ def frame_bench(args, mfs, torch):
         "cg_iters_per_frame": float(np.mean([st["cg_iterations"] for _, _, st in per_frame])),
         "cg_iters_per_newton": float(sum(st["cg_iterations"] for _, _, st in per_frame)
                                      / max(1, sum(st["iterations"] for _, _, st in per_frame))),
+        "fp64_resolves": {"newton_steps": sum(st["fp64_resolves"] for _, _, st in per_frame),
+                          "pcg_iterations": sum(st["fp64_resolve_cg_iterations"] for _, _, st in per_frame),
+                          "frames": sum(st["fp64_resolves"] > 0 for _, _, st in per_frame)},
         "status_codes": sorted(set(int(r) for r in rcs)),
         "fp64": {
             "frames_per_s": nchar * len(lat64) / sum(lat64) if lat64 else None,
@@ -481,12 +510,16 @@ def frame_bench(args, mfs, torch):
                    "newton": "fixed 10" if opts.get("fixed_newton") else f"max {opts['max_newton']}",
                    "warm_start": "previous frame" if warm else "rest",
                    "pcg_schedule": tuned or ctx.tuning(),
+                   **({"solve_option_overrides": args.opts} if args.opts else {}),
                    **({"size_classes": K, "class_tet_edges": [float(e) for e in edges],
                        "class_sizes": [len(m_) for m_ in members]} if K > 1 else {}),
                    **({"extended": extended} if extended else {})},
         "roofline": {
             "bound": "hbm",
             "kernel": kernel,
+            "sampled_over": ("every stride-th launch of the timed steps" if sample_timed else
+                             f"every stride-th launch of {args.roofline_steps} frames after the timed steps, "
+                             f"launched directly (the timed steps replay their PCG runs as graphs)"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -579,6 +612,9 @@ def serve_bench(args, mfs, torch):
     queue = max(1, args.queue // K)  # the same total queue capacity however the pool is split
     srv = mfs.Server(ctx, slots=slots[0], queue_capacity=queue, workspace_budget_bytes=max(budgets),
                      lane_max_tets=lane_max, **opts)
+    fixed = {k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))} if args.tuning else {}
+    if fixed:  # stated schedule fields over the autotuned ones (or the defaults)
+        tuned = [dict(t, **fixed) for t in tuned] if tuned else [dict(ctx.tuning(), **fixed) for _ in range(K)]
     for g, t in enumerate(tuned):
         srv.set_lane_tuning(g, **t)
     for j in range(min(args.warmup, n_req)):  # warm the kernels and graphs
@@ -601,8 +637,24 @@ def serve_bench(args, mfs, torch):
                 raise
             rejected += 1
     lat, tet_iters, tet_iters_all, done_t, conv, first_submit = [], 0, 0, [], [], None
-    for k, tk in tickets:
-        _, st, tm, _ = srv.wait(tk)
+    # drain: poll the tickets in order, reporting progress; a server that
+    # completes nothing for SERVE_STALL_S seconds ends the run with an error
+    last_done, last_change = srv.info()["completed"], time.perf_counter()
+    for n_done, (k, tk) in enumerate(tickets):
+        while True:
+            res = srv.poll(tk)
+            if res is not None:
+                break
+            time.sleep(0.01)
+            c = srv.info()["completed"]
+            if c != last_done:
+                last_done, last_change = c, time.perf_counter()
+            elif time.perf_counter() - last_change > SERVE_STALL_S:
+                raise RuntimeError(f"serving stalled: no request completed in {SERVE_STALL_S} s "
+                                   f"({c} completed, {len(tickets)} accepted)")
+        if n_done % 1000 == 0 and n_done:
+            _progress(f"collected {n_done} of {len(tickets)} results")
+        _, st, tm, _ = res
         lat.append(tm["done_s"] - tm["submit_s"])
         first_submit = tm["submit_s"] if first_submit is None else min(first_submit, tm["submit_s"])
         done_t.append(tm["done_s"])
@@ -665,11 +717,17 @@ def main():
                          "iterations per character (no timed run)")
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--profile-stride", type=int, default=8)
+    ap.add_argument("--roofline-steps", type=int, default=2,
+                    help="frames of the sampled pass that follows the timed region where PCG runs replay "
+                         "as graphs (the asynchronous batch form samples its timed launches instead)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default PCG schedule")
     ap.add_argument("--tuning", default="",
                     help="PCG schedule fields set after autotuning, KEY=VALUE,... (mfs_tuning names), e.g. "
                          "with --no-autotune to run a stated schedule")
+    ap.add_argument("--opts", default="",
+                    help="solve options over the workload's, KEY=VALUE,... (mfs_solve_opts names, e.g. "
+                         "fp32_cg_max=4000)")
     ap.add_argument("--batch-async", type=int, default=1, choices=(0, 1),
                     help="batches with the two-kernel PCG: each character runs its own Newton steps (1) or "
                          "all run the same Newton iteration (0)")

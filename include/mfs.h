@@ -115,7 +115,7 @@ typedef struct mfs_solve_opts {
   int32_t fp32_cg_max;      /* FP32_REFINED: a Newton step whose FP32 PCG has not converged
                                after this many iterations (or broke down) is solved again in
                                FP64 (element records, assembly, and a PCG started from the
-                               FP32 iterate); 0 = 100 n^(1/3), at least 2000 */
+                               FP32 iterate); 0 = 100 n^(1/3), at least 8000 */
 } mfs_solve_opts;
 
 typedef struct mfs_solve_stats {
@@ -132,7 +132,7 @@ typedef struct mfs_solve_stats {
   double last_step;         /* max_v ||alpha dx_v|| of the last iteration */
   double cg_rel_residual;   /* ||r|| / ||b|| of the last PCG solve */
   int32_t fp64_resolves;    /* FP32_REFINED: Newton steps re-solved in FP64 (fp32_cg_max) */
-  int32_t reserved;
+  int32_t fp64_resolve_cg_iterations; /* PCG iterations of those re-solves (included in cg_iterations) */
 } mfs_solve_stats;
 
 /* ---- library and context --------------------------------------------- */
@@ -323,8 +323,11 @@ int mfs_solve_batch(mfs_context* ctx, int32_t count, mfs_character* const* chars
  * graph, first convergence check, shortest run between checks) for a batch
  * like this one and apply it to the context.  Each candidate solves the
  * given frames (as mfs_solve_batch with `opts`, but from the rest shape and
- * for exactly `newton_iterations` iterations, into scratch device memory)
- * twice, timing the second.  A candidate's time is scaled by the default
+ * for exactly `newton_iterations` iterations, or, with newton_iterations 0,
+ * as whole frames under `opts`' stop rule and Newton cap, into scratch
+ * device memory) twice, timing the second.  The two-kernel form in the
+ * asynchronous batch form is timed at one graph length only (it launches
+ * directly).  A candidate's time is scaled by the default
  * schedule's total PCG iteration count over its own (summation order alone
  * moves the counts by a few percent), and the winner is the fastest
  * candidate by that time whose solves are as good as the default

@@ -74,10 +74,10 @@ class SolveStats(ctypes.Structure):
                 ("cg_iterations", c_i32), ("halvings", c_i32), ("clamped", c_i32),
                 ("fp64_routed", c_i32), ("cg_not_converged", c_i32), ("energy", c_dbl),
                 ("grad_norm", c_dbl), ("last_step", c_dbl), ("cg_rel_residual", c_dbl),
-                ("fp64_resolves", c_i32), ("reserved", c_i32)]
+                ("fp64_resolves", c_i32), ("fp64_resolve_cg_iterations", c_i32)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class CharacterInfo(ctypes.Structure):

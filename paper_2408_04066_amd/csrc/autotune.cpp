@@ -103,7 +103,7 @@ extern "C" int mfs_autotune(mfs_context* ctx, int32_t count, mfs_character* cons
   clear_error();
   if (!ctx || count < 1 || !chars || !handle_R || !handle_t)
     return set_error(MFS_E_INVALID, "null argument or empty batch");
-  if (newton_iterations < 1) return set_error(MFS_E_INVALID, "newton_iterations must be positive");
+  if (newton_iterations < 0) return set_error(MFS_E_INVALID, "newton_iterations must be >= 0");
   for (int i = 0; i < count; ++i)
     if (!chars[i] || chars[i]->ctx != ctx) return set_error(MFS_E_INVALID, "character %d is null or of another context", i);
   MFS_HIP(hipSetDevice(ctx->device));
@@ -137,8 +137,13 @@ extern "C" int mfs_autotune(mfs_context* ctx, int32_t count, mfs_character* cons
   mfs_default_opts(&o);
   if (opts) o = *opts;
   o.warm_start = MFS_WARM_REST;
-  o.fixed_newton = 1;
-  o.max_newton = newton_iterations;
+  // a fixed number of Newton iterations, or (0) whole frames with the
+  // caller's stop rule and Newton cap: the asynchronous batch form's launch
+  // sets change over a frame, so its first iterations alone misjudge it
+  if (newton_iterations > 0) {
+    o.fixed_newton = 1;
+    o.max_newton = newton_iterations;
+  }
   o.output_memory = MFS_MEM_DEVICE;
   std::vector<DevBuf> outs(count);
   std::vector<double*> xo(count);
@@ -204,6 +209,12 @@ extern "C" int mfs_autotune(mfs_context* ctx, int32_t count, mfs_character* cons
   for (int lpr : {2, 4, 8})
     for (int gi : {4, 8, 16}) {
       if (form == 2 && gi != 8) continue;
+      // the two-kernel form in the asynchronous batch form launches directly:
+      // its graph length does not matter
+      if (form == 0 && win.batch_async && gi != 8) continue;
+      // batches: the persistent launch holds one system's tiles only, and the
+      // shortest graphs lose to longer ones at batch sizes
+      if (count > 1 && (form == 2 || gi == 4)) continue;
       mfs_tuning t = win;
       t.pcg_pipelined = form > 0 ? 1 : 0;
       t.pcg_persistent = form == 2 ? 1 : 0;

@@ -457,7 +457,7 @@ int Engine::tiles_for(const std::vector<int>& ids) {
 
 int Engine::fp32_cap(const mfs_character* ch) const {
   if (o_.fp32_cg_max > 0) return std::min(o_.cg_max, o_.fp32_cg_max);
-  return std::min(o_.cg_max, std::max(2000, (int)(100.0 * std::cbrt((double)ch->n))));
+  return std::min(o_.cg_max, std::max(8000, (int)(100.0 * std::cbrt((double)ch->n))));
 }
 
 int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* failed) {
@@ -552,6 +552,7 @@ int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* fai
           return set_error(MFS_E_HIP, "persistent PCG: a barrier wait timed out (slot %d)", i);
         const bool ok = hg[i].done == 1;
         slot_[i].cg += hg[i].iters;
+        if (!fp32 && fp32_) slot_[i].cg_resolve += hg[i].iters;
         if (ok) continue;
         if (failed)
           failed->push_back(i);
@@ -651,7 +652,9 @@ int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* fai
   if (live.size() != act.size()) MFS_TRY(tiles_for(act));
   for (int i : act) {
     const bool ok = hg[i].done == 1;
-    slot_[i].cg += hg[i].done ? hg[i].iters : (stopped_at[i] >= 0 ? stopped_at[i] : cit);
+    const int ran = hg[i].done ? hg[i].iters : (stopped_at[i] >= 0 ? stopped_at[i] : cit);
+    slot_[i].cg += ran;
+    if (!fp32 && fp32_) slot_[i].cg_resolve += ran;
     if (ok) continue;
     if (failed)
       failed->push_back(i);
@@ -926,11 +929,10 @@ int Engine::finish_newton(int i) {
   // A short step also says little when its PCG stopped on a loose forcing
   // term (near 0.1 when the gradient stalls): the solve can leave a soft
   // mode of the Newton step unsolved, so the steps shrink while the
-  // iterate stays where it is.  The symptom is steps that shrink slowly
-  // (rho above 1/2, or no previous full step to compare with); such a stop
-  // after a solve looser than the check tolerance is taken only after one
-  // more step whose forcing term is at most that tolerance.
-  const bool check = final_pose && was_newton && o_.cg_adaptive && S.relres > kCheckEta && !(rho <= 0.5);
+  // iterate stays where it is.  A stop after a solve looser than the check
+  // tolerance is taken only after one more step whose forcing term is at
+  // most that tolerance.
+  const bool check = final_pose && was_newton && o_.cg_adaptive && S.relres > kCheckEta;
   if (o_.fixed_newton) {
     if (S.iters >= o_.max_newton) S.done = true;
   } else if (was_newton && S.step <= need && check) {
@@ -1012,6 +1014,7 @@ void Engine::stats(int i, mfs_solve_stats* s) const {
   s->fp64_routed = S.routed;
   s->cg_not_converged = S.cg_fail;
   s->fp64_resolves = S.resolves;
+  s->fp64_resolve_cg_iterations = S.cg_resolve;
   s->energy = S.E;
   s->grad_norm = S.grad;
   s->last_step = S.step;

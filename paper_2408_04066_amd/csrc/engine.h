@@ -47,6 +47,7 @@ struct SlotState {
   int phase = 0;  // 0 mixed (s != J x), 1 Newton (s = J x)
   int status = MFS_OK;
   int iters = 0, mixed = 0, cg = 0, halvings = 0, clamped = 0, routed = 0, cg_fail = 0, resolves = 0;
+  int cg_resolve = 0;  // PCG iterations of the FP64 re-solves (counted in cg too)
   double E = INFINITY;
   bool E_known = false;
   double grad = NAN, step = NAN, relres = NAN;
@@ -138,8 +139,10 @@ class Engine {
   // which slots share a launch changes.
   int advance();
   // advance() applies: the context runs the two-kernel PCG with the
-  // asynchronous batch form enabled.
+  // asynchronous batch form enabled, and the engine's driver allows it.
   bool async_mode() const;
+  // The serving lanes keep the lockstep form (see server.cpp).
+  void allow_async(bool on) { async_ok_ = on; }
   // Some slot is inside an asynchronous Newton step (solving, or waiting for
   // its FP64 re-solve): advance() must run until none is, even after the
   // context left the asynchronous form.
@@ -209,6 +212,7 @@ class Engine {
   TileSet lts_[2];
   DevBuf ltiles_[2];
   int64_t launched_[2] = {0, 0};
+  bool async_ok_ = true;
   std::vector<hipEvent_t> queued_;
   std::vector<SolveSpan> spans_;
   std::vector<std::vector<int>> gens_;

@@ -26,7 +26,9 @@
 
 namespace mfs {
 
-bool Engine::async_mode() const { return ctx_->batch_async && !ctx_->pipelined && !ctx_->persistent; }
+bool Engine::async_mode() const {
+  return async_ok_ && ctx_->batch_async && !ctx_->pipelined && !ctx_->persistent;
+}
 
 uint64_t Engine::progress_key() const {
   uint64_t k = (uint64_t)launched_[0] * 0x9E3779B97F4A7C15ull + (uint64_t)launched_[1];
@@ -251,6 +253,7 @@ int Engine::async_pcg() {
     for (int i : live_[p]) {
       SlotState& S = slot_[i];
       const int64_t ran = launched_[p] - S.pcg_base;
+      const int before = S.cg;
       if (hg[i].done) {
         S.cg += hg[i].iters;
         if (S.span >= 0) spans_[S.span].end = S.pcg_base + hg[i].iters;
@@ -261,6 +264,7 @@ int Engine::async_pcg() {
         still.push_back(i);
         continue;
       }
+      if (p == 0 && fp32_) S.cg_resolve += S.cg - before;  // an FP64 re-solve's iterations
       out.push_back(i);
       const bool ok = hg[i].done == 1;
       if (!ok && p == 1) {

@@ -1391,13 +1391,12 @@ hipError_t launch_pcg_persist(hipStream_t st, const SysDesc* sd, const Tile* tv,
   const int L = (lpr == 2 || lpr == 8) ? lpr : 4;
   void* args[] = {(void*)&sd, (void*)&tv, (void*)&ntv};
   LaunchEvents& le = launch_events();
-  if (le.stop && !le.started) (void)hipEventRecord(le.start, st);
-  const hipError_t e = hipLaunchCooperativeKernel(persist_fn(L), dim3(ntv), dim3(64 * L), args, (unsigned)lds_bytes, st);
-  if (le.stop) {
-    (void)hipEventRecord(le.stop, st);
+  if (le.stop && !le.started) {
+    (void)hipEventRecord(le.start, st);
     le.started = true;
+    le.where = st;
   }
-  return e;
+  return hipLaunchCooperativeKernel(persist_fn(L), dim3(ntv), dim3(64 * L), args, (unsigned)lds_bytes, st);
 }
 
 void launch_cg_finish(hipStream_t st, const SysDesc* sd, const Tile* tv, int ntv, int fp32) {

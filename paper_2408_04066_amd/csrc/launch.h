@@ -1,7 +1,6 @@
 // Host-side launchers of the library's kernels (one per kernel family).
 #pragma once
 
-#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -9,27 +8,27 @@
 
 namespace mfs {
 
-// Event pair of a sampled profiler scope.  While `stop` is set, launches
-// through MFS_LAUNCH go out as hipExtLaunchKernelGGL with the events in the
-// dispatch itself: `start` takes the first kernel's start time and `stop`
-// each kernel's end time, so the interval is kernel execution without the
-// gaps of separately recorded events.
+// Event pair of a sampled profiler scope.  While `stop` is set, the first
+// launch through MFS_LAUNCH records `start` on its stream just before it; the
+// scope records `stop` on the same stream when it closes, after its last
+// launch, so the interval spans the scope's kernels (and the small gaps
+// between them).
 struct LaunchEvents {
   hipEvent_t start = nullptr, stop = nullptr;
   bool started = false;
+  hipStream_t where = nullptr;  // the stream of the first launch
 };
 LaunchEvents& launch_events();  // this host thread's pair
 
 #define MFS_LAUNCH(kernel, grid, block, shmem, stream, ...)                                            \
   do {                                                                                               \
     ::mfs::LaunchEvents& le_ = ::mfs::launch_events();                                               \
-    if (le_.stop) {                                                                                  \
-      hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, le_.started ? nullptr : le_.start, le_.stop, \
-                            0, __VA_ARGS__);                                                         \
+    if (le_.stop && !le_.started) {                                                                  \
+      (void)hipEventRecord(le_.start, stream);                                                       \
       le_.started = true;                                                                            \
-    } else {                                                                                         \
-      hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                           \
+      le_.where = stream;                                                                            \
     }                                                                                                \
+    hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                             \
   } while (0)
 
 // setup and helpers

@@ -1,6 +1,6 @@
 // Context profiler: for every stride-th launch group of a kernel family, a
-// HIP event pair carried by the group's kernel dispatches (start of its
-// first kernel, end of its last), folded into per-family totals at stream
+// HIP event pair recorded on the group's stream around its launches (before
+// its first kernel, after its last), folded into per-family totals at stream
 // syncs.
 #include <cstring>
 
@@ -49,12 +49,14 @@ ProfScope::~ProfScope() {
   if (!a) return;
   LaunchEvents& le = launch_events();
   const bool launched = le.started;
+  const hipStream_t st = le.where;
   le = LaunchEvents();
   if (!launched) {
     c->ev_pool.push_back(a);
     c->ev_pool.push_back(b);
     return;
   }
+  (void)hipEventRecord(b, st);  // after the scope's last launch
   c->pending.push_back(ProfPending{fam, bytes, a, b, tag, -1.0f});
 }
 
