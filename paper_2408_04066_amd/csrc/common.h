@@ -19,7 +19,6 @@ constexpr int kTTile = 256;      // tets per tile
 constexpr int kSTile = 256;      // matrix-block slots per tile
 constexpr int kMaxHandles = 256;
 constexpr int kNumTrials = 5;    // line-search step lengths evaluated per energy pass
-constexpr double kCheckEta = 1e-3;  // largest PCG forcing term of a step that checks a stop
 
 // Per-tile partial-result planes (index into SysDesc::part).
 enum PartSlot : int {
@@ -107,7 +106,7 @@ struct Ctrl {
 // PCG stopping threshold on |r|^2 / |b|^2 for one Newton step: the floor
 // cg_tol^2, raised in adaptive mode to the Eisenstat-Walker (choice 2) forcing
 // eta^2 with eta = min(eta_max, 0.9 (|b| / |b_prev|)^2), eta_max = 0.1 except
-// in a step that checks a stop (kCheckEta), never below the safeguard
+// in a step that checks a stop (a smaller cg_eta_max), never below the safeguard
 // eta_min; the first step uses eta = eta_max.
 __host__ __device__ inline double pcg_tol2(const Ctrl& C, double bb) {
   double tol2 = C.cg_tol2;

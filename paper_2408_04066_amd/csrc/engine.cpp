@@ -949,6 +949,13 @@ int Engine::finish_newton(int i) {
       MFS_TRY(set_pose(i, std::min(1.0, S.tau_done + S.delta)));
     }
   }
+  // The step that will likely be the last (this one times its contraction
+  // rate, at least 0.1, is within the tolerance) is solved to the check
+  // tolerance at once, so that a stop after it needs no extra check step.
+  if (!S.done && !o_.fixed_newton && final_pose && was_newton && o_.cg_adaptive && S.phase == 1) {
+    const double r = rho < 1.0 ? std::max(rho, 0.1) : 1.0;  // no rate yet: as if 1
+    if (S.step * r <= tol * S.ch->bbox_diag) S.check_next = true;
+  }
   if (!S.done && S.iters >= o_.max_newton) {
     S.done = true;
     S.status = MFS_W_NOT_CONVERGED;

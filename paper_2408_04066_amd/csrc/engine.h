@@ -19,6 +19,10 @@
 
 namespace mfs {
 
+// Largest PCG forcing term of a Newton step that checks a stop (see
+// Engine::finish_newton).
+constexpr double kCheckEta = 1e-2;
+
 // Host side of a wait for the GPU (a stop flag, or the event behind a chunk
 // of PCG launches): polls back to back for a short while, since a chunk
 // usually ends within it, then sleeps between polls so that the host thread
