@@ -242,7 +242,7 @@ struct SysDesc {
   int32_t n, m, nnzb, nh;
   int32_t ntv, ntt, nts, ptile;   // tiles per system: vertex, tet, slot; partial stride
   int32_t ticket;                 // PCG reductions by arrival ticket (ntv above the all-read limit)
-  int32_t pad0;
+  int32_t par0;                   // pipelined PCG: parity of the launch that runs this system's iteration 0
   double ks;                      // pin stiffness
   // resident (reordered) mesh data
   const int4* tets;        // m

@@ -63,9 +63,25 @@ int sync_event(mfs_context* ctx, hipEvent_t* out) {
   return MFS_OK;
 }
 
+int wait_stream(mfs_context* ctx) {
+  hipEvent_t e = nullptr;
+  MFS_TRY(sync_event(ctx, &e));
+  MFS_HIP(hipEventRecord(e, ctx->stream));
+  PollPacer pacer;
+  for (;;) {
+    const hipError_t r = hipEventQuery(e);
+    if (r == hipSuccess) break;
+    if (r != hipErrorNotReady) return set_error(MFS_E_HIP, "stream wait: %s", hipGetErrorString(r));
+    if (!pacer.pace())
+      return set_error(MFS_E_HIP, "stream wait: not done in %d s", PollPacer::kLimitSeconds);
+  }
+  ctx->sync_events.push_back(e);
+  return MFS_OK;
+}
+
 int read_cg(mfs_context* ctx, int count, bool resolve) {
   MFS_HIP(hipMemcpyAsync(ctx->h_cg.p, ctx->cg.p, count * sizeof(CgState), hipMemcpyDeviceToHost, ctx->stream));
-  MFS_HIP(hipStreamSynchronize(ctx->stream));
+  MFS_TRY(wait_stream(ctx));
   if (resolve) prof_resolve(ctx);
   return MFS_OK;
 }
@@ -73,7 +89,7 @@ int read_cg(mfs_context* ctx, int count, bool resolve) {
 int read_red(mfs_context* ctx, int count) {
   MFS_HIP(hipMemcpyAsync(ctx->h_red.p, ctx->red.p, count * P_COUNT * sizeof(double), hipMemcpyDeviceToHost,
                          ctx->stream));
-  MFS_HIP(hipStreamSynchronize(ctx->stream));
+  MFS_TRY(wait_stream(ctx));
   prof_resolve(ctx);
   return MFS_OK;
 }
@@ -511,6 +527,14 @@ int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* fai
     }
   };
   if (pipe) {
+    // iteration j runs with parity j & 1 here (a slot that last solved in
+    // the asynchronous form may carry another offset)
+    for (int i : act)
+      if (hd_[i].par0 != 0) {
+        hd_[i].par0 = 0;
+        desc_dirty_ = true;
+      }
+    MFS_TRY(upload_desc());
     ProfScope ps(ctx, MFS_K_OTHER);
     launch_pcg_start(ctx->stream, dsd, ts_.dv, ts_.nv, fp32, ctx->lpr, one);
   }
@@ -587,7 +611,7 @@ int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* fai
     return MFS_OK;
   };
   auto drain = [&]() -> int {
-    MFS_HIP(hipStreamSynchronize(ctx->stream));
+    MFS_TRY(wait_stream(ctx));
     for (auto& qe : queued) ctx->sync_events.push_back(qe.second);
     queued.clear();
     return MFS_OK;

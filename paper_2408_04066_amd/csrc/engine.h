@@ -24,24 +24,23 @@ namespace mfs {
 constexpr double kCheckEta = 1e-2;
 
 // Host side of a wait for the GPU (a stop flag, or the event behind a chunk
-// of PCG launches): polls back to back for a short while, since a chunk
-// usually ends within it, then sleeps between polls so that the host thread
-// does not keep the HIP runtime busy with queries; a wait that sees nothing
-// for kLimitSeconds is given up (the caller returns an error).
+// of PCG launches): polls back to back for the first kSpinMicros, since a
+// chunk usually ends within it and the GPU may have only a few tens of
+// microseconds of queued work left (a sleep wakes up late), then sleeps
+// between polls so that a long wait does not keep the HIP runtime busy with
+// queries; a wait that sees nothing for kLimitSeconds is given up (the
+// caller returns an error).
 struct PollPacer {
-  static constexpr int kSpins = 256;
+  static constexpr int kSpinMicros = 2000;
   static constexpr int kLimitSeconds = 120;
-  int spins = 0;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
-  void reset() {
-    spins = 0;
-    t0 = std::chrono::steady_clock::now();
-  }
+  void reset() { t0 = std::chrono::steady_clock::now(); }
   // false once the wait has lasted longer than the limit
   bool pace() {
-    if (++spins < kSpins) return true;
+    const auto waited = std::chrono::steady_clock::now() - t0;
+    if (waited < std::chrono::microseconds(kSpinMicros)) return true;
     std::this_thread::sleep_for(std::chrono::microseconds(20));
-    return std::chrono::steady_clock::now() - t0 < std::chrono::seconds(kLimitSeconds);
+    return waited < std::chrono::seconds(kLimitSeconds);
   }
 };
 
@@ -107,6 +106,10 @@ int upload_ctrl(mfs_context* ctx, int count);
 int ensure_stop_flags(mfs_context* ctx, int slots);
 // An event (no timing) from the context's pool.
 int sync_event(mfs_context* ctx, hipEvent_t* out);
+// Wait until the work queued on the context's stream is done, polling an
+// event with a PollPacer (a stream synchronisation can return well after
+// the work ends).
+int wait_stream(mfs_context* ctx);
 int read_cg(mfs_context* ctx, int count, bool resolve = true);
 int read_red(mfs_context* ctx, int count);
 // Tiles of the listed slots (indices into by_slot), uploaded in stream order
@@ -133,8 +136,7 @@ class Engine {
   int bind_workspace(int slot, char* base);
   // One Newton iteration for every occupied, unfinished slot.
   int step();
-  // Asynchronous batch form (two-kernel PCG): each slot runs its own Newton
-  // steps.  One call is one scheduling event: slots at the start of a Newton
+  // Asynchronous batch form: each slot runs its own Newton steps.  One call is one scheduling event: slots at the start of a Newton
   // step get their element pass, assembly and PCG start; PCG chunks run over
   // every slot then solving, in each precision, until enough of them stop;
   // stopped FP32 solves that stalled are queued for an FP64 re-solve, and the
@@ -142,8 +144,12 @@ class Engine {
   // finish).  A slot's arithmetic is the same as in step() and as alone; only
   // which slots share a launch changes.
   int advance();
-  // advance() applies: the context runs the two-kernel PCG with the
-  // asynchronous batch form enabled, and the engine's driver allows it.
+  // advance() applies: the context has the asynchronous batch form enabled,
+  // the engine's driver allows it, and the PCG form launches per iteration:
+  // the two-kernel form, or the pipelined form for a batch of more than one
+  // slot (one slot keeps the lockstep form, whose pipelined runs replay as
+  // graphs).  The persistent launch holds one set of systems for a whole
+  // solve, so it keeps the lockstep form.
   bool async_mode() const;
   // The serving lanes keep the lockstep form (see server.cpp).
   void allow_async(bool on) { async_ok_ = on; }
@@ -186,6 +192,9 @@ class Engine {
   int async_head(const std::vector<int>& ids, int prec, bool redo);
   int async_pcg();
   int async_enqueue(int prec, int run);
+  // precision prec's live set runs the pipelined PCG (else the two-kernel
+  // form; FP64 re-solves of stalled FP32 solves always do)
+  bool pipe_set(int prec) const { return ctx_->pipelined && (prec == 1 || !fp32_); }
   void async_attribute();
   int vertex_tiles(int prec, const std::vector<int>& ids);
   int set_pose(int slot, double tau);

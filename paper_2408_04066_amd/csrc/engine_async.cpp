@@ -1,4 +1,4 @@
-// Asynchronous batch form of the engine (two-kernel PCG).
+// Asynchronous batch form of the engine (two-kernel or pipelined PCG).
 //
 // In step() every slot of a batch runs the same Newton iteration: the batch
 // waits for the slowest slot's PCG solve before any slot takes its line
@@ -27,7 +27,11 @@
 namespace mfs {
 
 bool Engine::async_mode() const {
-  return async_ok_ && ctx_->batch_async && !ctx_->pipelined && !ctx_->persistent;
+  if (!async_ok_ || !ctx_->batch_async || ctx_->persistent) return false;
+  if (!ctx_->pipelined) return true;
+  int used = 0;
+  for (const SlotState& S : slot_) used += S.used ? 1 : 0;
+  return used > 1;
 }
 
 uint64_t Engine::progress_key() const {
@@ -90,6 +94,17 @@ int Engine::async_head(const std::vector<int>& ids, int prec, bool redo) {
     S.epoch = epoch;
     S.pcg_cap = (prec == 1) ? fp32_cap(S.ch) : o_.cg_max;
   }
+  // a pipelined solve's iteration j runs in the live set's launch
+  // launched_[prec] + j, whose parity argument is that launch's: the system's
+  // par0 maps it back to j's parity
+  const bool pipe = pipe_set(prec);
+  if (pipe)
+    for (int i : ids)
+      if (hd_[i].par0 != (int)(launched_[prec] & 1)) {
+        hd_[i].par0 = (int)(launched_[prec] & 1);
+        desc_dirty_ = true;
+      }
+  MFS_TRY(upload_desc());  // stream-ordered: in-flight launches read the old, equal, entries of other slots
   MFS_TRY(upload_ctrl(ctx, (int)slot_.size()));
   MFS_TRY(tiles_for(ids));
   const SysDesc* dsd = ctx->desc.as<SysDesc>();
@@ -103,10 +118,16 @@ int Engine::async_head(const std::vector<int>& ids, int prec, bool redo) {
   }
   {
     ProfScope ps(ctx, MFS_K_OTHER);
-    launch_cg_init(st, dsd, ts_.dv, ts_.nv, prec, redo ? 1 : 0);
+    // the FP32 pipelined solve keeps its vectors in FP64 (k_pcg_init)
+    if (pipe && prec == 1)
+      launch_pcg_init(st, dsd, ts_.dv, ts_.nv, 1);
+    else
+      launch_cg_init(st, dsd, ts_.dv, ts_.nv, prec, redo ? 1 : 0);
+    if (pipe) launch_pcg_start(st, dsd, ts_.dv, ts_.nv, prec, ctx->lpr, nullptr);
   }
   MFS_HIP(hipGetLastError());
   const double word = prec ? 4.0 : 8.0;
+  const double per_row = (pipe ? 48.0 : 6.0) * word;  // as in run_cg
   for (int i : ids) {
     SlotState& S = slot_[i];
     S.stage = prec ? kPcg32 : kPcg64;
@@ -116,7 +137,7 @@ int Engine::async_head(const std::vector<int>& ids, int prec, bool redo) {
       const mfs_character* c = S.ch;
       S.span = (int)spans_.size();
       spans_.push_back(SolveSpan{prec, launched_[prec], -1,
-                                 c->nnzb * (9.0 * word + 4.0) + (c->n + 1) * 4.0 + c->n * 6.0 * word});
+                                 c->nnzb * (9.0 * word + 4.0) + (c->n + 1) * 4.0 + c->n * per_row});
     }
     live_[prec].push_back(i);
   }
@@ -138,6 +159,7 @@ int Engine::async_enqueue(int prec, int run) {
   }
   const SysDesc* dsd = ctx->desc.as<SysDesc>();
   const SysDesc* one = live.size() == 1 ? &hd_[live[0]] : nullptr;
+  const bool pipe = pipe_set(prec);
   for (int j = 0; j < run; ++j) {
     {
       ProfScope ps(ctx, MFS_K_SPMV, 0.0, (int)timed_.size());
@@ -145,8 +167,13 @@ int Engine::async_enqueue(int prec, int run) {
         timed_.push_back(TimedLaunch{launched_[prec] + j, prec, gen_[prec]});
       else
         ps.tag = -1;
-      launch_cg_spmv(ctx->stream, dsd, lts_[prec].dv, lts_[prec].nv, prec, ctx->lpr, one);
+      if (pipe)
+        launch_pcg_iter(ctx->stream, dsd, lts_[prec].dv, lts_[prec].nv, prec, ctx->lpr, one,
+                        (int)((launched_[prec] + j) & 1));
+      else
+        launch_cg_spmv(ctx->stream, dsd, lts_[prec].dv, lts_[prec].nv, prec, ctx->lpr, one);
     }
+    if (pipe) continue;
     ProfScope ps(ctx, MFS_K_CG_UPDATE);
     launch_cg_update(ctx->stream, dsd, lts_[prec].dv, lts_[prec].nv, prec, one);
   }
@@ -243,7 +270,7 @@ int Engine::async_pcg() {
     queued_.erase(queued_.begin());
   }
   // drain, then read every slot's PCG state
-  MFS_HIP(hipStreamSynchronize(ctx->stream));
+  MFS_TRY(wait_stream(ctx));
   for (hipEvent_t e : queued_) ctx->sync_events.push_back(e);
   queued_.clear();
   MFS_TRY(read_cg(ctx, (int)slot_.size(), false));
@@ -279,7 +306,8 @@ int Engine::async_pcg() {
     MFS_TRY(tiles_for(out));
     {
       ProfScope ps(ctx, MFS_K_OTHER);
-      launch_cg_finish(ctx->stream, ctx->desc.as<SysDesc>(), ts_.dv, ts_.nv, p);
+      // (a pipelined iterate is FP64 in both precisions)
+      launch_cg_finish(ctx->stream, ctx->desc.as<SysDesc>(), ts_.dv, ts_.nv, pipe_set(p) ? 0 : p);
     }
     MFS_HIP(hipGetLastError());
     live_[p].swap(still);

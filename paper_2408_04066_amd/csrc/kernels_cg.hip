@@ -512,7 +512,10 @@ __global__ __launch_bounds__(64) void k_cg_update(const SysDesc* __restrict__ sd
 // lose the residual in FP32 rounding well before 1e-5 (its three-term
 // updates break down), so the FP32 path runs them in FP64.  The parity is a launch
 // argument: a captured run of an even number of iterations replays from any
-// even iteration.
+// even iteration.  A launch over systems whose solves began at different
+// launches (the asynchronous batch form) gives each system the parity of its
+// own iteration: the launch's parity xor the system's par0, the parity of the
+// launch that ran its iteration 0.
 
 // acc = (K v)_row over this lane's share of the row's blocks, then summed
 // over the LPR lanes of the row (every lane of the row gets the sum).  The
@@ -656,7 +659,7 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_start(const SysDesc* __restric
   }
 }
 
-// Iteration i (parity = i & 1) of the pipelined PCG.  Everything the launch
+// Iteration i (parity ^ par0 = i & 1) of the pipelined PCG.  Everything the launch
 // reads that no workgroup of it writes (the row's block range, the row's own
 // vector entries, the partial sums of the previous launch, the PCG state) is
 // loaded at its head, before the convergence flag is tested, so the loads
@@ -678,7 +681,7 @@ __global__ __launch_bounds__(64 * LPR) void k_pcg_iter(const SysDesc* __restrict
   const Tile t = vertex_tile<ONE>(tiles, ntiles, one);
   const SysDesc& S = ONE ? one : sd[t.sys];
   CgState* st = S.cg;
-  const int par = parity & 1;
+  const int par = (parity ^ S.par0) & 1;
   const int lane = threadIdx.x % LPR;
   const int row = t.begin + threadIdx.x / LPR;
   const bool valid = row < t.end;

@@ -275,6 +275,48 @@ def test_batch_equals_alone(ctx):
         ch.close()
 
 
+def test_pipelined_batch_equals_alone(ctx):
+    """With the pipelined PCG a batch runs the asynchronous form (direct
+    launches; each system's iteration parity offset by the launch its solve
+    began at) while a character solved alone runs the lockstep form (graph
+    replays from iteration 0): positions and statistics agree bitwise, in
+    FP32 + refinement, with a small FP32 cap (FP64 re-solves in the
+    two-kernel form beside pipelined FP32 solves), and in FP64."""
+    mfs = _mfs()
+    probs = [humanoid(100 + i, target_tets=t, n_bones=b, models=(NH, COROT))
+             for i, (t, b) in enumerate([(1500, 8), (3000, 12), (800, 10)])]
+    poses = [random_pose(p, 200 + i) for i, p in enumerate(probs)]
+    chars = [mfs.Character(ctx, p) for p in probs]
+    keys = ("status", "iterations", "mixed_iterations", "cg_iterations", "halvings", "fp64_resolves")
+    base = ctx.tuning()
+    cases = [("fp32", dict(precision=mfs.FP32_REFINED, cg_tol=1e-5, step_tol=1e-9)),
+             ("fp32 cap 30", dict(precision=mfs.FP32_REFINED, cg_tol=1e-5, step_tol=1e-9, fp32_cg_max=30)),
+             ("fp64", dict(precision=mfs.FP64, cg_tol=1e-8, step_tol=1e-9))]
+    try:
+        ctx.set_tuning(pcg_pipelined=1, pcg_persistent=0, batch_async=1, use_graphs=1, graph_iterations=8)
+        for name, opts in cases:
+            alone, worst = [], 0
+            for ch, pose in zip(chars, poses):
+                _say(f"pipelined {name}: solve alone n={ch.n}")
+                x, st, rc = ch.solve(*pose, **opts)
+                assert rc >= 0, (name, st)
+                worst = max(worst, rc)
+                alone.append((x, st))
+            _say(f"pipelined {name}: alone {[st for _, st in alone]}")
+            if name == "fp32 cap 30":
+                assert any(st["fp64_resolves"] > 0 for _, st in alone)
+            _say(f"pipelined {name}: solve batch of 3")
+            xs, sts, rc = mfs.solve_batch(ctx, chars, poses, **opts)
+            assert rc == worst
+            for (xa, sa), xb, sb in zip(alone, xs, sts):
+                assert np.array_equal(xa, xb), name
+                assert all(sa[k] == sb[k] for k in keys), (name, sa, sb)
+    finally:
+        ctx.set_tuning(**base)
+    for ch in chars:
+        ch.close()
+
+
 def test_graph_replay_and_lane_counts(ctx):
     """Replayed PCG graphs give bitwise the same frame as direct launches;
     other SpMV lane counts agree to the FP64 tolerance."""
