@@ -86,10 +86,27 @@ int read_cg(mfs_context* ctx, int count, bool resolve) {
   return MFS_OK;
 }
 
-int read_red(mfs_context* ctx, int count) {
+int read_red(mfs_context* ctx, int count, const std::function<int()>& fill) {
   MFS_HIP(hipMemcpyAsync(ctx->h_red.p, ctx->red.p, count * P_COUNT * sizeof(double), hipMemcpyDeviceToHost,
                          ctx->stream));
-  MFS_TRY(wait_stream(ctx));
+  if (fill) {
+    // wait for the copy only; the work `fill` queues behind it runs meanwhile
+    hipEvent_t e = nullptr;
+    MFS_TRY(sync_event(ctx, &e));
+    MFS_HIP(hipEventRecord(e, ctx->stream));
+    MFS_TRY(fill());
+    PollPacer pacer;
+    for (;;) {
+      const hipError_t r = hipEventQuery(e);
+      if (r == hipSuccess) break;
+      if (r != hipErrorNotReady) return set_error(MFS_E_HIP, "reduction read: %s", hipGetErrorString(r));
+      if (!pacer.pace())
+        return set_error(MFS_E_HIP, "reduction read: not done in %d s", PollPacer::kLimitSeconds);
+    }
+    ctx->sync_events.push_back(e);
+  } else {
+    MFS_TRY(wait_stream(ctx));
+  }
   prof_resolve(ctx);
   return MFS_OK;
 }
@@ -669,8 +686,10 @@ int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* fai
       if (cit < max_cap) MFS_TRY(enqueue(std::min(steady, max_cap - cit)));
     }
   }
-  MFS_TRY(drain());
+  // (the read waits for every queued chunk)
   MFS_TRY(read_cg(ctx, n, false));
+  for (auto& qe : queued) ctx->sync_events.push_back(qe.second);
+  queued.clear();
   attribute_bytes();
   prof_resolve(ctx);
   if (live.size() != act.size()) MFS_TRY(tiles_for(act));
@@ -720,7 +739,7 @@ int Engine::linesearch(const std::vector<int>& act) {
       launch_finalize(st, dsd, ctx->sys_ids.as<int32_t>(), (int)srch.size());
     }
     MFS_HIP(hipGetLastError());
-    MFS_TRY(read_red(ctx, n));
+    MFS_TRY(read_red(ctx, n, first_pass ? ls_fill_ : std::function<int()>()));
     std::vector<int> next;
     for (int i : srch) {
       SlotState& S = slot_[i];

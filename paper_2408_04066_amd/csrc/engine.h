@@ -12,6 +12,7 @@
 #pragma once
 
 #include <chrono>
+#include <functional>
 #include <thread>
 #include <vector>
 
@@ -111,7 +112,10 @@ int sync_event(mfs_context* ctx, hipEvent_t* out);
 // the work ends).
 int wait_stream(mfs_context* ctx);
 int read_cg(mfs_context* ctx, int count, bool resolve = true);
-int read_red(mfs_context* ctx, int count);
+// The per-system reductions to the host.  With `fill`, the host waits for
+// the copy only: fill() queues more work behind it first (work that neither
+// the copy nor the host's use of the reductions depends on).
+int read_red(mfs_context* ctx, int count, const std::function<int()>& fill = std::function<int()>());
 // Tiles of the listed slots (indices into by_slot), uploaded in stream order
 // to the context's tile buffer, plus the slot-id list of the finalize kernel
 // (a buffer that must grow is replaced only after the stream drains).
@@ -231,6 +235,9 @@ class Engine {
   std::vector<std::vector<int>> gens_;
   int gen_[2] = {-1, -1};
   std::vector<TimedLaunch> timed_;
+  // asynchronous form: PCG work for the slots still solving, queued behind
+  // the first line-search pass's reduction copy (see linesearch)
+  std::function<int()> ls_fill_;
 };
 
 }  // namespace mfs

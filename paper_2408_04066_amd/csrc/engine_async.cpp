@@ -269,11 +269,11 @@ int Engine::async_pcg() {
     ctx->sync_events.push_back(queued_.front());
     queued_.erase(queued_.begin());
   }
-  // drain, then read every slot's PCG state
-  MFS_TRY(wait_stream(ctx));
+  // drain, then read every slot's PCG state (the read waits for every
+  // queued chunk)
+  MFS_TRY(read_cg(ctx, (int)slot_.size(), false));
   for (hipEvent_t e : queued_) ctx->sync_events.push_back(e);
   queued_.clear();
-  MFS_TRY(read_cg(ctx, (int)slot_.size(), false));
   const CgState* hg = ctx->h_cg.as<CgState>();
   for (int p = 1; p >= 0; --p) {
     std::vector<int> still, out;
@@ -375,17 +375,23 @@ int Engine::advance() {
     if (slot_[i].used && !slot_[i].done && slot_[i].stage == kTail) tails.push_back(i);
   if (tails.empty()) return MFS_OK;
   // keep the GPU on the slots still solving while the host takes the line
-  // searches (their reads synchronise the stream behind this chunk)
+  // searches: a chunk queued behind the first pass's reduction copy runs
+  // while the host reads the reductions and decides the steps
   if (!live_[0].empty() || !live_[1].empty()) {
-    const int steady = std::max(1, std::min(ctx->cg_min_run, ctx->cg_max_run));
-    for (int p = 1; p >= 0; --p) {
-      int run = steady;
-      for (int i : live_[p])
-        run = std::min<int64_t>(run, slot_[i].pcg_base + slot_[i].pcg_cap - launched_[p]);
-      MFS_TRY(async_enqueue(p, std::max(run, 0)));
-    }
+    ls_fill_ = [this, ctx]() -> int {
+      const int steady = std::max(1, std::min(ctx->cg_min_run, ctx->cg_max_run));
+      for (int p = 1; p >= 0; --p) {
+        int run = steady;
+        for (int i : live_[p])
+          run = std::min<int64_t>(run, slot_[i].pcg_base + slot_[i].pcg_cap - launched_[p]);
+        MFS_TRY(async_enqueue(p, std::max(run, 0)));
+      }
+      return MFS_OK;
+    };
   }
-  MFS_TRY(linesearch(tails));
+  const int ls = linesearch(tails);
+  ls_fill_ = nullptr;
+  MFS_TRY(ls);
   MFS_TRY(apply_update(tails));
   for (int i : tails) {
     MFS_TRY(finish_newton(i));
