@@ -328,17 +328,15 @@ def frame_bench(args, mfs, torch):
     _progress("warmup done")
 
     # ---- timed region.  The library's profiler times every stride-th launch
-    # of each kernel family with a HIP event pair carried in the launch's own
-    # dispatches (on the library's stream).  Where every launch is direct (the
-    # asynchronous batch form) it samples the timed launches themselves;
-    # where PCG runs replay as HIP graphs (the lockstep form: a single
-    # character with the pipelined PCG, or the asynchronous form switched
-    # off) sampling needs direct launches, so it runs on the next frames of
-    # the same kind after the timed region and the timed frames keep their
-    # graphs ----
+    # of each kernel family with a HIP event pair recorded around it on the
+    # library's stream.  Where every launch is direct (the asynchronous batch
+    # form) it samples the timed launches themselves; where PCG runs replay
+    # as HIP graphs (the lockstep form: a single character, or the
+    # asynchronous form switched off) sampling needs direct launches, so it
+    # runs on the next frames of the same kind after the timed region and the
+    # timed frames keep their graphs ----
     def graphs_replayed(t, count):
-        asynchronous = (bool(t["batch_async"]) and not t["pcg_persistent"]
-                        and (not t["pcg_pipelined"] or count > 1))
+        asynchronous = bool(t["batch_async"]) and not t["pcg_persistent"] and count > 1
         return bool(t["use_graphs"]) and not asynchronous
     sample_timed = not any(graphs_replayed(c.tuning(), len(members[g])) for g, c in enumerate(ctxs))
     if sample_timed:

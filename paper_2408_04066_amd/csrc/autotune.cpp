@@ -209,10 +209,9 @@ extern "C" int mfs_autotune(mfs_context* ctx, int32_t count, mfs_character* cons
   for (int lpr : {2, 4, 8})
     for (int gi : {4, 8, 16}) {
       if (form == 2 && gi != 8) continue;
-      // the asynchronous batch form launches directly, so the graph length
-      // does not matter: the two-kernel form runs in it at any batch size,
-      // the pipelined form for batches
-      if (win.batch_async && (form == 0 || (form == 1 && count > 1)) && gi != 8) continue;
+      // the asynchronous batch form (batches) launches directly, so the
+      // graph length does not matter
+      if (win.batch_async && count > 1 && form < 2 && gi != 8) continue;
       // batches: the persistent launch holds one system's tiles only, and the
       // shortest graphs lose to longer ones at batch sizes
       if (count > 1 && (form == 2 || gi == 4)) continue;

@@ -149,11 +149,11 @@ class Engine {
   // which slots share a launch changes.
   int advance();
   // advance() applies: the context has the asynchronous batch form enabled,
-  // the engine's driver allows it, and the PCG form launches per iteration:
-  // the two-kernel form, or the pipelined form for a batch of more than one
-  // slot (one slot keeps the lockstep form, whose pipelined runs replay as
-  // graphs).  The persistent launch holds one set of systems for a whole
-  // solve, so it keeps the lockstep form.
+  // the engine's driver allows it, the engine holds more than one slot (a
+  // single system gains nothing from it, and the lockstep form replays its
+  // PCG runs as graphs), and the PCG form launches per iteration (the
+  // persistent launch holds one set of systems for a whole solve, so it
+  // keeps the lockstep form).
   bool async_mode() const;
   // The serving lanes keep the lockstep form (see server.cpp).
   void allow_async(bool on) { async_ok_ = on; }

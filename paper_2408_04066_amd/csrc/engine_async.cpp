@@ -28,7 +28,6 @@ namespace mfs {
 
 bool Engine::async_mode() const {
   if (!async_ok_ || !ctx_->batch_async || ctx_->persistent) return false;
-  if (!ctx_->pipelined) return true;
   int used = 0;
   for (const SlotState& S : slot_) used += S.used ? 1 : 0;
   return used > 1;
