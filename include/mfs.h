@@ -182,15 +182,18 @@ typedef struct mfs_tuning {
                                  iterates are the same bitwise.  Default 0: it pays off for
                                  small systems, where the launch per iteration dominates
                                  (the autotuner tries it) */
-  int32_t batch_async;        /* 1 (default): a batch (mfs_solve_batch, a server lane) whose
-                                 solves run the two-kernel PCG lets each character run its
-                                 own Newton steps: a character whose PCG solve has stopped
-                                 takes its line search, update and next element pass and
-                                 assembly while the others' solves go on, and every PCG
-                                 launch covers the characters solving at that moment; 0:
-                                 every character of the batch runs the same Newton
-                                 iteration, which waits for the slowest PCG solve.  Results
-                                 are the same bitwise either way */
+  int32_t batch_async;        /* 1 (default): a batch of two or more characters
+                                 (mfs_solve_batch) whose solves run the two-kernel or the
+                                 pipelined PCG (not the persistent launch) lets each
+                                 character run its own Newton steps: a character whose PCG
+                                 solve has stopped takes its line search, update and next
+                                 element pass and assembly while the others' solves go on,
+                                 and every PCG launch covers the characters solving at that
+                                 moment (launched directly, not as graphs); 0: every
+                                 character of the batch runs the same Newton iteration,
+                                 which waits for the slowest PCG solve.  A single character
+                                 and the server's lanes always run the second form.
+                                 Results are the same bitwise either way */
 } mfs_tuning;
 
 int mfs_context_get_tuning(const mfs_context* ctx, mfs_tuning* out);
@@ -325,9 +328,8 @@ int mfs_solve_batch(mfs_context* ctx, int32_t count, mfs_character* const* chars
  * given frames (as mfs_solve_batch with `opts`, but from the rest shape and
  * for exactly `newton_iterations` iterations, or, with newton_iterations 0,
  * as whole frames under `opts`' stop rule and Newton cap, into scratch
- * device memory) twice, timing the second.  The two-kernel form in the
- * asynchronous batch form is timed at one graph length only (it launches
- * directly).  A candidate's time is scaled by the default
+ * device memory) twice, timing the second.  A batch in the asynchronous
+ * form is timed at one graph length only (it launches directly).  A candidate's time is scaled by the default
  * schedule's total PCG iteration count over its own (summation order alone
  * moves the counts by a few percent), and the winner is the fastest
  * candidate by that time whose solves are as good as the default

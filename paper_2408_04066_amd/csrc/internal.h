@@ -121,7 +121,7 @@ struct mfs_context {
   size_t persist_lds = 0;
   int persist_capacity = 0;          // workgroups of the persistent PCG the device holds at once
   int allread_tiles = mfs::kAllReadTiles;  // largest system (vertex tiles) with all-read PCG sums
-  bool batch_async = true;           // batches with the two-kernel PCG: each system runs its own Newton steps
+  bool batch_async = true;           // batches (two-kernel or pipelined PCG): each system runs its own Newton steps
   std::vector<mfs::CgGraph> graphs;
   // batch scratch
   mfs::DevBuf desc, ctrl, red, cg, tiles, sys_ids, tmp;
