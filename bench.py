@@ -381,6 +381,7 @@ def frame_bench(args, mfs, torch):
                     "grad_norm": st["grad_norm"], "last_step_bbox": st["last_step"] / infos[j]["bbox_diag"]}
                    for i, j, st in per_frame if st["status"] != 0]
     conv_iters = [st["iterations"] for _, _, st in per_frame if st["status"] == 0]
+    conv_mixed = [st["mixed_iterations"] for _, _, st in per_frame if st["status"] == 0]
 
 
     # ---- FP32 + refinement against the FP64 form of the same solve, both
@@ -481,6 +482,8 @@ def frame_bench(args, mfs, torch):
         "newton_iters_per_frame": float(np.mean([st["iterations"] for _, _, st in per_frame])),
         "newton_iters_converged": {"mean": float(np.mean(conv_iters)) if conv_iters else None,
                                    "max": int(max(conv_iters)) if conv_iters else None},
+        "mixed_iters_converged": {"mean": float(np.mean(conv_mixed)) if conv_mixed else None,
+                                  "max": int(max(conv_mixed)) if conv_mixed else None},
         "cg_iters_per_frame": float(np.mean([st["cg_iterations"] for _, _, st in per_frame])),
         "cg_iters_per_newton": float(sum(st["cg_iterations"] for _, _, st in per_frame)
                                      / max(1, sum(st["iterations"] for _, _, st in per_frame))),
