@@ -238,3 +238,41 @@ def test_batched_characters_at_full_size(c4_batch):
             checked += 1
             break
     assert checked == len(groups)
+
+
+def test_served_positions_match_oracle_solutions(c4_batch, mfs):
+    """The serving path on the same size-stratified subset: the eight members
+    with oracle solutions, each next to another converging member, submitted
+    in one burst to a server with two size-class lanes (the serving
+    workload's layout, four slots per lane), solved from the rest shape with
+    the bench's options.  Each served result against the oracle's x* within
+    1e-7 of the bbox diagonal (Algorithm 1's output for every request), and
+    bitwise equal to the same member's result in the batched run: the lanes
+    take the context's PCG schedule, and a solve's arithmetic does not
+    depend on the solves beside it."""
+    probs, poses, ctx, chars, xs, sts, opts = c4_batch
+    gold = np.load(GOLDEN_C4, allow_pickle=False)
+    members = [int(k) for k in gold["members"]]
+    others = [k for k in range(len(probs)) if k not in members and k not in KNOWN_UNCONVERGED_C4][:len(members)]
+    order = [k for pair in zip(members, others) for k in pair]
+    sizes = sorted(len(probs[k]["T"]) for k in order)
+    bound = sizes[len(sizes) // 2]
+    _say(f"  serving {len(order)} requests, lanes split at {bound} tets")
+    srv = mfs.Server(ctx, slots=4, lane_max_tets=(bound,), **opts)
+    try:
+        tickets = [(k, srv.submit(chars[k], *poses[k])) for k in order]
+        res = {k: srv.wait(t) for k, t in tickets}
+        info = srv.info()
+    finally:
+        srv.close()
+    _say(f"  server: {info}")
+    assert info["completed"] == len(order)
+    for k in members:
+        x, st, tm, rc = res[k]
+        idx = gold[f"idx_{k}"]
+        e = _err(x[idx], gold[f"x_{k}"], probs[k]["bbox_diag"])
+        d = _err(x, xs[k], probs[k]["bbox_diag"])
+        _say(f"  member {k}: served {st}; |x_served - x*| / bbox = {e:.3e}, |x_served - x_batch| / bbox = {d:.3e}")
+        assert rc == 0 and st["status"] == 0
+        assert e <= 1e-7
+        assert np.array_equal(x, xs[k])
