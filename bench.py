@@ -171,6 +171,18 @@ def host_cpu():
 TUNE_NEWTON = 12
 SERVE_STALL_S = 120.0  # a serving run that completes no request for this long is reported as stalled
 CPU_BASELINE_MAX_TETS = 200_000  # largest single character whose oracle frame is a bounded sample
+# Newton iterations of the oracle's sample: about ten seconds per run on the
+# GPU host's cores (the oracle does about 4e4 tet Newton iterations per
+# second there): the quartile members of a batch (about 94k tets together),
+# or one character of up to 50k tets
+CPU_BASELINE_ITERS_BATCH = 5
+CPU_BASELINE_ITERS_ONE = 8
+
+
+def ordinal(k):
+    """1st, 2nd, 3rd, 4th, ..., 32nd."""
+    suffix = "th" if 10 <= k % 100 <= 20 else {1: "st", 2: "nd", 3: "rd"}.get(k % 10, "th")
+    return f"{k}{suffix}"
 
 
 def cpu_baseline(sample, iterations, what):
@@ -521,8 +533,8 @@ def frame_bench(args, mfs, torch):
         "roofline": {
             "bound": "hbm",
             "kernel": kernel,
-            "sampled_over": (f"every {args.profile_stride}th launch of the timed steps" if sample_timed else
-                             f"every {args.profile_stride}th launch of {args.roofline_steps} frames after the timed steps, "
+            "sampled_over": (f"every {ordinal(args.profile_stride)} launch of the timed steps" if sample_timed else
+                             f"every {ordinal(args.profile_stride)} launch of {args.roofline_steps} frames after the timed steps, "
                              f"launched directly (the timed steps replay their PCG runs as graphs)"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
@@ -551,10 +563,10 @@ def frame_bench(args, mfs, torch):
             sample = [(probs[k], steps[args.warmup][k]) for k in pick]
             what = (f"the frames of the members at the three quartiles of size ({', '.join(str(sizes[k]) for k in pick)} "
                     f"tets) of the first timed step")
-            result["cpu_baseline"] = cpu_baseline(sample, 1, what)
+            result["cpu_baseline"] = cpu_baseline(sample, CPU_BASELINE_ITERS_BATCH, what)
         elif sizes[0] <= CPU_BASELINE_MAX_TETS:
             sample = [(probs[0], steps[args.warmup][0])]
-            result["cpu_baseline"] = cpu_baseline(sample, 2, f"one frame of the {sizes[0]}-tet character")
+            result["cpu_baseline"] = cpu_baseline(sample, CPU_BASELINE_ITERS_ONE, f"one frame of the {sizes[0]}-tet character")
         else:  # the oracle's sparse LU of one Newton step alone runs for minutes here
             result["cpu_baseline"] = None
             result["cpu_baseline_skipped"] = (f"the {sizes[0]}-tet character is above {CPU_BASELINE_MAX_TETS} tets, "
