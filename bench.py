@@ -171,10 +171,10 @@ def host_cpu():
 TUNE_NEWTON = 12
 SERVE_STALL_S = 120.0  # a serving run that completes no request for this long is reported as stalled
 CPU_BASELINE_MAX_TETS = 200_000  # largest single character whose oracle frame is a bounded sample
-# Newton iterations of the oracle's sample: about ten seconds per run on the
-# GPU host's cores (the oracle does about 4e4 tet Newton iterations per
-# second there): the quartile members of a batch (about 94k tets together),
-# or one character of up to 50k tets
+# Newton iterations of the oracle's sample: about ten seconds per run on a
+# 16-core host (the oracle does about 4e4 tet Newton iterations per second
+# there): the quartile members of a batch (about 94k tets together), or one
+# character of up to 50k tets
 CPU_BASELINE_ITERS_BATCH = 5
 CPU_BASELINE_ITERS_ONE = 8
 

@@ -130,7 +130,7 @@ def c4_batch(mfs):
     with the bench's options: (probs, poses, ctx, chars, xs, stats, opts)."""
     import bench
     # the pool does not depend on the worker count; this process already
-    # holds the GPU, so its forked builders stay well inside the box's limit
+    # holds the GPU, so few forked builders keep the count of processes low
     bench._workers = lambda: 8
     probs, pose_of, wname, opts = bench.make_workload("c4")
     poses = pose_of(0)
