@@ -86,6 +86,18 @@ int read_cg(mfs_context* ctx, int count, bool resolve) {
   return MFS_OK;
 }
 
+int wait_event(mfs_context* ctx, hipEvent_t e) {
+  PollPacer pacer;
+  for (;;) {
+    const hipError_t r = hipEventQuery(e);
+    if (r == hipSuccess) break;
+    if (r != hipErrorNotReady) return set_error(MFS_E_HIP, "event wait: %s", hipGetErrorString(r));
+    if (!pacer.pace()) return set_error(MFS_E_HIP, "event wait: not done in %d s", PollPacer::kLimitSeconds);
+  }
+  ctx->sync_events.push_back(e);
+  return MFS_OK;
+}
+
 int read_red(mfs_context* ctx, int count, const std::function<int()>& fill) {
   MFS_HIP(hipMemcpyAsync(ctx->h_red.p, ctx->red.p, count * P_COUNT * sizeof(double), hipMemcpyDeviceToHost,
                          ctx->stream));
@@ -95,15 +107,7 @@ int read_red(mfs_context* ctx, int count, const std::function<int()>& fill) {
     MFS_TRY(sync_event(ctx, &e));
     MFS_HIP(hipEventRecord(e, ctx->stream));
     MFS_TRY(fill());
-    PollPacer pacer;
-    for (;;) {
-      const hipError_t r = hipEventQuery(e);
-      if (r == hipSuccess) break;
-      if (r != hipErrorNotReady) return set_error(MFS_E_HIP, "reduction read: %s", hipGetErrorString(r));
-      if (!pacer.pace())
-        return set_error(MFS_E_HIP, "reduction read: not done in %d s", PollPacer::kLimitSeconds);
-    }
-    ctx->sync_events.push_back(e);
+    MFS_TRY(wait_event(ctx, e));
   } else {
     MFS_TRY(wait_stream(ctx));
   }
@@ -493,7 +497,8 @@ int Engine::fp32_cap(const mfs_character* ch) const {
   return std::min(o_.cg_max, std::max(8000, (int)(100.0 * std::cbrt((double)ch->n))));
 }
 
-int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* failed) {
+int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* failed,
+                   const std::function<int()>& before_wait) {
   mfs_context* ctx = ctx_;
   const SysDesc* dsd = ctx->desc.as<SysDesc>();
   const int n = (int)slot_.size();
@@ -686,13 +691,26 @@ int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* fai
       if (cit < max_cap) MFS_TRY(enqueue(std::min(steady, max_cap - cit)));
     }
   }
-  // (the read waits for every queued chunk)
-  MFS_TRY(read_cg(ctx, n, false));
+  // The PCG state to the host (behind every queued chunk), the iterates into
+  // dx (FP64; a pipelined iterate is FP64 already), and the caller's next
+  // work, all queued before the host waits for the state: the GPU goes on
+  // while the host reads it.
+  MFS_HIP(hipMemcpyAsync(ctx->h_cg.p, ctx->cg.p, n * sizeof(CgState), hipMemcpyDeviceToHost, ctx->stream));
+  hipEvent_t state_read = nullptr;
+  MFS_TRY(sync_event(ctx, &state_read));
+  MFS_HIP(hipEventRecord(state_read, ctx->stream));
+  if (live.size() != act.size()) MFS_TRY(tiles_for(act));
+  {
+    ProfScope ps(ctx, MFS_K_OTHER);
+    launch_cg_finish(ctx->stream, dsd, ts_.dv, ts_.nv, pipe ? 0 : fp32);
+  }
+  MFS_HIP(hipGetLastError());
+  if (before_wait) MFS_TRY(before_wait());
+  MFS_TRY(wait_event(ctx, state_read));
   for (auto& qe : queued) ctx->sync_events.push_back(qe.second);
   queued.clear();
   attribute_bytes();
   prof_resolve(ctx);
-  if (live.size() != act.size()) MFS_TRY(tiles_for(act));
   for (int i : act) {
     const bool ok = hg[i].done == 1;
     const int ran = hg[i].done ? hg[i].iters : (stopped_at[i] >= 0 ? stopped_at[i] : cit);
@@ -704,8 +722,40 @@ int Engine::run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* fai
     else
       slot_[i].cg_fail++;
   }
-  ProfScope ps(ctx, MFS_K_OTHER);
-  launch_cg_finish(ctx->stream, dsd, ts_.dv, ts_.nv, pipe ? 0 : fp32);  // pipelined iterate is FP64
+  return MFS_OK;
+}
+
+// first pass: Newton slots evaluate E at {0, 1, 1/2, 1/4, 1/8}; mixed slots
+// get the halving count their worst tet needs
+void Engine::ls_setup(const std::vector<int>& act) {
+  Ctrl* hc = ctx_->h_ctrl.data();
+  for (int i : act) {
+    slot_[i].alpha = 0.0;
+    hc[i].phase = slot_[i].phase;
+    hc[i].trials[0] = 0.0;
+    for (int j = 1; j < kNumTrials; ++j) hc[i].trials[j] = std::ldexp(1.0, -(j - 1));
+  }
+}
+
+int Engine::ls_queue(const std::vector<int>& act) {
+  mfs_context* ctx = ctx_;
+  hipStream_t st = ctx->stream;
+  const int n = (int)slot_.size();
+  ls_setup(act);
+  MFS_TRY(tiles_for(act));
+  MFS_TRY(upload_ctrl(ctx, n));
+  {
+    ProfScope ps(ctx, MFS_K_LINESEARCH);
+    launch_linesearch(st, ctx->desc.as<SysDesc>(), ctx->ctrl.as<Ctrl>(), ts_.dt, ts_.nt, ts_.dv, ts_.nv);
+  }
+  {
+    ProfScope ps(ctx, MFS_K_OTHER);
+    launch_finalize(st, ctx->desc.as<SysDesc>(), ctx->sys_ids.as<int32_t>(), (int)act.size());
+  }
+  MFS_HIP(hipGetLastError());
+  MFS_HIP(hipMemcpyAsync(ctx->h_red.p, ctx->red.p, n * P_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
+  MFS_TRY(sync_event(ctx, &ls_event_));
+  MFS_HIP(hipEventRecord(ls_event_, st));
   return MFS_OK;
 }
 
@@ -717,29 +767,30 @@ int Engine::linesearch(const std::vector<int>& act) {
   Ctrl* hc = ctx->h_ctrl.data();
   const double* hr = ctx->h_red.as<double>();
   const int n = (int)slot_.size();
-  // first pass: Newton slots evaluate E at {0, 1, 1/2, 1/4, 1/8}; mixed
-  // slots get the halving count their worst tet needs
-  for (int i : act) {
-    slot_[i].alpha = 0.0;
-    hc[i].phase = slot_[i].phase;
-    hc[i].trials[0] = 0.0;
-    for (int j = 1; j < kNumTrials; ++j) hc[i].trials[j] = std::ldexp(1.0, -(j - 1));
-  }
+  const bool queued = ls_event_ != nullptr;  // the first pass is on its way (ls_queue)
+  if (!queued) ls_setup(act);
   std::vector<int> srch = act;
   bool first_pass = true;
   while (!srch.empty()) {
-    MFS_TRY(tiles_for(srch));
-    MFS_TRY(upload_ctrl(ctx, n));
-    {
-      ProfScope ps(ctx, MFS_K_LINESEARCH);
-      launch_linesearch(st, dsd, dctrl, ts_.dt, ts_.nt, ts_.dv, ts_.nv);
+    if (first_pass && queued) {
+      const hipEvent_t e = ls_event_;
+      ls_event_ = nullptr;
+      MFS_TRY(wait_event(ctx, e));
+      prof_resolve(ctx);
+    } else {
+      MFS_TRY(tiles_for(srch));
+      MFS_TRY(upload_ctrl(ctx, n));
+      {
+        ProfScope ps(ctx, MFS_K_LINESEARCH);
+        launch_linesearch(st, dsd, dctrl, ts_.dt, ts_.nt, ts_.dv, ts_.nv);
+      }
+      {
+        ProfScope ps(ctx, MFS_K_OTHER);
+        launch_finalize(st, dsd, ctx->sys_ids.as<int32_t>(), (int)srch.size());
+      }
+      MFS_HIP(hipGetLastError());
+      MFS_TRY(read_red(ctx, n, first_pass ? ls_fill_ : std::function<int()>()));
     }
-    {
-      ProfScope ps(ctx, MFS_K_OTHER);
-      launch_finalize(st, dsd, ctx->sys_ids.as<int32_t>(), (int)srch.size());
-    }
-    MFS_HIP(hipGetLastError());
-    MFS_TRY(read_red(ctx, n, first_pass ? ls_fill_ : std::function<int()>()));
     std::vector<int> next;
     for (int i : srch) {
       SlotState& S = slot_[i];
@@ -870,7 +921,16 @@ int Engine::step() {
   }
   MFS_HIP(hipGetLastError());
   std::vector<int> redo;
-  MFS_TRY(run_cg(act, fp32_, fp32_ ? &redo : nullptr));
+  // the first line-search pass is queued behind the PCG run, so the GPU
+  // does not wait for the host to read the PCG state; it is dropped when
+  // some Newton system needs its FP64 re-solve
+  MFS_TRY(run_cg(act, fp32_, fp32_ ? &redo : nullptr, [&]() { return ls_queue(act); }));
+  if (!redo.empty() && ls_event_) {
+    const hipEvent_t e = ls_event_;
+    ls_event_ = nullptr;
+    MFS_TRY(wait_event(ctx, e));
+    prof_resolve(ctx);
+  }
   if (!redo.empty()) {
     // FP32 could not solve these Newton systems (ill-conditioned beyond
     // single precision): element records, assembly and PCG again in FP64,

@@ -111,6 +111,9 @@ int sync_event(mfs_context* ctx, hipEvent_t* out);
 // event with a PollPacer (a stream synchronisation can return well after
 // the work ends).
 int wait_stream(mfs_context* ctx);
+// Wait for an event recorded on the context's stream (polled with a
+// PollPacer), then return it to the context's pool.
+int wait_event(mfs_context* ctx, hipEvent_t e);
 int read_cg(mfs_context* ctx, int count, bool resolve = true);
 // The per-system reductions to the host.  With `fill`, the host waits for
 // the copy only: fill() queues more work behind it first (work that neither
@@ -207,9 +210,19 @@ class Engine {
   // PCG for the listed slots in the given precision; with `failed`, slots
   // whose solve stops unconverged (cap or breakdown) are listed there instead
   // of counted as failures (the FP32 pass, re-solved in FP64).
-  int run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* failed);
+  // `before_wait`, when given, queues more work behind the run's last
+  // launches (after the iterates go to dx) before the host waits for the
+  // PCG state; the persistent launch does not call it.
+  int run_cg(const std::vector<int>& act, bool fp32, std::vector<int>* failed,
+             const std::function<int()>& before_wait = std::function<int()>());
   int fp32_cap(const mfs_character* ch) const;
+  // The line search of the listed slots; its first pass may have been
+  // queued already by ls_queue (then ls_event_ is set).
   int linesearch(const std::vector<int>& act);
+  // Queue the first line-search pass of the listed slots (launches and the
+  // copy of its reductions, ls_event_ recorded after it) without waiting.
+  int ls_queue(const std::vector<int>& act);
+  void ls_setup(const std::vector<int>& act);
 
   mfs_context* ctx_;
   mfs_solve_opts o_{};
@@ -238,6 +251,8 @@ class Engine {
   // asynchronous form: PCG work for the slots still solving, queued behind
   // the first line-search pass's reduction copy (see linesearch)
   std::function<int()> ls_fill_;
+  // lockstep form: event behind a queued first line-search pass, or null
+  hipEvent_t ls_event_ = nullptr;
 };
 
 }  // namespace mfs
