@@ -95,3 +95,39 @@ def test_large_animation_workload():
         L0, L1 = local(pose_of(f)[0][0]), local(pose_of(f + 1)[0][0])
         steps = [angle(a, b) for a, b in zip(L0, L1)]
         assert 0.0 < max(steps) <= bound
+
+
+def test_roofline_byte_count_and_traffic_summaries():
+    """The algorithmic bytes of one SpMV-family launch follow the block-sparse
+    count (every block's nine values and column, the row pointers, one input
+    and one output vector; the pipelined kernel adds twelve vector passes and
+    the preconditioner rows): the C1 beam's 425 vertices and 4,921 blocks
+    give 208,744 bytes in FP32.  A committed counter summary is read back
+    only while the kernel sources hash to the value it records, and then its
+    counted and algorithmic bytes are the ones its table states."""
+    sys.path.insert(0, ROOT)
+    import bench
+    info = {"n_vertices": 425, "n_blocks": 4921}
+    assert bench.spmv_algorithmic_bytes(info, 4, False) == 4921 * 40 + 4 * 426 + 24 * 425 == 208744
+    assert bench.spmv_algorithmic_bytes(info, 8, True) == 4921 * 76 + 4 * 426 + 48 * 425 + 336 * 425
+    import glob
+    for path in glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md")):
+        text = open(path).read()
+        fields = dict(line[2:].split(": ", 1) for line in text.splitlines() if line.startswith("- ") and ": " in line)
+        fields = {k.strip("`"): v.strip().strip("`") for k, v in fields.items()}
+        got = bench.counted_traffic(fields["workload"], fields["kernel"])
+        if fields["kernel_sources_sha256"] != bench.kernel_source_hash():
+            assert got is None
+            continue
+        assert got["counted_bytes_per_dispatch"] == float(fields["traffic_bytes_per_launch"])
+        assert got["algorithmic_bytes_per_dispatch"] == float(fields["algorithmic_bytes_per_launch"])
+        ratio = [line for line in text.splitlines() if line.startswith("| traffic / algorithmic |")][0]
+        stated = float(ratio.split("|")[2])
+        assert abs(got["counted_bytes_per_dispatch"] / got["algorithmic_bytes_per_dispatch"] - stated) < 1e-3
+
+
+def test_ordinals():
+    sys.path.insert(0, ROOT)
+    import bench
+    assert [bench.ordinal(k) for k in (1, 2, 3, 4, 11, 12, 13, 21, 22, 32, 111, 112)] == \
+        ["1st", "2nd", "3rd", "4th", "11th", "12th", "13th", "21st", "22nd", "32nd", "111th", "112th"]
