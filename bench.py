@@ -761,10 +761,10 @@ def main():
     ap.add_argument("--queue", type=int, default=512, help="c5: queued requests before rejection")
     ap.add_argument("--size-classes", type=int, default=None,
                     help="c4, c5: batches / servers by tet-count class, each on its own context and stream "
-                         "(default: 2 for c5, 1 otherwise)")
+                         "(default: 3 for c5, 1 otherwise)")
     args = ap.parse_args()
     if args.size_classes is None:
-        args.size_classes = 2 if args.workload == "c5" else 1
+        args.size_classes = 3 if args.workload == "c5" else 1
     if args.gpus != 1:
         print("bench.py measures one GPU: each frame solve runs on a single device and "
               "multi-GPU sharding is not implemented", file=sys.stderr)
